@@ -1,0 +1,200 @@
+"""FP64 CPU oracle for the visibility / chi-square path of GALARIO
+(Tazzari, Beaujean & Testi 2018, arXiv:1709.06999).
+
+TEST INFRASTRUCTURE ONLY.  The oracle is the independent checker of the HIP
+library: it shares no code with it, and only ``tests/``, the smoke entry and the
+CPU-baseline leg of the benchmark may import it.  The product path never calls
+it.  The arithmetic lives in ``oracle.c`` (plain C + OpenMP, FP64, direct DFT);
+this module only marshals numpy arrays.
+
+Sign convention.  The paper's body text (Sec. 3.1, Eq. complex.visibility.obs.xy;
+Sec. 3.3 translation) writes V = FT with exp(-2 pi i (u l + v m)) and a phase
+exp(-2 pi i (u dRA + v dDec)); its Appendix D reference functions, which fix
+the pixel orientation (East left, North up) jointly with the transform, compute
+V(u, v) = sum_pixels I exp(+2 pi i (u x + v y)) with the offset phase
+exp(+i theta), theta = 2 pi (u dRA + v dDec).  The two differ by complex
+conjugation.  The oracle (and the library) follow Appendix D.
+
+Functions and the passages they follow:
+  sweep          Sec. 2.2 (sampleProfile, inc), Sec. 4 (Create image), App. D
+  grid           Sec. 4 (shift -> real-to-complex FFT -> shift) as a direct DFT
+  grid_cell      one node of ``grid`` by the non-separable double sum
+  sample_grid    Sec. 3.3 (rotation by PA, translation), Sec. 3.4 (bilinear), App. D
+  sample_direct  as sample_grid with every node from ``grid_cell``
+  chi2           Sec. 3.1, Eq. def.chi.square
+  grad_image / grad_profile   transpose of the above (not in the paper)
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+import subprocess
+
+import numpy as np
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+_SRC = os.path.join(_HERE, "oracle.c")
+_SO = os.path.join(_HERE, "liboracle.so")
+_lib = None
+
+_D = ctypes.POINTER(ctypes.c_double)
+_I64 = ctypes.c_int64
+
+
+def build() -> str:
+    """Compile oracle.c with gcc (FP64, OpenMP, no fast-math)."""
+    tmp = _SO + ".tmp"
+    cmd = ["gcc", "-O2", "-fopenmp", "-fno-fast-math", "-ffp-contract=off",
+           "-shared", "-fPIC", _SRC, "-o", tmp, "-lm"]
+    subprocess.check_call(cmd)
+    os.replace(tmp, _SO)
+    return _SO
+
+
+def _load():
+    global _lib
+    if _lib is not None:
+        return _lib
+    if not os.path.exists(_SO):
+        build()
+    lib = ctypes.CDLL(_SO)
+    lib.orc_num_threads.restype = ctypes.c_int
+    lib.orc_sweep.argtypes = [_D, _I64, ctypes.c_double, ctypes.c_double, _I64,
+                              ctypes.c_double, ctypes.c_double, _D]
+    lib.orc_sweep.restype = ctypes.c_int
+    lib.orc_grid.argtypes = [_D, _I64, _D]
+    lib.orc_grid.restype = ctypes.c_int
+    lib.orc_grid_cell.argtypes = [_D, _I64, _I64, _I64, _D]
+    lib.orc_grid_cell.restype = None
+    for name in ("orc_sample", "orc_sample_direct"):
+        f = getattr(lib, name)
+        f.argtypes = [_D, _I64, ctypes.c_double, _D, _D, _I64, ctypes.c_double,
+                      ctypes.c_double, ctypes.c_double, ctypes.c_double, _D]
+        f.restype = _I64
+    lib.orc_chi2.argtypes = [_D, _D, _D, _D, _I64]
+    lib.orc_chi2.restype = ctypes.c_double
+    lib.orc_grad_image.argtypes = [_D, _I64, ctypes.c_double, _D, _D, _D, _D, _D,
+                                   _I64, ctypes.c_double, ctypes.c_double,
+                                   ctypes.c_double, ctypes.c_double, _D]
+    lib.orc_grad_image.restype = _I64
+    lib.orc_grad_profile.argtypes = [_D, _I64, ctypes.c_double, ctypes.c_double,
+                                     _I64, ctypes.c_double, ctypes.c_double, _D]
+    lib.orc_grad_profile.restype = ctypes.c_int
+    _lib = lib
+    return lib
+
+
+def _f64(a) -> np.ndarray:
+    return np.ascontiguousarray(np.asarray(a, dtype=np.float64))
+
+
+def _p(a: np.ndarray):
+    return a.ctypes.data_as(_D)
+
+
+def num_threads() -> int:
+    """OpenMP threads the oracle uses (OMP_NUM_THREADS or all cores)."""
+    return int(_load().orc_num_threads())
+
+
+def sweep(I, Rmin, dR, N, dxy, inc=0.0) -> np.ndarray:
+    """Image [N, N] in Jy/pixel from the radial profile I [Jy/sr]."""
+    I = _f64(I)
+    img = np.empty((int(N), int(N)), dtype=np.float64)
+    rc = _load().orc_sweep(_p(I), I.size, float(Rmin), float(dR), int(N), float(dxy),
+                           float(inc), _p(img))
+    if rc != 0:
+        raise ValueError(f"orc_sweep: error {rc}")
+    return img
+
+
+def grid(img) -> np.ndarray:
+    """Half spectrum G [N, N/2+1] (complex128), rows p unshifted (frequency p - N [p >= N/2])."""
+    img = _f64(img)
+    N = img.shape[0]
+    assert img.shape == (N, N)
+    G = np.empty((N, N // 2 + 1, 2), dtype=np.float64)
+    rc = _load().orc_grid(_p(img), N, _p(G))
+    if rc != 0:
+        raise ValueError(f"orc_grid: error {rc}")
+    return G[..., 0] + 1j * G[..., 1]
+
+
+def grid_cell(img, p, q) -> complex:
+    img = _f64(img)
+    out = np.empty(2, dtype=np.float64)
+    _load().orc_grid_cell(_p(img), img.shape[0], int(p), int(q), _p(out))
+    return complex(out[0], out[1])
+
+
+def sample_grid(G, N, dxy, u, v, PA=0.0, dRA=0.0, dDec=0.0, inc=0.0) -> np.ndarray:
+    """Sample a half spectrum from ``grid`` at the uv points (NaN where off grid)."""
+    G = np.ascontiguousarray(G, dtype=np.complex128)
+    Gi = np.ascontiguousarray(np.stack([G.real, G.imag], axis=-1))
+    u, v = _f64(u), _f64(v)
+    out = np.empty((u.size, 2), dtype=np.float64)
+    _load().orc_sample(_p(Gi), int(N), float(dxy), _p(u), _p(v), u.size, float(PA),
+                       float(dRA), float(dDec), float(inc), _p(out))
+    return out[:, 0] + 1j * out[:, 1]
+
+
+def sample_direct(img, dxy, u, v, PA=0.0, dRA=0.0, dDec=0.0, inc=0.0) -> np.ndarray:
+    """Like sampleImage, each node by the non-separable double sum (few points, any N)."""
+    img = _f64(img)
+    u, v = _f64(u), _f64(v)
+    out = np.empty((u.size, 2), dtype=np.float64)
+    _load().orc_sample_direct(_p(img), img.shape[0], float(dxy), _p(u), _p(v), u.size,
+                              float(PA), float(dRA), float(dDec), float(inc), _p(out))
+    return out[:, 0] + 1j * out[:, 1]
+
+
+def sampleImage(image, dxy, u, v, PA=0.0, dRA=0.0, dDec=0.0, inc=0.0) -> np.ndarray:
+    image = _f64(image)
+    return sample_grid(grid(image), image.shape[0], dxy, u, v, PA, dRA, dDec, inc)
+
+
+def sampleProfile(I, Rmin, dR, Nxy, dxy, u, v, inc=0.0, PA=0.0, dRA=0.0, dDec=0.0) -> np.ndarray:
+    img = sweep(I, Rmin, dR, Nxy, dxy, inc)
+    return sample_grid(grid(img), Nxy, dxy, u, v, PA, dRA, dDec, 0.0)
+
+
+def chi2(V, re, im, w) -> float:
+    V = np.ascontiguousarray(V, dtype=np.complex128)
+    Vi = np.ascontiguousarray(np.stack([V.real, V.imag], axis=-1))
+    re, im, w = _f64(re), _f64(im), _f64(w)
+    return float(_load().orc_chi2(_p(Vi), _p(re), _p(im), _p(w), re.size))
+
+
+def chi2Image(image, dxy, u, v, re, im, w, PA=0.0, dRA=0.0, dDec=0.0, inc=0.0) -> float:
+    return chi2(sampleImage(image, dxy, u, v, PA, dRA, dDec, inc), re, im, w)
+
+
+def chi2Profile(I, Rmin, dR, Nxy, dxy, u, v, re, im, w, inc=0.0, PA=0.0, dRA=0.0,
+                dDec=0.0) -> float:
+    return chi2(sampleProfile(I, Rmin, dR, Nxy, dxy, u, v, inc, PA, dRA, dDec), re, im, w)
+
+
+def grad_image(image, dxy, u, v, re, im, w, PA=0.0, dRA=0.0, dDec=0.0, inc=0.0):
+    """(chi2, d chi2 / d image) -- the transpose of the sampling map."""
+    image = _f64(image)
+    N = image.shape[0]
+    V = sampleImage(image, dxy, u, v, PA, dRA, dDec, inc)
+    Vi = np.ascontiguousarray(np.stack([V.real, V.imag], axis=-1))
+    u, v, re, im, w = map(_f64, (u, v, re, im, w))
+    g = np.empty((N, N), dtype=np.float64)
+    _load().orc_grad_image(_p(Vi), N, float(dxy), _p(u), _p(v), _p(re), _p(im), _p(w),
+                           u.size, float(PA), float(dRA), float(dDec), float(inc), _p(g))
+    return chi2(V, re, im, w), g
+
+
+def grad_profile(I, Rmin, dR, Nxy, dxy, u, v, re, im, w, inc=0.0, PA=0.0, dRA=0.0, dDec=0.0):
+    """(chi2, d chi2 / d I) through the sweep."""
+    I = _f64(I)
+    img = sweep(I, Rmin, dR, Nxy, dxy, inc)
+    c2, gimg = grad_image(img, dxy, u, v, re, im, w, PA, dRA, dDec, 0.0)
+    gI = np.empty(I.size, dtype=np.float64)
+    rc = _load().orc_grad_profile(_p(np.ascontiguousarray(gimg)), I.size, float(Rmin),
+                                  float(dR), int(Nxy), float(dxy), float(inc), _p(gI))
+    if rc != 0:
+        raise ValueError(f"orc_grad_profile: error {rc}")
+    return c2, gI

@@ -1,0 +1,242 @@
+"""Seeded synthetic inputs for the visibility / chi-square path.
+
+This module only draws inputs: uv coverages, model images and profiles, noise.
+It holds none of the method's arithmetic (no transform, no sampling, no
+chi-square), so both the oracle-side tests and the GPU side may use it.
+Observed visibilities are assembled by the caller as ``model + noise`` from
+whichever model it trusts (the oracle in tests, the library in the benchmark).
+
+The workloads stand in for the paper's unspecified profiles, images and uv
+sets: their sizes follow the paper's timing setup (M = 10^6, FP64, images
+512^2 ... 16384^2, Sec. 6) and its table of ALMA / VLA configurations
+(Sec. 3.4, Table tb:array.config.matrix.properties, lambda = 1.3 mm).
+
+Units: angles in radians, uv in wavelengths, profiles in Jy/sr, images in
+Jy/pixel, weights 1/sigma^2 in Jy^-2.
+"""
+from __future__ import annotations
+
+import math
+from dataclasses import dataclass, field
+
+import numpy as np
+
+ARCSEC = math.pi / 648000.0
+DEG = math.pi / 180.0
+
+
+# ----------------------------------------------------------------------------
+# uv coverages
+# ----------------------------------------------------------------------------
+def uv_uniform_disk(M: int, radius: float, seed: int):
+    """M points uniform in a disk: rho = R sqrt(U), phi = 2 pi U'."""
+    rng = np.random.default_rng(seed)
+    rho = radius * np.sqrt(rng.random(M))
+    phi = 2.0 * np.pi * rng.random(M)
+    return rho * np.cos(phi), rho * np.sin(phi)
+
+
+def uv_log_uniform(M: int, rho_min: float, rho_max: float, seed: int):
+    """M points with ln(rho) uniform in [ln rho_min, ln rho_max], uniform angle."""
+    rng = np.random.default_rng(seed)
+    rho = np.exp(rng.uniform(math.log(rho_min), math.log(rho_max), M))
+    phi = 2.0 * np.pi * rng.random(M)
+    return rho * np.cos(phi), rho * np.sin(phi)
+
+
+def noise(M: int, sigma: float, seed: int):
+    """Independent N(0, sigma^2) draws for the real and imaginary parts, and w = 1/sigma^2."""
+    rng = np.random.default_rng(seed)
+    nre = rng.normal(0.0, sigma, M)
+    nim = rng.normal(0.0, sigma, M)
+    w = np.full(M, 1.0 / sigma**2)
+    return nre, nim, w
+
+
+# ----------------------------------------------------------------------------
+# model images and profiles
+# ----------------------------------------------------------------------------
+def pixel_axes(N: int, dxy: float):
+    """Sky coordinates of the pixel centres: x_c = (N/2 - c) dxy (East at c = 0),
+    y_r = (N/2 - r) dxy (North at r = 0); the paper's image orientation (Sec. 2.2)."""
+    idx = np.arange(N, dtype=np.float64)
+    return (N // 2 - idx) * dxy, (N // 2 - idx) * dxy
+
+
+def gaussian_image(N: int, dxy: float, flux: float, sigma_x: float, sigma_y: float,
+                   x0: float = 0.0, y0: float = 0.0, angle: float = 0.0):
+    """Pixel values F dxy^2 / (2 pi sx sy) exp(-x'^2/2sx^2 - y'^2/2sy^2), the
+    Gaussian centred at (x0, y0) with axes rotated by ``angle``."""
+    x, y = pixel_axes(N, dxy)
+    X = x[None, :] - x0
+    Y = y[:, None] - y0
+    ca, sa = math.cos(angle), math.sin(angle)
+    xr = X * ca + Y * sa
+    yr = -X * sa + Y * ca
+    amp = flux * dxy * dxy / (2.0 * math.pi * sigma_x * sigma_y)
+    return amp * np.exp(-0.5 * (xr / sigma_x) ** 2 - 0.5 * (yr / sigma_y) ** 2)
+
+
+def blob_image(N: int, dxy: float, n_blobs: int, seed: int, total_flux: float = 1.0):
+    """Sum of elliptical Gaussian blobs: centres uniform in |x|,|y| <= N dxy / 4,
+    sigma log-uniform in [2, 16] px, axis ratio U[0.5, 1], orientation U[0, pi),
+    fluxes log-normal(0, 1) renormalised to ``total_flux``.  Each blob is
+    evaluated inside a +-8 sigma box (the rest is below 1e-13 of its peak)."""
+    rng = np.random.default_rng(seed)
+    half = N * dxy / 4.0
+    cx = rng.uniform(-half, half, n_blobs)
+    cy = rng.uniform(-half, half, n_blobs)
+    sig = np.exp(rng.uniform(math.log(2.0), math.log(16.0), n_blobs)) * dxy
+    ratio = rng.uniform(0.5, 1.0, n_blobs)
+    ang = rng.uniform(0.0, math.pi, n_blobs)
+    flux = rng.lognormal(0.0, 1.0, n_blobs)
+    flux *= total_flux / flux.sum()
+    img = np.zeros((N, N), dtype=np.float64)
+    x, y = pixel_axes(N, dxy)
+    for b in range(n_blobs):
+        sx, sy = sig[b], sig[b] * ratio[b]
+        box = int(math.ceil(8.0 * sx / dxy)) + 1
+        c0 = int(round(N // 2 - cx[b] / dxy))
+        r0 = int(round(N // 2 - cy[b] / dxy))
+        cs = slice(max(c0 - box, 0), min(c0 + box + 1, N))
+        rs = slice(max(r0 - box, 0), min(r0 + box + 1, N))
+        X = x[cs][None, :] - cx[b]
+        Y = y[rs][:, None] - cy[b]
+        ca, sa = math.cos(ang[b]), math.sin(ang[b])
+        xr = X * ca + Y * sa
+        yr = -X * sa + Y * ca
+        amp = flux[b] * dxy * dxy / (2.0 * math.pi * sx * sy)
+        img[rs, cs] += amp * np.exp(-0.5 * (xr / sx) ** 2 - 0.5 * (yr / sy) ** 2)
+    return img
+
+
+def gapped_powerlaw_profile(r_arcsec, gaps=((0.3, 0.02, 0.9), (0.7, 0.04, 0.7))):
+    """I(r) ~ r^-0.8 exp(-(r / 1'')^2) prod_g [1 - depth_g exp(-(r - r_g)^2 / (2 w_g^2))],
+    r in arcsec, gaps given as (centre, width, depth) in arcsec."""
+    r = np.asarray(r_arcsec, dtype=np.float64)
+    with np.errstate(divide="ignore"):
+        base = np.where(r > 0, r, np.inf) ** -0.8 * np.exp(-(r / 1.0) ** 2)
+    for rg, wg, dg in gaps:
+        base = base * (1.0 - dg * np.exp(-((r - rg) ** 2) / (2.0 * wg**2)))
+    return base
+
+
+def _face_on_flux(profile_fn, r_max_arcsec: float) -> float:
+    """2 pi int_0^rmax I(r) r dr (r in radians) for a profile in arbitrary units,
+    by the trapezoid rule on a fine grid in sqrt(r) (the integrand ~ r^0.2 near 0)."""
+    s = np.linspace(0.0, math.sqrt(r_max_arcsec), 400001)
+    r = s * s
+    f = np.zeros_like(r)
+    f[1:] = profile_fn(r[1:]) * r[1:] * 2.0 * s[1:]  # I(r) r dr/ds
+    return 2.0 * math.pi * np.trapezoid(f, s) * ARCSEC**2
+
+
+# ----------------------------------------------------------------------------
+# the benchmark / parity workloads
+# ----------------------------------------------------------------------------
+@dataclass
+class Workload:
+    name: str
+    kind: str                    # "image" or "profile"
+    N: int
+    dxy: float
+    u: np.ndarray
+    v: np.ndarray
+    noise_re: np.ndarray
+    noise_im: np.ndarray
+    w: np.ndarray
+    PA: float = 0.0
+    inc: float = 0.0
+    dRA: float = 0.0
+    dDec: float = 0.0
+    image: np.ndarray | None = None
+    I: np.ndarray | None = None
+    Rmin: float = 0.0
+    dR: float = 0.0
+    meta: dict = field(default_factory=dict)
+
+    @property
+    def M(self) -> int:
+        return int(self.u.size)
+
+
+def config0() -> Workload:
+    """chi2Image, 256^2 FP64: elliptical Gaussian (1 Jy, sigma 0.2'' N-S and
+    0.2'' cos 30 deg E-W, i.e. a 30 deg inclination in the image itself),
+    dxy = 0.01'', M = 10^4 uniform in a disk of radius 0.4 / dxy,
+    PA = 60 deg, dRA = dDec = 0.05'', noise sigma 1e-3 Jy."""
+    N, dxy = 256, 0.01 * ARCSEC
+    sig = 0.2 * ARCSEC
+    img = gaussian_image(N, dxy, 1.0, sig * math.cos(30 * DEG), sig)
+    u, v = uv_uniform_disk(10_000, 0.4 / dxy, seed=1000)
+    nre, nim, w = noise(u.size, 1e-3, seed=1001)
+    return Workload("config0_chi2Image_256_M1e4", "image", N, dxy, u, v, nre, nim, w,
+                    PA=60 * DEG, inc=0.0, dRA=0.05 * ARCSEC, dDec=0.05 * ARCSEC, image=img,
+                    meta={"image_inclination_deg": 30.0})
+
+
+def config1_profile(Nr: int = 4096):
+    """The gapped power-law profile of config 1 in Jy/sr, normalised to a
+    face-on flux of 1 Jy, on r_j = Rmin + j dR out to 5.4''."""
+    Rmin_as = 1e-4
+    Rmax_as = 5.4
+    dR_as = (Rmax_as - Rmin_as) / (Nr - 1)
+    r_as = Rmin_as + dR_as * np.arange(Nr)
+    norm = _face_on_flux(gapped_powerlaw_profile, Rmax_as)
+    I = gapped_powerlaw_profile(r_as) / norm
+    return I, Rmin_as * ARCSEC, dR_as * ARCSEC
+
+
+def config1(M: int = 1_000_000) -> Workload:
+    """chi2Profile, 2048^2 FP64: Nr = 4096 profile, dxy = 0.003'', M = 10^6
+    uv points log-uniform in [1.877e5, 1.2457e7] lambda (ALMA C43-10 at
+    1.3 mm), inc = 45 deg, PA = 120 deg, noise sigma 1e-3 Jy."""
+    N, dxy = 2048, 0.003 * ARCSEC
+    I, Rmin, dR = config1_profile()
+    u, v = uv_log_uniform(M, 1.877e5, 1.2457e7, seed=1100)
+    nre, nim, w = noise(u.size, 1e-3, seed=1101)
+    return Workload("config1_chi2Profile_2048_M1e6", "profile", N, dxy, u, v, nre, nim, w,
+                    PA=120 * DEG, inc=45 * DEG, I=I, Rmin=Rmin, dR=dR)
+
+
+def config2(M: int = 5_000_000) -> Workload:
+    """chi2Image, 4096^2: 200 Gaussian blobs, dxy = 0.013'' (ALMA C43-6),
+    M = 5e6 log-uniform in [1.123e4, 1.936e6] lambda, noise sigma 1e-3 Jy."""
+    N, dxy = 4096, 0.013 * ARCSEC
+    img = blob_image(N, dxy, 200, seed=1200)
+    u, v = uv_log_uniform(M, 1.123e4, 1.936e6, seed=1201)
+    nre, nim, w = noise(u.size, 1e-3, seed=1202)
+    return Workload("config2_chi2Image_4096_M5e6", "image", N, dxy, u, v, nre, nim, w,
+                    PA=0.0, inc=0.0, image=img)
+
+
+# ----------------------------------------------------------------------------
+# small random cases for parity sweeps
+# ----------------------------------------------------------------------------
+def random_case(N: int, M: int, seed: int, kind: str = "image", fill: float = 0.9,
+                Nr: int | None = None) -> Workload:
+    """Random image (or profile), uv inside ``fill`` of the valid radius
+    (N/2 - 1) du, random PA / inc / offsets, noise sigma 1e-3."""
+    rng = np.random.default_rng(seed)
+    dxy = 0.01 * ARCSEC * (1.0 + rng.random())
+    du = 1.0 / (N * dxy)
+    rho_lim = fill * (N / 2 - 1) * du
+    u, v = uv_uniform_disk(M, rho_lim, seed=seed + 1)
+    nre, nim, w = noise(M, 1e-3, seed=seed + 2)
+    w = w * rng.uniform(0.5, 1.5, M)
+    PA = rng.uniform(0.0, 2 * math.pi)
+    inc = rng.uniform(0.0, 70 * DEG)
+    dRA, dDec = rng.normal(0.0, 5 * dxy, 2)
+    if kind == "image":
+        img = rng.normal(0.0, 1e-3, (N, N)) + gaussian_image(
+            N, dxy, 1.0, 3 * dxy, 2 * dxy, x0=2 * dxy, y0=-3 * dxy, angle=0.3)
+        return Workload(f"random_image_N{N}_M{M}_s{seed}", "image", N, dxy, u, v, nre, nim, w,
+                        PA=PA, inc=inc, dRA=dRA, dDec=dDec, image=img)
+    Nr = Nr or max(2, N)
+    Rmin = 0.1 * dxy * rng.random()
+    Rmax = 0.75 * N * dxy
+    dR = (Rmax - Rmin) / (Nr - 1)
+    r = Rmin + dR * np.arange(Nr)
+    I = np.exp(-((r / (0.15 * N * dxy)) ** 2)) * (1.0 + 0.3 * rng.random(Nr)) / dxy**2
+    return Workload(f"random_profile_N{N}_M{M}_s{seed}", "profile", N, dxy, u, v, nre, nim, w,
+                    PA=PA, inc=inc, dRA=dRA, dDec=dDec, I=I, Rmin=Rmin, dR=dR)
