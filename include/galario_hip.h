@@ -1,0 +1,221 @@
+/*
+ * galario_hip.h -- C ABI of an MI355X (gfx950) implementation of the
+ * visibility / chi-square path of Tazzari, Beaujean & Testi, "GALARIO: a GPU
+ * accelerated library for analysing radio interferometer observations"
+ * (MNRAS 2018, arXiv:1709.06999).
+ *
+ * The library turns a model image, or a radial profile swept into one, into
+ * synthetic visibilities at arbitrary (u, v) points, and the weighted
+ * chi-square against observed visibilities (Sec. 2.2 lists the calls; Sec. 4,
+ * Fig. flow, the steps: create image -> rotate -> shift/FFT/shift ->
+ * interpolate -> translate -> reduce chi^2).
+ *
+ * Conventions shared by every call
+ * --------------------------------
+ *  - Units (Sec. 2.2): angles (dxy, Rmin, dR, PA, inc, dRA, dDec) in radians;
+ *    u, v in wavelengths; images in Jy/pixel; profiles in Jy/sr; visibilities
+ *    in Jy; weights w = 1/sigma^2 in Jy^-2.
+ *  - Image layout: Nxy x Nxy, row-major, row 0 = North, column 0 = East,
+ *    pixel (r, c) centred at x = (Nxy/2 - c) dxy, y = (Nxy/2 - r) dxy;
+ *    the origin (x, y) = (0, 0) is pixel (Nxy/2, Nxy/2) (Sec. 2.2, App. D).
+ *  - Transform convention (App. D): V(u, v) = sum_pixels I exp(+2 pi i (u x + v y)),
+ *    sampled by bilinear interpolation of the real-to-complex half spectrum
+ *    (Sec. 3.4) after rotating (u, v) by PA (Sec. 3.3) and mirroring points
+ *    with u' < 0; the offset (dRA, dDec) multiplies V by
+ *    exp(+2 pi i (u dRA + v dDec)) (Sec. 3.3).  The body text of Sec. 3.1
+ *    writes the conjugate convention.
+ *  - inc: for *Profile the sweep stretches x by 1/cos(inc) (Sec. 2.2).  For
+ *    *Image a non-zero inc deprojects the rotated u' <- u' cos(inc) and
+ *    scales V by cos(inc), the transform of the image stretched the same way
+ *    (extension; inc = 0 is the paper's *Image).
+ *  - Nxy must be a power of two, 16 <= Nxy <= 8192.  A uv point is usable
+ *    when all four nodes of its bilinear stencil lie on the half spectrum:
+ *    0 <= floor(|u'|/du) <= Nxy/2 - 1 and -Nxy/2 <= floor(v'/du) <= Nxy/2 - 2,
+ *    du = 1/(Nxy dxy).  Calls on raw uv arrays check this per point on the
+ *    device: offending points give NaN and raise the workspace status flag
+ *    (gal_read_status).  Calls on a dataset check it on the host before any
+ *    launch from the dataset's rho_max (GAL_ERR_UV_RANGE when
+ *    rho_max >= (Nxy/2 - 1) du).
+ *  - Precision: suffix _d = double arrays, _f = float arrays.  Scalars are
+ *    always double; uv geometry and the chi^2 accumulation run in FP64 in
+ *    both variants; the image, the FFT and the visibilities use the array
+ *    type (Sec. 2.1: identical interfaces for single and double precision).
+ *  - Pointers: every array argument is a caller-owned DEVICE pointer on the
+ *    current HIP device, contiguous, not retained after return; arrays of
+ *    complex values are interleaved (re, im).  chi2 outputs are device
+ *    doubles.  `stream` is a hipStream_t (NULL = default stream); all work is
+ *    enqueued on it and the calls return without synchronising.
+ *  - Workspace: `ws` is caller-owned device memory of at least
+ *    gal_workspace_bytes_{d,f}(Nxy, M) bytes whose first 256 bytes were zeroed
+ *    once (gal_workspace_init).  Calls sharing one workspace must be ordered
+ *    (same stream); the library itself allocates nothing in these calls.
+ *  - Errors: every call returns GAL_OK or a negative GAL_ERR_* code, checked
+ *    on the host before anything is enqueued (no output is written on an
+ *    error); gal_last_error() gives a message for the calling thread.
+ */
+#ifndef GALARIO_HIP_H
+#define GALARIO_HIP_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+#define GAL_OK               0
+#define GAL_ERR_NULL        (-1)  /* a required pointer is NULL */
+#define GAL_ERR_SIZE        (-2)  /* Nxy not a power of two in [16, 8192], Nr < 2, M < 0 */
+#define GAL_ERR_UV_RANGE    (-3)  /* dataset rho_max outside the half spectrum */
+#define GAL_ERR_SCALAR      (-4)  /* dxy <= 0, dR <= 0, Rmin < 0, cos(inc) <= 0, non-finite */
+#define GAL_ERR_WORKSPACE   (-5)  /* workspace too small / out of memory */
+#define GAL_ERR_HIP         (-6)  /* a HIP runtime call failed */
+#define GAL_ERR_UNSUPPORTED (-7)  /* e.g. dataset precision differs from the call */
+
+/* ---- library ---------------------------------------------------------- */
+const char *gal_version(void);
+/* Message describing the last error returned on the calling thread. */
+const char *gal_last_error(void);
+/* Prepare `device` (upload the twiddle tables).  Optional: every call does it
+ * on first use; call it before capturing calls into a HIP graph. */
+int gal_init(int device);
+
+/* Bytes of workspace needed by any call with this image size and point
+ * count (plain and dataset calls, sample and chi2). */
+size_t gal_workspace_bytes_d(int Nxy, int64_t M);
+size_t gal_workspace_bytes_f(int Nxy, int64_t M);
+/* Zero the control block (first 256 bytes) of a workspace, on `stream`. */
+int gal_workspace_init(void *ws, size_t ws_bytes, void *stream);
+/* Synchronise `stream`, return the workspace status flag in *status
+ * (0 = fine, 1 = some uv point fell outside the half spectrum) and clear it. */
+int gal_read_status(void *ws, void *stream, int *status);
+
+/* ---- the paper's calls (Sec. 2.2) on raw device arrays ---------------- */
+
+/* sweep: image[Nxy*Nxy] from the radial profile I[Nr] on r_j = Rmin + j dR:
+ * linear interpolation in radius rho = sqrt((x/cos inc)^2 + y^2), 0 outside
+ * [Rmin, Rmin + (Nr-1) dR], centre pixel = the first segment extrapolated to
+ * rho = 0, times dxy^2 (Sec. 2.2, Sec. 4 "Create image", App. D). */
+int gal_sweep_d(const double *I, int Nr, double Rmin, double dR, int Nxy, double dxy,
+                double inc, double *image, void *stream);
+int gal_sweep_f(const float *I, int Nr, double Rmin, double dR, int Nxy, double dxy,
+                double inc, float *image, void *stream);
+
+/* sampleImage: vis[2M] = V at the M points (Sec. 2.2, Sec. 3.3, Sec. 3.4). */
+int gal_sampleImage_d(const double *image, int Nxy, double dxy, const double *u,
+                      const double *v, int64_t M, double PA, double dRA, double dDec,
+                      double inc, double *vis, void *ws, size_t ws_bytes, void *stream);
+int gal_sampleImage_f(const float *image, int Nxy, double dxy, const float *u,
+                      const float *v, int64_t M, double PA, double dRA, double dDec,
+                      double inc, float *vis, void *ws, size_t ws_bytes, void *stream);
+
+/* sampleProfile: sweep then sampleImage, without materialising the image. */
+int gal_sampleProfile_d(const double *I, int Nr, double Rmin, double dR, int Nxy,
+                        double dxy, const double *u, const double *v, int64_t M,
+                        double inc, double PA, double dRA, double dDec, double *vis,
+                        void *ws, size_t ws_bytes, void *stream);
+int gal_sampleProfile_f(const float *I, int Nr, double Rmin, double dR, int Nxy,
+                        double dxy, const float *u, const float *v, int64_t M,
+                        double inc, double PA, double dRA, double dDec, float *vis,
+                        void *ws, size_t ws_bytes, void *stream);
+
+/* chi2Image: *chi2 = sum_k w_k |Vobs_k - V_k|^2 (Sec. 3.1, Eq. def.chi.square),
+ * reduced on the device in a fixed order (bitwise repeatable). */
+int gal_chi2Image_d(const double *image, int Nxy, double dxy, const double *u,
+                    const double *v, const double *re, const double *im, const double *w,
+                    int64_t M, double PA, double dRA, double dDec, double inc,
+                    double *chi2, void *ws, size_t ws_bytes, void *stream);
+int gal_chi2Image_f(const float *image, int Nxy, double dxy, const float *u,
+                    const float *v, const float *re, const float *im, const float *w,
+                    int64_t M, double PA, double dRA, double dDec, double inc,
+                    double *chi2, void *ws, size_t ws_bytes, void *stream);
+
+/* chi2Profile: sweep + chi2Image; only the profile is read (Sec. 4). */
+int gal_chi2Profile_d(const double *I, int Nr, double Rmin, double dR, int Nxy, double dxy,
+                      const double *u, const double *v, const double *re, const double *im,
+                      const double *w, int64_t M, double inc, double PA, double dRA,
+                      double dDec, double *chi2, void *ws, size_t ws_bytes, void *stream);
+int gal_chi2Profile_f(const float *I, int Nr, double Rmin, double dR, int Nxy, double dxy,
+                      const float *u, const float *v, const float *re, const float *im,
+                      const float *w, int64_t M, double inc, double PA, double dRA,
+                      double dDec, double *chi2, void *ws, size_t ws_bytes, void *stream);
+
+/* ---- separately callable steps (Sec. 4: every operation is accessible) -- */
+
+/* spectrum: the half spectrum G[Nxy][Nxy/2+1] (interleaved complex) of the
+ * image with its origin moved to pixel (Nxy/2, Nxy/2):
+ * G[p][q] = sum_{r,c} img[r][c] exp(-2 pi i (p (r - Nxy/2) + q (c - Nxy/2)) / Nxy),
+ * row p holds frequency p - Nxy [p >= Nxy/2]  (Sec. 4: shift -> FFT -> shift). */
+int gal_spectrum_d(const double *image, int Nxy, double *spec, void *ws, size_t ws_bytes,
+                   void *stream);
+int gal_spectrum_f(const float *image, int Nxy, float *spec, void *ws, size_t ws_bytes,
+                   void *stream);
+/* sample_spectrum: sample a half spectrum in the layout above at the M points
+ * (rotation, mirror, bilinear, deprojection, phase; Sec. 3.3, Sec. 3.4). */
+int gal_sample_spectrum_d(const double *spec, int Nxy, double dxy, const double *u,
+                          const double *v, int64_t M, double PA, double dRA, double dDec,
+                          double inc, double *vis, void *ws, size_t ws_bytes, void *stream);
+int gal_sample_spectrum_f(const float *spec, int Nxy, double dxy, const float *u,
+                          const float *v, int64_t M, double PA, double dRA, double dDec,
+                          double inc, float *vis, void *ws, size_t ws_bytes, void *stream);
+
+/* ---- device-resident datasets ------------------------------------------
+ * A dataset is an observation (u, v, Re Vobs, Im Vobs, w)[M] copied once into
+ * library-owned device memory, with rho_max = max_k sqrt(u_k^2 + v_k^2)
+ * (PA-independent).  Calls on a dataset read no observation from the host,
+ * check the uv range on the host, and only transform the part of the half
+ * spectrum that the points can reach (|u'|, |v'| <= rho_max): the samples are
+ * the same as on the full spectrum.  `precision` of the arrays is fixed at
+ * creation (_d: double, _f: float).  re/im/w may be NULL for a dataset used
+ * only by sample calls.  Creation allocates and synchronises `stream`. */
+typedef struct gal_dataset gal_dataset;
+int gal_dataset_create_d(const double *u, const double *v, const double *re,
+                         const double *im, const double *w, int64_t M, void *stream,
+                         gal_dataset **out);
+int gal_dataset_create_f(const float *u, const float *v, const float *re,
+                         const float *im, const float *w, int64_t M, void *stream,
+                         gal_dataset **out);
+int gal_dataset_destroy(gal_dataset *ds);
+/* M, rho_max and the precision (8 = double, 4 = float) of a dataset. */
+int gal_dataset_info(const gal_dataset *ds, int64_t *M, double *rho_max, int *precision);
+
+int gal_chi2Image_ds_d(const gal_dataset *ds, const double *image, int Nxy, double dxy,
+                       double PA, double dRA, double dDec, double inc, double *chi2,
+                       void *ws, size_t ws_bytes, void *stream);
+int gal_chi2Image_ds_f(const gal_dataset *ds, const float *image, int Nxy, double dxy,
+                       double PA, double dRA, double dDec, double inc, double *chi2,
+                       void *ws, size_t ws_bytes, void *stream);
+int gal_chi2Profile_ds_d(const gal_dataset *ds, const double *I, int Nr, double Rmin,
+                         double dR, int Nxy, double dxy, double inc, double PA, double dRA,
+                         double dDec, double *chi2, void *ws, size_t ws_bytes, void *stream);
+int gal_chi2Profile_ds_f(const gal_dataset *ds, const float *I, int Nr, double Rmin,
+                         double dR, int Nxy, double dxy, double inc, double PA, double dRA,
+                         double dDec, double *chi2, void *ws, size_t ws_bytes, void *stream);
+int gal_sampleImage_ds_d(const gal_dataset *ds, const double *image, int Nxy, double dxy,
+                         double PA, double dRA, double dDec, double inc, double *vis,
+                         void *ws, size_t ws_bytes, void *stream);
+int gal_sampleImage_ds_f(const gal_dataset *ds, const float *image, int Nxy, double dxy,
+                         double PA, double dRA, double dDec, double inc, float *vis,
+                         void *ws, size_t ws_bytes, void *stream);
+int gal_sampleProfile_ds_d(const gal_dataset *ds, const double *I, int Nr, double Rmin,
+                           double dR, int Nxy, double dxy, double inc, double PA,
+                           double dRA, double dDec, double *vis, void *ws, size_t ws_bytes,
+                           void *stream);
+int gal_sampleProfile_ds_f(const gal_dataset *ds, const float *I, int Nr, double Rmin,
+                           double dR, int Nxy, double dxy, double inc, double PA,
+                           double dRA, double dDec, float *vis, void *ws, size_t ws_bytes,
+                           void *stream);
+
+/* ---- per-kernel timing (HIP events on the launch stream) ----------------
+ * When enabled, every kernel launch of the library is bracketed by HIP events
+ * recorded on its stream.  gal_timing_read synchronises, and for each kernel
+ * name fills the total milliseconds and launch count since the last reset;
+ * it returns the number of kernel names (at most `cap` are filled). */
+int gal_timing_enable(int on);
+int gal_timing_reset(void);
+int gal_timing_read(int cap, const char **names, double *total_ms, int64_t *launches);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* GALARIO_HIP_H */

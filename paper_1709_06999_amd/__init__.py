@@ -1,0 +1,370 @@
+"""MI355X (gfx950) visibility / chi-square library after GALARIO
+(Tazzari, Beaujean & Testi 2018, arXiv:1709.06999).
+
+Thin torch binding of the C ABI in ``include/galario_hip.h``: it checks
+tensors, picks the precision from their dtype (float64 -> ``_d``,
+float32 -> ``_f``), passes device pointers and the current HIP stream, and
+keeps one workspace per (device, dtype).  Every step of the path runs in the
+library's HIP kernels; there is no other implementation behind these calls.
+
+The calls follow the paper's Python interface (Sec. 2.2):
+
+    sampleImage(image, dxy, u, v, PA=0, dRA=0, dDec=0, inc=0)  -> complex V [M]
+    sampleProfile(I, Rmin, dR, Nxy, dxy, u, v, inc=0, PA=0, dRA=0, dDec=0)
+    chi2Image(image, dxy, u, v, Re, Im, w, PA=0, dRA=0, dDec=0, inc=0) -> 0-d tensor
+    chi2Profile(I, Rmin, dR, Nxy, dxy, u, v, Re, Im, w, inc=0, PA=0, dRA=0, dDec=0)
+    sweep(I, Rmin, dR, Nxy, dxy, inc=0) -> image [Nxy, Nxy]
+
+Angles in radians, uv in wavelengths.  chi2 results stay on the device as
+0-d float64 tensors (call ``float()`` to synchronise).
+"""
+from __future__ import annotations
+
+import ctypes
+
+import torch
+
+from . import _native
+from ._native import GalarioError, check
+
+__all__ = [
+    "sweep", "sampleImage", "sampleProfile", "chi2Image", "chi2Profile", "spectrum",
+    "sample_spectrum", "Dataset", "Workspace", "read_status", "timing", "GalarioError",
+    "version", "init",
+]
+
+
+def _lib():
+    return _native.lib()
+
+
+def version() -> str:
+    return _lib().gal_version().decode()
+
+
+def init(device: int | None = None):
+    dev = torch.cuda.current_device() if device is None else int(device)
+    check(_lib().gal_init(dev), "gal_init")
+
+
+def _sfx(dtype: torch.dtype) -> str:
+    if dtype == torch.float64:
+        return "_d"
+    if dtype == torch.float32:
+        return "_f"
+    raise TypeError(f"arrays must be float64 or float32, got {dtype}")
+
+
+def _stream(device: torch.device):
+    return ctypes.c_void_p(torch.cuda.current_stream(device).cuda_stream)
+
+
+def _ptr(t: torch.Tensor | None):
+    return ctypes.c_void_p(0 if t is None else t.data_ptr())
+
+
+def _arr(t, name: str, dtype: torch.dtype, device: torch.device, n: int | None = None):
+    if not isinstance(t, torch.Tensor):
+        raise TypeError(f"{name} must be a torch tensor on the GPU")
+    if t.device != device:
+        raise ValueError(f"{name} is on {t.device}, expected {device}")
+    if t.dtype != dtype:
+        raise TypeError(f"{name} has dtype {t.dtype}, expected {dtype}")
+    if not t.is_contiguous():
+        raise ValueError(f"{name} must be contiguous")
+    if n is not None and t.numel() != n:
+        raise ValueError(f"{name} has {t.numel()} elements, expected {n}")
+    return t
+
+
+def _device_of(t: torch.Tensor) -> torch.device:
+    if not isinstance(t, torch.Tensor) or t.device.type != "cuda":
+        raise TypeError("inputs must be torch tensors on a GPU (device 'cuda')")
+    return t.device
+
+
+class Workspace:
+    """Device scratch memory for the library calls on one device and dtype.
+
+    Grows on demand; its 256-byte control block is zero at allocation.  Calls
+    that share a workspace must run on one stream (they do when they use the
+    default per-device workspace from the current stream)."""
+
+    def __init__(self, device: torch.device, dtype: torch.dtype):
+        self.device = torch.device(device)
+        self.dtype = dtype
+        self.buf = torch.zeros(0, dtype=torch.uint8, device=self.device)
+
+    def reserve(self, Nxy: int, M: int) -> torch.Tensor:
+        need = getattr(_lib(), "gal_workspace_bytes" + _sfx(self.dtype))(int(Nxy), int(M))
+        if need == 0:
+            raise GalarioError(-2, f"gal_workspace_bytes(Nxy={Nxy}, M={M})")
+        if self.buf.numel() < need:
+            self.buf = torch.zeros(int(need), dtype=torch.uint8, device=self.device)
+        return self.buf
+
+
+_default_ws: dict = {}
+
+
+def _ws(device: torch.device, dtype: torch.dtype, ws: Workspace | None) -> Workspace:
+    if ws is not None:
+        return ws
+    key = (device.index if device.index is not None else torch.cuda.current_device(), dtype)
+    if key not in _default_ws:
+        _default_ws[key] = Workspace(torch.device("cuda", key[0]), dtype)
+    return _default_ws[key]
+
+
+def read_status(dtype: torch.dtype = torch.float64, device=None, ws: Workspace | None = None) -> int:
+    """1 if a uv point of a raw-array call fell outside the half spectrum since
+    the last read (its samples are NaN), else 0.  Synchronises the stream."""
+    dev = torch.device("cuda", torch.cuda.current_device()) if device is None else torch.device(device)
+    w = _ws(dev, dtype, ws)
+    if w.buf.numel() == 0:
+        return 0
+    st = ctypes.c_int(0)
+    with torch.cuda.device(dev):
+        check(_lib().gal_read_status(_ptr(w.buf), _stream(dev), ctypes.byref(st)), "gal_read_status")
+    return int(st.value)
+
+
+# ----------------------------------------------------------------------------
+def sweep(I, Rmin, dR, Nxy, dxy, inc=0.0):
+    dev = _device_of(I)
+    _arr(I, "I", I.dtype, dev)
+    out = torch.empty((int(Nxy), int(Nxy)), dtype=I.dtype, device=dev)
+    with torch.cuda.device(dev):
+        check(getattr(_lib(), "gal_sweep" + _sfx(I.dtype))(
+            _ptr(I), I.numel(), float(Rmin), float(dR), int(Nxy), float(dxy), float(inc),
+            _ptr(out), _stream(dev)), "sweep")
+    return out
+
+
+def sampleImage(image, dxy, u, v, PA=0.0, dRA=0.0, dDec=0.0, inc=0.0, ws: Workspace | None = None):
+    dev = _device_of(image)
+    dt = image.dtype
+    N = image.shape[0]
+    if image.dim() != 2 or image.shape[1] != N:
+        raise ValueError("image must be square [Nxy, Nxy]")
+    _arr(image, "image", dt, dev)
+    M = u.numel()
+    _arr(u, "u", dt, dev, M), _arr(v, "v", dt, dev, M)
+    out = torch.empty((M, 2), dtype=dt, device=dev)
+    w = _ws(dev, dt, ws).reserve(N, M)
+    with torch.cuda.device(dev):
+        check(getattr(_lib(), "gal_sampleImage" + _sfx(dt))(
+            _ptr(image), N, float(dxy), _ptr(u), _ptr(v), M, float(PA), float(dRA), float(dDec),
+            float(inc), _ptr(out), _ptr(w), w.numel(), _stream(dev)), "sampleImage")
+    return torch.view_as_complex(out)
+
+
+def sampleProfile(I, Rmin, dR, Nxy, dxy, u, v, inc=0.0, PA=0.0, dRA=0.0, dDec=0.0,
+                  ws: Workspace | None = None):
+    dev = _device_of(I)
+    dt = I.dtype
+    _arr(I, "I", dt, dev)
+    M = u.numel()
+    _arr(u, "u", dt, dev, M), _arr(v, "v", dt, dev, M)
+    out = torch.empty((M, 2), dtype=dt, device=dev)
+    w = _ws(dev, dt, ws).reserve(Nxy, M)
+    with torch.cuda.device(dev):
+        check(getattr(_lib(), "gal_sampleProfile" + _sfx(dt))(
+            _ptr(I), I.numel(), float(Rmin), float(dR), int(Nxy), float(dxy), _ptr(u), _ptr(v), M,
+            float(inc), float(PA), float(dRA), float(dDec), _ptr(out), _ptr(w), w.numel(),
+            _stream(dev)), "sampleProfile")
+    return torch.view_as_complex(out)
+
+
+def chi2Image(image, dxy, u, v, re, im, w, PA=0.0, dRA=0.0, dDec=0.0, inc=0.0,
+              ws: Workspace | None = None, out: torch.Tensor | None = None):
+    dev = _device_of(image)
+    dt = image.dtype
+    N = image.shape[0]
+    if image.dim() != 2 or image.shape[1] != N:
+        raise ValueError("image must be square [Nxy, Nxy]")
+    _arr(image, "image", dt, dev)
+    M = u.numel()
+    for t, n in ((u, "u"), (v, "v"), (re, "Re"), (im, "Im"), (w, "w")):
+        _arr(t, n, dt, dev, M)
+    res = torch.empty((), dtype=torch.float64, device=dev) if out is None else out
+    wsb = _ws(dev, dt, ws).reserve(N, M)
+    with torch.cuda.device(dev):
+        check(getattr(_lib(), "gal_chi2Image" + _sfx(dt))(
+            _ptr(image), N, float(dxy), _ptr(u), _ptr(v), _ptr(re), _ptr(im), _ptr(w), M,
+            float(PA), float(dRA), float(dDec), float(inc), _ptr(res), _ptr(wsb), wsb.numel(),
+            _stream(dev)), "chi2Image")
+    return res
+
+
+def chi2Profile(I, Rmin, dR, Nxy, dxy, u, v, re, im, w, inc=0.0, PA=0.0, dRA=0.0, dDec=0.0,
+                ws: Workspace | None = None, out: torch.Tensor | None = None):
+    dev = _device_of(I)
+    dt = I.dtype
+    _arr(I, "I", dt, dev)
+    M = u.numel()
+    for t, n in ((u, "u"), (v, "v"), (re, "Re"), (im, "Im"), (w, "w")):
+        _arr(t, n, dt, dev, M)
+    res = torch.empty((), dtype=torch.float64, device=dev) if out is None else out
+    wsb = _ws(dev, dt, ws).reserve(Nxy, M)
+    with torch.cuda.device(dev):
+        check(getattr(_lib(), "gal_chi2Profile" + _sfx(dt))(
+            _ptr(I), I.numel(), float(Rmin), float(dR), int(Nxy), float(dxy), _ptr(u), _ptr(v),
+            _ptr(re), _ptr(im), _ptr(w), M, float(inc), float(PA), float(dRA), float(dDec),
+            _ptr(res), _ptr(wsb), wsb.numel(), _stream(dev)), "chi2Profile")
+    return res
+
+
+def spectrum(image, ws: Workspace | None = None):
+    """Half spectrum G [Nxy, Nxy/2+1] (complex) of the image with its origin at
+    pixel (Nxy/2, Nxy/2); row p is frequency p - Nxy [p >= Nxy/2]."""
+    dev = _device_of(image)
+    dt = image.dtype
+    N = image.shape[0]
+    _arr(image, "image", dt, dev, N * N)
+    out = torch.empty((N, N // 2 + 1, 2), dtype=dt, device=dev)
+    wsb = _ws(dev, dt, ws).reserve(N, 0)
+    with torch.cuda.device(dev):
+        check(getattr(_lib(), "gal_spectrum" + _sfx(dt))(
+            _ptr(image), N, _ptr(out), _ptr(wsb), wsb.numel(), _stream(dev)), "spectrum")
+    return torch.view_as_complex(out)
+
+
+def sample_spectrum(spec, dxy, u, v, PA=0.0, dRA=0.0, dDec=0.0, inc=0.0,
+                    ws: Workspace | None = None):
+    """Sample a half spectrum laid out as ``spectrum`` returns it."""
+    dev = _device_of(spec)
+    if not spec.is_complex():
+        raise TypeError("spec must be complex")
+    sr = torch.view_as_real(spec)
+    dt = sr.dtype
+    N = spec.shape[0]
+    if spec.shape != (N, N // 2 + 1) or not spec.is_contiguous():
+        raise ValueError("spec must be a contiguous [Nxy, Nxy/2+1] complex tensor")
+    M = u.numel()
+    _arr(u, "u", dt, dev, M), _arr(v, "v", dt, dev, M)
+    out = torch.empty((M, 2), dtype=dt, device=dev)
+    wsb = _ws(dev, dt, ws).reserve(N, M)
+    with torch.cuda.device(dev):
+        check(getattr(_lib(), "gal_sample_spectrum" + _sfx(dt))(
+            _ptr(sr), N, float(dxy), _ptr(u), _ptr(v), M, float(PA), float(dRA), float(dDec),
+            float(inc), _ptr(out), _ptr(wsb), wsb.numel(), _stream(dev)), "sample_spectrum")
+    return torch.view_as_complex(out)
+
+
+# ----------------------------------------------------------------------------
+class Dataset:
+    """An observation registered once in library-owned device memory.
+
+    Calls on a dataset check the uv range on the host and transform only the
+    part of the half spectrum its points reach (same samples as the full
+    spectrum)."""
+
+    def __init__(self, u, v, re=None, im=None, w=None):
+        dev = _device_of(u)
+        dt = u.dtype
+        M = u.numel()
+        _arr(u, "u", dt, dev, M), _arr(v, "v", dt, dev, M)
+        if re is not None or im is not None or w is not None:
+            for t, n in ((re, "Re"), (im, "Im"), (w, "w")):
+                _arr(t, n, dt, dev, M)
+        self.device, self.dtype, self.M = dev, dt, M
+        self.has_obs = re is not None
+        h = ctypes.c_void_p(0)
+        with torch.cuda.device(dev):
+            check(getattr(_lib(), "gal_dataset_create" + _sfx(dt))(
+                _ptr(u), _ptr(v), _ptr(re), _ptr(im), _ptr(w), M, _stream(dev), ctypes.byref(h)),
+                "Dataset")
+        self._h = h
+        m, rho, prec = ctypes.c_int64(0), ctypes.c_double(0), ctypes.c_int(0)
+        check(_lib().gal_dataset_info(h, ctypes.byref(m), ctypes.byref(rho), ctypes.byref(prec)),
+              "gal_dataset_info")
+        self.rho_max = float(rho.value)
+
+    def close(self):
+        if getattr(self, "_h", None) and self._h.value:
+            with torch.cuda.device(self.device):
+                _lib().gal_dataset_destroy(self._h)
+            self._h = ctypes.c_void_p(0)
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def _chk(self, t, name):
+        return _arr(t, name, self.dtype, self.device)
+
+    def chi2Image(self, image, dxy, PA=0.0, dRA=0.0, dDec=0.0, inc=0.0,
+                  ws: Workspace | None = None, out: torch.Tensor | None = None):
+        self._chk(image, "image")
+        N = image.shape[0]
+        res = torch.empty((), dtype=torch.float64, device=self.device) if out is None else out
+        wsb = _ws(self.device, self.dtype, ws).reserve(N, self.M)
+        with torch.cuda.device(self.device):
+            check(getattr(_lib(), "gal_chi2Image_ds" + _sfx(self.dtype))(
+                self._h, _ptr(image), N, float(dxy), float(PA), float(dRA), float(dDec), float(inc),
+                _ptr(res), _ptr(wsb), wsb.numel(), _stream(self.device)), "Dataset.chi2Image")
+        return res
+
+    def chi2Profile(self, I, Rmin, dR, Nxy, dxy, inc=0.0, PA=0.0, dRA=0.0, dDec=0.0,
+                    ws: Workspace | None = None, out: torch.Tensor | None = None):
+        self._chk(I, "I")
+        res = torch.empty((), dtype=torch.float64, device=self.device) if out is None else out
+        wsb = _ws(self.device, self.dtype, ws).reserve(Nxy, self.M)
+        with torch.cuda.device(self.device):
+            check(getattr(_lib(), "gal_chi2Profile_ds" + _sfx(self.dtype))(
+                self._h, _ptr(I), I.numel(), float(Rmin), float(dR), int(Nxy), float(dxy),
+                float(inc), float(PA), float(dRA), float(dDec), _ptr(res), _ptr(wsb), wsb.numel(),
+                _stream(self.device)), "Dataset.chi2Profile")
+        return res
+
+    def sampleImage(self, image, dxy, PA=0.0, dRA=0.0, dDec=0.0, inc=0.0,
+                    ws: Workspace | None = None):
+        self._chk(image, "image")
+        N = image.shape[0]
+        out = torch.empty((self.M, 2), dtype=self.dtype, device=self.device)
+        wsb = _ws(self.device, self.dtype, ws).reserve(N, self.M)
+        with torch.cuda.device(self.device):
+            check(getattr(_lib(), "gal_sampleImage_ds" + _sfx(self.dtype))(
+                self._h, _ptr(image), N, float(dxy), float(PA), float(dRA), float(dDec), float(inc),
+                _ptr(out), _ptr(wsb), wsb.numel(), _stream(self.device)), "Dataset.sampleImage")
+        return torch.view_as_complex(out)
+
+    def sampleProfile(self, I, Rmin, dR, Nxy, dxy, inc=0.0, PA=0.0, dRA=0.0, dDec=0.0,
+                      ws: Workspace | None = None):
+        self._chk(I, "I")
+        out = torch.empty((self.M, 2), dtype=self.dtype, device=self.device)
+        wsb = _ws(self.device, self.dtype, ws).reserve(Nxy, self.M)
+        with torch.cuda.device(self.device):
+            check(getattr(_lib(), "gal_sampleProfile_ds" + _sfx(self.dtype))(
+                self._h, _ptr(I), I.numel(), float(Rmin), float(dR), int(Nxy), float(dxy),
+                float(inc), float(PA), float(dRA), float(dDec), _ptr(out), _ptr(wsb), wsb.numel(),
+                _stream(self.device)), "Dataset.sampleProfile")
+        return torch.view_as_complex(out)
+
+
+# ----------------------------------------------------------------------------
+class timing:
+    """Per-kernel HIP-event timing inside the library (for benchmarks)."""
+
+    @staticmethod
+    def enable(on: bool = True):
+        check(_lib().gal_timing_enable(1 if on else 0), "gal_timing_enable")
+
+    @staticmethod
+    def reset():
+        check(_lib().gal_timing_reset(), "gal_timing_reset")
+
+    @staticmethod
+    def read() -> dict:
+        """{kernel name: (total ms, launches)}; synchronises."""
+        n = _lib().gal_timing_read(0, None, None, None)
+        if n < 0:
+            check(n, "gal_timing_read")
+        names = (ctypes.c_char_p * max(n, 1))()
+        ms = (ctypes.c_double * max(n, 1))()
+        cnt = (ctypes.c_int64 * max(n, 1))()
+        n = _lib().gal_timing_read(n, names, ms, cnt)
+        return {names[i].decode(): (ms[i], int(cnt[i])) for i in range(n)}

@@ -1,0 +1,107 @@
+"""ctypes declarations of the C ABI in include/galario_hip.h.
+
+Loading fails loudly when the HIP library has not been built: there is no
+fallback implementation.
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(HERE, "libgalario_hip.so")
+
+GAL_OK = 0
+ERRORS = {
+    -1: "GAL_ERR_NULL",
+    -2: "GAL_ERR_SIZE",
+    -3: "GAL_ERR_UV_RANGE",
+    -4: "GAL_ERR_SCALAR",
+    -5: "GAL_ERR_WORKSPACE",
+    -6: "GAL_ERR_HIP",
+    -7: "GAL_ERR_UNSUPPORTED",
+}
+
+P = ctypes.c_void_p
+D = ctypes.c_double
+I = ctypes.c_int
+I64 = ctypes.c_int64
+SZ = ctypes.c_size_t
+
+# name -> (restype, argtypes); the _d and _f variants share a signature
+_SIG = {
+    "gal_version": (ctypes.c_char_p, []),
+    "gal_last_error": (ctypes.c_char_p, []),
+    "gal_init": (I, [I]),
+    "gal_workspace_bytes_d": (SZ, [I, I64]),
+    "gal_workspace_bytes_f": (SZ, [I, I64]),
+    "gal_workspace_init": (I, [P, SZ, P]),
+    "gal_read_status": (I, [P, P, ctypes.POINTER(I)]),
+    "gal_sweep": (I, [P, I, D, D, I, D, D, P, P]),
+    "gal_sampleImage": (I, [P, I, D, P, P, I64, D, D, D, D, P, P, SZ, P]),
+    "gal_sampleProfile": (I, [P, I, D, D, I, D, P, P, I64, D, D, D, D, P, P, SZ, P]),
+    "gal_chi2Image": (I, [P, I, D, P, P, P, P, P, I64, D, D, D, D, P, P, SZ, P]),
+    "gal_chi2Profile": (I, [P, I, D, D, I, D, P, P, P, P, P, I64, D, D, D, D, P, P, SZ, P]),
+    "gal_spectrum": (I, [P, I, P, P, SZ, P]),
+    "gal_sample_spectrum": (I, [P, I, D, P, P, I64, D, D, D, D, P, P, SZ, P]),
+    "gal_dataset_create": (I, [P, P, P, P, P, I64, P, ctypes.POINTER(P)]),
+    "gal_dataset_destroy": (I, [P]),
+    "gal_dataset_info": (I, [P, ctypes.POINTER(I64), ctypes.POINTER(D), ctypes.POINTER(I)]),
+    "gal_chi2Image_ds": (I, [P, P, I, D, D, D, D, D, P, P, SZ, P]),
+    "gal_chi2Profile_ds": (I, [P, P, I, D, D, I, D, D, D, D, D, P, P, SZ, P]),
+    "gal_sampleImage_ds": (I, [P, P, I, D, D, D, D, D, P, P, SZ, P]),
+    "gal_sampleProfile_ds": (I, [P, P, I, D, D, I, D, D, D, D, D, P, P, SZ, P]),
+    "gal_timing_enable": (I, [I]),
+    "gal_timing_reset": (I, []),
+    "gal_timing_read": (I, [I, ctypes.POINTER(ctypes.c_char_p), ctypes.POINTER(D),
+                            ctypes.POINTER(I64)]),
+}
+_PRECISION_SUFFIXED = {
+    "gal_sweep", "gal_sampleImage", "gal_sampleProfile", "gal_chi2Image", "gal_chi2Profile",
+    "gal_spectrum", "gal_sample_spectrum", "gal_dataset_create", "gal_chi2Image_ds",
+    "gal_chi2Profile_ds", "gal_sampleImage_ds", "gal_sampleProfile_ds",
+}
+
+
+def exported_names():
+    """Every symbol the header declares."""
+    names = []
+    for n in _SIG:
+        if n in _PRECISION_SUFFIXED:
+            names += [n + "_d", n + "_f"]
+        else:
+            names.append(n)
+    return names
+
+
+_lib = None
+
+
+def lib():
+    global _lib
+    if _lib is not None:
+        return _lib
+    if not os.path.exists(LIB_PATH):
+        raise ImportError(
+            f"{LIB_PATH} is missing: build the HIP library first "
+            "(python -m paper_1709_06999_amd.build or __graft_entry__.build())")
+    L = ctypes.CDLL(LIB_PATH)
+    for n, (res, args) in _SIG.items():
+        for full in ([n + "_d", n + "_f"] if n in _PRECISION_SUFFIXED else [n]):
+            f = getattr(L, full)
+            f.restype = res
+            f.argtypes = args
+    _lib = L
+    return L
+
+
+class GalarioError(RuntimeError):
+    def __init__(self, code: int, where: str):
+        msg = lib().gal_last_error().decode(errors="replace")
+        super().__init__(f"{where}: {ERRORS.get(code, code)}: {msg}")
+        self.code = code
+
+
+def check(rc: int, where: str):
+    if rc != GAL_OK:
+        raise GalarioError(rc, where)
