@@ -179,6 +179,11 @@ int gal_dataset_destroy(gal_dataset *ds);
 /* M, rho_max and the precision (8 = double, 4 = float) of a dataset. */
 int gal_dataset_info(const gal_dataset *ds, int64_t *M, double *rho_max, int *precision);
 
+/* Part of the half spectrum a call on a dataset transforms for this image:
+ * columns q in [0, *Q) and rows p~ in [-*P, *P] (frequencies in units of
+ * du = 1/(Nxy dxy)); *Q = Nxy/2 + 1, *P = Nxy/2 is the whole spectrum. */
+int gal_dataset_geometry(const gal_dataset *ds, int Nxy, double dxy, int *Q, int *P);
+
 int gal_chi2Image_ds_d(const gal_dataset *ds, const double *image, int Nxy, double dxy,
                        double PA, double dRA, double dDec, double inc, double *chi2,
                        void *ws, size_t ws_bytes, void *stream);

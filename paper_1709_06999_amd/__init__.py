@@ -281,6 +281,14 @@ class Dataset:
               "gal_dataset_info")
         self.rho_max = float(rho.value)
 
+    def geometry(self, Nxy, dxy):
+        """(Q, P): columns [0, Q) and rows [-P, P] of the half spectrum that
+        calls on this dataset transform for an Nxy image of pixel dxy."""
+        q, p = ctypes.c_int(0), ctypes.c_int(0)
+        check(_lib().gal_dataset_geometry(self._h, int(Nxy), float(dxy), ctypes.byref(q),
+                                          ctypes.byref(p)), "gal_dataset_geometry")
+        return int(q.value), int(p.value)
+
     def close(self):
         if getattr(self, "_h", None) and self._h.value:
             with torch.cuda.device(self.device):

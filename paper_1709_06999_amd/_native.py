@@ -47,6 +47,7 @@ _SIG = {
     "gal_dataset_create": (I, [P, P, P, P, P, I64, P, ctypes.POINTER(P)]),
     "gal_dataset_destroy": (I, [P]),
     "gal_dataset_info": (I, [P, ctypes.POINTER(I64), ctypes.POINTER(D), ctypes.POINTER(I)]),
+    "gal_dataset_geometry": (I, [P, I, D, ctypes.POINTER(I), ctypes.POINTER(I)]),
     "gal_chi2Image_ds": (I, [P, P, I, D, D, D, D, D, P, P, SZ, P]),
     "gal_chi2Profile_ds": (I, [P, P, I, D, D, I, D, D, D, D, D, P, P, SZ, P]),
     "gal_sampleImage_ds": (I, [P, P, I, D, D, D, D, D, P, P, SZ, P]),

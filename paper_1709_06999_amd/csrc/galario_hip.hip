@@ -8,7 +8,9 @@
 #include <cmath>
 #include <cstdarg>
 #include <cstdio>
+#include <algorithm>
 #include <cstring>
+#include <utility>
 #include <mutex>
 #include <string>
 #include <vector>
@@ -216,6 +218,47 @@ static int dispatch_fft(int N, const T *src, bool profile, const SweepArgs &sw, 
     }
 }
 
+// Swept-profile transform (real, even spectrum): rows r in [0, N/2] in pairs,
+// then column pairs; result SR[q * CS + p], p in [0, P], q in [0, Qe).
+template <typename T, int N>
+static int launch_fft_sym(const T *I, const SweepArgs &sw, const Geom &g, int Qe, T *XR,
+                          hipStream_t s) {
+    using CC = ColCfg<T, N>;
+    {
+        const int pairs = N / 4 + 1;
+        const dim3 grid((pairs + CC::B - 1) / CC::B);
+        TimedLaunch tl("k_rows_sym", s);
+        k_rows_sym<T, CC><<<grid, CC::NT, 0, s>>>(I, sw, g, Qe, XR);
+    }
+    int rc = check_launch();
+    if (rc) return rc;
+    {
+        const int pairs = Qe / 2;
+        const dim3 grid((pairs + CC::B - 1) / CC::B);
+        TimedLaunch tl("k_cols_sym", s);
+        k_cols_sym<T, CC><<<grid, CC::NT, 0, s>>>(g, Qe, XR);
+    }
+    return check_launch();
+}
+
+template <typename T>
+static int dispatch_fft_sym(int N, const T *I, const SweepArgs &sw, const Geom &g, int Qe, T *XR,
+                            hipStream_t s) {
+    switch (N) {
+        case 16: return launch_fft_sym<T, 16>(I, sw, g, Qe, XR, s);
+        case 32: return launch_fft_sym<T, 32>(I, sw, g, Qe, XR, s);
+        case 64: return launch_fft_sym<T, 64>(I, sw, g, Qe, XR, s);
+        case 128: return launch_fft_sym<T, 128>(I, sw, g, Qe, XR, s);
+        case 256: return launch_fft_sym<T, 256>(I, sw, g, Qe, XR, s);
+        case 512: return launch_fft_sym<T, 512>(I, sw, g, Qe, XR, s);
+        case 1024: return launch_fft_sym<T, 1024>(I, sw, g, Qe, XR, s);
+        case 2048: return launch_fft_sym<T, 2048>(I, sw, g, Qe, XR, s);
+        case 4096: return launch_fft_sym<T, 4096>(I, sw, g, Qe, XR, s);
+        case 8192: return launch_fft_sym<T, 8192>(I, sw, g, Qe, XR, s);
+        default: return fail(GAL_ERR_SIZE, "Nxy=%d unsupported", N);
+    }
+}
+
 // ---------------------------------------------------------------------------
 // workspace: [control 256 B][partials][XT]
 static size_t align256(size_t x) { return (x + 255) & ~(size_t)255; }
@@ -319,6 +362,7 @@ template <typename T>
 struct Obs {
     const T *u, *v, *re, *im, *w;
     int64_t M;
+    const int32_t *perm;  // stored point k -> output slot perm[k] (NULL: k)
 };
 
 template <typename T>
@@ -330,20 +374,53 @@ static int run_path(const T *src, bool profile, const SweepArgs &sw, const Geom 
     WS w;
     rc = carve<T>(ws, ws_bytes_, g.N, o.M, w);
     if (rc) return rc;
+    const SampleArgs sa = make_sample(g, o.M, dxy, PA, dRA, dDec, inc);
+    const dim3 grid((unsigned)sample_blocks(o.M));
+    if (profile) {
+        // real spectrum of the (even) swept image, stored per column with stride N/2 + 2
+        Geom gr = g;
+        gr.CS = g.N / 2 + 2;
+        const int Qe = (g.Q + 1) & ~1;
+        T *XR = (T *)w.xt;
+        rc = dispatch_fft_sym<T>(g.N, src, sw, gr, Qe, XR, s);
+        if (rc) return rc;
+        if (chi2) {
+            {
+                TimedLaunch tl("k_sample_sym_chi2", s);
+                k_sample_sym<T, true><<<grid, SAMPLE_NT, 0, s>>>(XR, gr, sa, o.u, o.v, o.re, o.im,
+                                                                 o.w, nullptr, nullptr, w.partials,
+                                                                 w.ctl);
+            }
+            rc = check_launch();
+            if (rc) return rc;
+            TimedLaunch tl("k_reduce", s);
+            k_reduce<<<1, SAMPLE_NT, 0, s>>>(w.partials, (int)grid.x, chi2);
+        } else {
+            TimedLaunch tl("k_sample_sym_vis", s);
+            k_sample_sym<T, false><<<grid, SAMPLE_NT, 0, s>>>(XR, gr, sa, o.u, o.v, nullptr,
+                                                              nullptr, nullptr, (c2<T> *)vis,
+                                                              o.perm, w.partials, w.ctl);
+        }
+        return check_launch();
+    }
     c2<T> *XT = (c2<T> *)w.xt;
     rc = dispatch_fft<T>(g.N, src, profile, sw, g, XT, s);
     if (rc) return rc;
-    const SampleArgs sa = make_sample(g, o.M, dxy, PA, dRA, dDec, inc);
-    const dim3 grid((unsigned)sample_blocks(o.M));
     if (chi2) {
-        TimedLaunch tl("k_sample_chi2", s);
-        k_sample<T, true><<<grid, SAMPLE_NT, 0, s>>>(XT, g, sa, o.u, o.v, o.re, o.im, o.w, nullptr,
-                                                     w.partials, w.ctl, chi2);
+        {
+            TimedLaunch tl("k_sample_chi2", s);
+            k_sample<T, true><<<grid, SAMPLE_NT, 0, s>>>(XT, g, sa, o.u, o.v, o.re, o.im, o.w,
+                                                         nullptr, nullptr, w.partials, w.ctl);
+        }
+        rc = check_launch();
+        if (rc) return rc;
+        TimedLaunch tl("k_reduce", s);
+        k_reduce<<<1, SAMPLE_NT, 0, s>>>(w.partials, (int)grid.x, chi2);
     } else {
         TimedLaunch tl("k_sample_vis", s);
         k_sample<T, false><<<grid, SAMPLE_NT, 0, s>>>(XT, g, sa, o.u, o.v, nullptr, nullptr,
-                                                      nullptr, (c2<T> *)vis, w.partials, w.ctl,
-                                                      nullptr);
+                                                      nullptr, (c2<T> *)vis, o.perm, w.partials,
+                                                      w.ctl);
     }
     return check_launch();
 }
@@ -359,8 +436,9 @@ struct gal_dataset {
     int device;
     int64_t M;
     double rho_max;
-    void *buf;      // one allocation: u, v, re, im, w
+    void *buf;      // one allocation: u, v, re, im, w, perm (locality order)
     void *u, *v, *re, *im, *w;
+    int32_t *perm;  // perm[k] = registration index of stored point k
 };
 
 // The definitions below take their C linkage from the declarations in the
@@ -448,7 +526,7 @@ static int image_call(const T *image, int Nxy, double dxy, const T *u, const T *
     int rc = check_image_scalars(Nxy, dxy, PA, dRA, dDec, inc);
     if (rc) return rc;
     const Geom g = geom_full(Nxy);
-    return run_path<T>(image, false, SweepArgs{}, g, dxy, Obs<T>{u, v, re, im, w, M}, PA, dRA, dDec,
+    return run_path<T>(image, false, SweepArgs{}, g, dxy, Obs<T>{u, v, re, im, w, M, nullptr}, PA, dRA, dDec,
                        inc, vis, chi2, ws, ws_bytes_, (hipStream_t)stream);
 }
 
@@ -467,7 +545,7 @@ static int profile_call(const T *I, int Nr, double Rmin, double dR, int Nxy, dou
     if (rc) return rc;
     const Geom g = geom_full(Nxy);
     return run_path<T>(I, true, make_sweep(Nr, Rmin, dR, dxy, inc), g, dxy,
-                       Obs<T>{u, v, re, im, w, M}, PA, dRA, dDec, 0.0, vis, chi2, ws, ws_bytes_,
+                       Obs<T>{u, v, re, im, w, M, nullptr}, PA, dRA, dDec, 0.0, vis, chi2, ws, ws_bytes_,
                        (hipStream_t)stream);
 }
 
@@ -587,7 +665,7 @@ static int sample_spectrum_impl(const T *spec, int Nxy, double dxy, const T *u, 
     {
         TimedLaunch tl("k_sample_vis", s);
         k_sample<T, false><<<(unsigned)sample_blocks(M), SAMPLE_NT, 0, s>>>(
-            XT, g, sa, u, v, nullptr, nullptr, nullptr, (c2<T> *)vis, w.partials, w.ctl, nullptr);
+            XT, g, sa, u, v, nullptr, nullptr, nullptr, (c2<T> *)vis, nullptr, w.partials, w.ctl);
     }
     return check_launch();
 }
@@ -605,66 +683,105 @@ int gal_sample_spectrum_f(const float *spec, int Nxy, double dxy, const float *u
 }
 
 // ---- datasets -------------------------------------------------------------
+// Morton (Z-order) key of a uv point on a 2^16 x 2^16 grid over
+// [-rho_max, rho_max]^2: neighbouring keys are neighbouring points, and a
+// rotation by PA keeps neighbours together, so a wavefront of consecutive
+// points gathers from a few cache lines of the spectrum.
+static uint32_t spread16(uint32_t x) {
+    x &= 0xFFFFu;
+    x = (x | (x << 8)) & 0x00FF00FFu;
+    x = (x | (x << 4)) & 0x0F0F0F0Fu;
+    x = (x | (x << 2)) & 0x33333333u;
+    x = (x | (x << 1)) & 0x55555555u;
+    return x;
+}
+
+static uint32_t morton_key(double u, double v, double rho_max) {
+    const double sc = rho_max > 0.0 ? 32767.5 / rho_max : 0.0;
+    double x = (u * sc) + 32767.5, y = (v * sc) + 32767.5;
+    x = x < 0.0 ? 0.0 : (x > 65535.0 ? 65535.0 : x);
+    y = y < 0.0 ? 0.0 : (y > 65535.0 ? 65535.0 : y);
+    return spread16((uint32_t)x) | (spread16((uint32_t)y) << 1);
+}
+
 template <typename T>
 static int dataset_create(const T *u, const T *v, const T *re, const T *im, const T *w, int64_t M,
                           void *stream, gal_dataset **out) {
     if (!out) return fail(GAL_ERR_NULL, "NULL out");
     *out = nullptr;
     if (M < 0) return fail(GAL_ERR_SIZE, "M < 0");
+    if (M > (int64_t)0x7fffffff) return fail(GAL_ERR_SIZE, "M above 2^31 - 1");
     if (M > 0 && (!u || !v)) return fail(GAL_ERR_NULL, "NULL u or v");
     const bool has_obs = re && im && w;
     if ((re || im || w) && !has_obs) return fail(GAL_ERR_NULL, "re, im, w: give all or none");
     int rc = ensure_init();
     if (rc) return rc;
     hipStream_t s = (hipStream_t)stream;
+    const int n_cols = has_obs ? 5 : 2;
+    const T *src[5] = {u, v, re, im, w};
+    // observations to the host, in registration order
+    std::vector<std::vector<T>> h(n_cols, std::vector<T>((size_t)M));
+    for (int c = 0; c < n_cols && M > 0; ++c)
+        GAL_HIP(hipMemcpyAsync(h[c].data(), src[c], (size_t)M * sizeof(T), hipMemcpyDeviceToHost, s));
+    GAL_HIP(hipStreamSynchronize(s));
+    double r2max = 0.0;
+    for (int64_t k = 0; k < M; ++k) {
+        const double uu = h[0][k], vv = h[1][k];
+        const double r2 = uu * uu + vv * vv;
+        if (!std::isfinite(r2)) return fail(GAL_ERR_SCALAR, "non-finite uv coordinate at %lld",
+                                            (long long)k);
+        r2max = r2 > r2max ? r2 : r2max;
+    }
+    const double rho_max = std::sqrt(r2max);
+    // locality order
+    std::vector<std::pair<uint32_t, int32_t>> key((size_t)M);
+    for (int64_t k = 0; k < M; ++k)
+        key[k] = {morton_key((double)h[0][k], (double)h[1][k], rho_max), (int32_t)k};
+    std::stable_sort(key.begin(), key.end(),
+                     [](const std::pair<uint32_t, int32_t> &a, const std::pair<uint32_t, int32_t> &b) {
+                         return a.first < b.first;
+                     });
+    std::vector<int32_t> perm((size_t)M);
+    for (int64_t k = 0; k < M; ++k) perm[k] = key[k].second;
+    std::vector<T> tmp((size_t)M);
+    for (int c = 0; c < n_cols; ++c) {
+        for (int64_t k = 0; k < M; ++k) tmp[k] = h[c][perm[k]];
+        h[c].swap(tmp);
+    }
+
     gal_dataset *ds = new gal_dataset();
     ds->precision = (int)sizeof(T);
     GAL_HIP(hipGetDevice(&ds->device));
     ds->M = M;
+    ds->rho_max = rho_max;
     const size_t col = align256((size_t)(M > 0 ? M : 1) * sizeof(T));
-    const size_t n_cols = has_obs ? 5 : 2;
-    if (hipMalloc(&ds->buf, col * n_cols + 256) != hipSuccess) {
+    const size_t pcol = align256((size_t)(M > 0 ? M : 1) * sizeof(int32_t));
+    if (hipMalloc(&ds->buf, col * n_cols + pcol) != hipSuccess) {
         delete ds;
         return fail(GAL_ERR_WORKSPACE, "out of device memory for a dataset of %lld points",
                     (long long)M);
     }
     char *p = (char *)ds->buf;
-    ds->u = p;
-    ds->v = p + col;
-    ds->re = has_obs ? p + 2 * col : nullptr;
-    ds->im = has_obs ? p + 3 * col : nullptr;
-    ds->w = has_obs ? p + 4 * col : nullptr;
-    unsigned long long *r2 = (unsigned long long *)(p + col * n_cols);
-    auto cleanup = [&](int code) {
+    void *dst[5] = {p, p + col, p + 2 * col, p + 3 * col, p + 4 * col};
+    ds->u = dst[0];
+    ds->v = dst[1];
+    ds->re = has_obs ? dst[2] : nullptr;
+    ds->im = has_obs ? dst[3] : nullptr;
+    ds->w = has_obs ? dst[4] : nullptr;
+    ds->perm = (int32_t *)(p + col * n_cols);
+    bool ok = true;
+    for (int c = 0; c < n_cols && M > 0; ++c)
+        ok = ok && hipMemcpyAsync(dst[c], h[c].data(), (size_t)M * sizeof(T),
+                                  hipMemcpyHostToDevice, s) == hipSuccess;
+    if (M > 0)
+        ok = ok && hipMemcpyAsync(ds->perm, perm.data(), (size_t)M * sizeof(int32_t),
+                                  hipMemcpyHostToDevice, s) == hipSuccess;
+    ok = ok && hipStreamSynchronize(s) == hipSuccess;
+    if (!ok) {
         (void)hipFree(ds->buf);
         delete ds;
-        return code;
-    };
-    const size_t bytes = (size_t)M * sizeof(T);
-    if (M > 0) {
-        if (hipMemcpyAsync(ds->u, u, bytes, hipMemcpyDeviceToDevice, s) != hipSuccess ||
-            hipMemcpyAsync(ds->v, v, bytes, hipMemcpyDeviceToDevice, s) != hipSuccess)
-            return cleanup(fail(GAL_ERR_HIP, "dataset copy failed"));
-        if (has_obs &&
-            (hipMemcpyAsync(ds->re, re, bytes, hipMemcpyDeviceToDevice, s) != hipSuccess ||
-             hipMemcpyAsync(ds->im, im, bytes, hipMemcpyDeviceToDevice, s) != hipSuccess ||
-             hipMemcpyAsync(ds->w, w, bytes, hipMemcpyDeviceToDevice, s) != hipSuccess))
-            return cleanup(fail(GAL_ERR_HIP, "dataset copy failed"));
+        return fail(GAL_ERR_HIP, "dataset upload failed");
     }
-    if (hipMemsetAsync(r2, 0, sizeof(unsigned long long), s) != hipSuccess)
-        return cleanup(fail(GAL_ERR_HIP, "dataset set-up failed"));
-    if (M > 0) {
-        k_rho2max<T><<<256, 256, 0, s>>>((const T *)ds->u, (const T *)ds->v, M, r2);
-        if (hipGetLastError() != hipSuccess) return cleanup(fail(GAL_ERR_HIP, "rho_max kernel"));
-    }
-    unsigned long long bits = 0;
-    if (hipMemcpyAsync(&bits, r2, sizeof(bits), hipMemcpyDeviceToHost, s) != hipSuccess ||
-        hipStreamSynchronize(s) != hipSuccess)
-        return cleanup(fail(GAL_ERR_HIP, "dataset set-up failed"));
-    double r2max;
-    std::memcpy(&r2max, &bits, sizeof(r2max));
-    if (!std::isfinite(r2max)) return cleanup(fail(GAL_ERR_SCALAR, "non-finite uv coordinates"));
-    ds->rho_max = std::sqrt(r2max);
     *out = ds;
     return GAL_OK;
 }
@@ -696,6 +813,16 @@ int gal_dataset_info(const gal_dataset *ds, int64_t *M, double *rho_max, int *pr
     return GAL_OK;
 }
 
+int gal_dataset_geometry(const gal_dataset *ds, int Nxy, double dxy, int *Q, int *P) {
+    if (!ds || !Q || !P) return fail(GAL_ERR_NULL, "NULL argument");
+    int rc = check_image_scalars(Nxy, dxy, 0.0, 0.0, 0.0, 0.0);
+    if (rc) return rc;
+    const Geom g = geom_pruned(Nxy, dxy, ds->rho_max);
+    *Q = g.Q;
+    *P = g.P;
+    return GAL_OK;
+}
+
 template <typename T>
 static int ds_call(const gal_dataset *ds, const T *src, bool profile, int Nr, double Rmin,
                    double dR, int Nxy, double dxy, double inc, double PA, double dRA, double dDec,
@@ -719,7 +846,7 @@ static int ds_call(const gal_dataset *ds, const T *src, bool profile, int Nr, do
                     ds->rho_max, ((double)(Nxy / 2) - 1.0) * du, Nxy, dxy);
     const Geom g = geom_pruned(Nxy, dxy, ds->rho_max);
     const Obs<T> o{(const T *)ds->u, (const T *)ds->v, (const T *)ds->re, (const T *)ds->im,
-                   (const T *)ds->w, ds->M};
+                   (const T *)ds->w, ds->M, ds->perm};
     const SweepArgs sw = profile ? make_sweep(Nr, Rmin, dR, dxy, inc) : SweepArgs{};
     return run_path<T>(src, profile, sw, g, dxy, o, PA, dRA, dDec, profile ? 0.0 : inc, vis, chi2,
                        ws, ws_bytes_, (hipStream_t)stream);

@@ -7,8 +7,8 @@
 //             the sign (-1)^p, written back in place as the rows
 //             p~ in [-P, P] that the uv points can reach.
 //   k_sample  uv rotation, mirror, bilinear gather, deprojection, phase
-//             shift; writes V or reduces the weighted chi^2 (last-block
-//             deterministic reduction).
+//             shift; writes V or per-block partial sums of the weighted
+//             chi^2, which k_reduce adds in a fixed order.
 //
 // Shifting the image origin to pixel (N/2, N/2) multiplies the unshifted
 // DFT F[p][q] by exp(i pi (p + q)) = (-1)^(p+q) (Sec. 4 shift -> FFT -> shift),
@@ -164,6 +164,105 @@ __global__ __launch_bounds__(Cfg::NT) void k_cols(Geom g, c2<T> *__restrict__ XT
 }
 
 // ---------------------------------------------------------------------------
+// Swept profiles.  The swept image is even about its centre pixel in both
+// axes: x_c = (N/2 - c) dxy and x_{N-c} = -x_c exactly, and rho depends on
+// x^2 and y^2 only, so f[r][c] = f[r][N-c] and f[r][c] = f[N-r][c] bit for
+// bit.  In DFT terms (indices mod N about the centre) the image is even, its
+// shifted half spectrum G is real and even in p, and rows r and N - r have
+// the same transform.  The two passes below use that: rows r in [0, N/2]
+// only, two at a time as the real and imaginary parts of one length-N
+// complex FFT (both transforms are real, so Re and Im separate them), a real
+// intermediate, columns two at a time the same way, and a real spectrum
+// stored for p in [0, P].  The samples equal those of the general path up
+// to rounding.
+//
+// Row pass: pair m holds rows 2m and 2m+1; output XR[q * CS + r] (real,
+// shift sign (-1)^q) for r in [0, N/2], q in [0, Qe) (Qe = Q rounded up to
+// even so that the column pass can pair columns).
+template <typename T, typename Cfg>
+__global__ __launch_bounds__(Cfg::NT) void k_rows_sym(const T *__restrict__ I, SweepArgs sw,
+                                                      Geom g, int Qe, T *__restrict__ XR) {
+    constexpr int L = Cfg::L, B = Cfg::B, NT = Cfg::NT, E = Cfg::E;
+    constexpr int N = L;
+    constexpr int R0 = pass_radix(L, 1, Cfg::RMAX);
+    constexpr int LR = L / R0;
+    __shared__ c2<T> lds[B * Cfg::LS];
+    const int tid = threadIdx.x;
+    const int m0 = xcd_remap(blockIdx.x, gridDim.x) * B;
+
+    c2<T> v[E];
+#pragma unroll
+    for (int i = 0; i < E / R0; ++i) {
+        const int gi = tid + i * NT;
+        const int b = gi / LR, j = gi % LR;
+        const int r = 2 * (m0 + b);  // rows r, r + 1 (r + 1 <= N/2 + 1 < N)
+#pragma unroll
+        for (int t = 0; t < R0; ++t) {
+            const int n = j + t * LR;
+            v[i * R0 + t].x = (T)sweep_pixel(I, N, r, n, sw);
+            v[i * R0 + t].y = (T)sweep_pixel(I, N, r + 1, n, sw);
+        }
+    }
+    fft_passes<Cfg, 1>(v, lds, twiddles<T>(), tid);
+
+    constexpr int RB = 2 * B;  // rows per block
+    for (int idx = tid; idx < Qe * RB; idx += NT) {
+        const int q = idx / RB, rr = idx % RB;
+        const int r = 2 * m0 + rr;
+        if (r > N / 2) continue;
+        const c2<T> z = lds[(rr >> 1) * Cfg::LS + q];
+        T x = (rr & 1) ? z.y : z.x;
+        if (q & 1) x = -x;
+        XR[(size_t)q * g.CS + r] = x;
+    }
+}
+
+// Column pass of a swept profile, in place: pair of columns (2m, 2m+1),
+// input over r in [0, N) from the stored half r' = min(r, N - r); output
+// SR[q * CS + p] = (-1)^p G[p][q] for p in [0, P].
+template <typename T, typename Cfg>
+__global__ __launch_bounds__(Cfg::NT) void k_cols_sym(Geom g, int Qe, T *__restrict__ XR) {
+    constexpr int L = Cfg::L, B = Cfg::B, NT = Cfg::NT, E = Cfg::E;
+    constexpr int N = L;
+    constexpr int R0 = pass_radix(L, 1, Cfg::RMAX);
+    constexpr int LR = L / R0;
+    __shared__ c2<T> lds[B * Cfg::LS];
+    const int tid = threadIdx.x;
+    const int m0 = blockIdx.x * B;
+
+    c2<T> v[E];
+#pragma unroll
+    for (int i = 0; i < E / R0; ++i) {
+        const int gi = tid + i * NT;
+        const int b = gi / LR, j = gi % LR;
+        const int q = 2 * (m0 + b);
+#pragma unroll
+        for (int t = 0; t < R0; ++t) {
+            const int n = j + t * LR;
+            const int rr = n <= N / 2 ? n : N - n;
+            if (q < Qe) {
+                v[i * R0 + t].x = XR[(size_t)q * g.CS + rr];
+                v[i * R0 + t].y = XR[(size_t)(q + 1) * g.CS + rr];
+            } else {
+                v[i * R0 + t] = c2<T>{T(0), T(0)};
+            }
+        }
+    }
+    fft_passes<Cfg, 1>(v, lds, twiddles<T>(), tid);
+
+    const int NP = g.P + 1;
+    for (int idx = tid; idx < NP * 2 * B; idx += NT) {
+        const int cb = idx / NP, p = idx % NP;
+        const int q = 2 * m0 + cb;
+        if (q >= Qe) continue;
+        const c2<T> z = lds[(cb >> 1) * Cfg::LS + p];
+        T x = (cb & 1) ? z.y : z.x;
+        if (p & 1) x = -x;
+        XR[(size_t)q * g.CS + p] = x;
+    }
+}
+
+// ---------------------------------------------------------------------------
 // Sampling (Sec. 3.3, Sec. 3.4, App. D) and the chi^2 reduction (Sec. 3.1).
 struct SampleArgs {
     int64_t M;
@@ -177,47 +276,64 @@ constexpr int SAMPLE_NT = 256;
 constexpr int SAMPLE_PPT = 4;
 
 struct Control {
-    unsigned int counter;  // blocks done (reset by the last block)
+    unsigned int reserved;
     int flag;              // 1 once a uv point fell outside the spectrum
 };
 
+// Bilinear sample of the stored spectrum at one uv point: rotation by PA,
+// deprojection, mirror of u' < 0 (conjugate), 4-node interpolation, flux
+// factor cos(inc), phase exp(+2 pi i (u dRA + v dDec)).
 template <typename T>
-__device__ __forceinline__ void sample_point(const c2<T> *__restrict__ S, const Geom &g,
-                                             const SampleArgs &a, double u, double v,
-                                             double &Vre, double &Vim, bool &ok) {
+struct Stencil {
+    const c2<T> *c0;   // node (q, i); (q, i+1) follows, (q+1, .) is CS further
+    double s, t;
+    bool mirror, ok;
+};
+
+template <typename T>
+__device__ __forceinline__ Stencil<T> locate(const c2<T> *__restrict__ S, const Geom &g,
+                                             const SampleArgs &a, double u, double v) {
+    Stencil<T> st;
     double ur = u * a.cpa - v * a.spa;
     double vr = u * a.spa + v * a.cpa;
     ur *= a.cinc;
-    const bool mirror = ur < 0.0;
-    if (mirror) {
+    st.mirror = ur < 0.0;
+    if (st.mirror) {
         ur = -ur;
         vr = -vr;
     }
     const double fu = ur * a.inv_du, fv = vr * a.inv_du;
     const double j0f = floor(fu), i0f = floor(fv);
-    ok = (j0f >= 0.0) && (j0f <= (double)a.jmax) && (i0f >= (double)a.imin) &&
-         (i0f <= (double)a.imax);
-    if (!ok) {
+    st.ok = (j0f >= 0.0) && (j0f <= (double)a.jmax) && (i0f >= (double)a.imin) &&
+            (i0f <= (double)a.imax);
+    st.s = fu - j0f;
+    st.t = fv - i0f;
+    const int q = st.ok ? (int)j0f : 0;
+    const int i = st.ok ? (int)i0f + g.P : g.P;
+    st.c0 = S + (size_t)q * g.CS + i;
+    return st;
+}
+
+template <typename T>
+__device__ __forceinline__ void finish(const Stencil<T> &st, c2<T> a00, c2<T> a10, c2<T> a01,
+                                       c2<T> a11, const SampleArgs &a, double u, double v,
+                                       double &Vre, double &Vim) {
+    if (!st.ok) {
         Vre = __builtin_nan("");
         Vim = __builtin_nan("");
         return;
     }
-    const double s = fu - j0f, t = fv - i0f;
-    const int q = (int)j0f;
-    const int i = (int)i0f + g.P;
-    const c2<T> *c0 = S + (size_t)q * g.CS + i;
-    const c2<T> *c1 = c0 + g.CS;
-    const c2<T> a00 = c0[0], a10 = c0[1], a01 = c1[0], a11 = c1[1];
+    const double s = st.s, t = st.t;
     const double w00 = (1.0 - t) * (1.0 - s), w01 = (1.0 - t) * s;
     const double w10 = t * (1.0 - s), w11 = t * s;
     double br = w00 * (double)a00.x + w01 * (double)a01.x + w10 * (double)a10.x + w11 * (double)a11.x;
     double bi = w00 * (double)a00.y + w01 * (double)a01.y + w10 * (double)a10.y + w11 * (double)a11.y;
-    if (mirror) bi = -bi;
+    if (st.mirror) bi = -bi;
     br *= a.cinc;
     bi *= a.cinc;
-    const double theta = 6.283185307179586476925286766559 * (u * a.dRA + v * a.dDec);
+    // exp(i theta), theta = 2 pi (u dRA + v dDec) = pi * x
     double sn, cs;
-    sincos(theta, &sn, &cs);
+    sincospi(2.0 * (u * a.dRA + v * a.dDec), &sn, &cs);
     Vre = br * cs - bi * sn;
     Vim = br * sn + bi * cs;
 }
@@ -242,56 +358,172 @@ __device__ __forceinline__ double block_sum(double x, double *red) {
     return s;
 }
 
+// Sampling of the real, p-even spectrum of a swept profile: node (q, p~)
+// holds SR[q * CS + |p~|], so the two rows of a stencil are the adjacent
+// pair starting at min(|p~0|, |p~0 + 1|).
+template <typename T>
+struct StencilR {
+    const T *c0;       // SR + q * CS + lo; row lo and lo + 1
+    double s, t;
+    bool swap, ok;     // swap: node p~0 is at lo + 1 (p~0 < 0)
+};
+
+template <typename T>
+__device__ __forceinline__ StencilR<T> locate_r(const T *__restrict__ S, const Geom &g,
+                                                const SampleArgs &a, double u, double v) {
+    StencilR<T> st;
+    double ur = u * a.cpa - v * a.spa;
+    double vr = u * a.spa + v * a.cpa;
+    ur *= a.cinc;
+    if (ur < 0.0) {
+        ur = -ur;
+        vr = -vr;
+    }
+    const double fu = ur * a.inv_du, fv = vr * a.inv_du;
+    const double j0f = floor(fu), i0f = floor(fv);
+    st.ok = (j0f >= 0.0) && (j0f <= (double)a.jmax) && (i0f >= (double)a.imin) &&
+            (i0f <= (double)a.imax);
+    st.s = fu - j0f;
+    st.t = fv - i0f;
+    const int q = st.ok ? (int)j0f : 0;
+    const int p0 = st.ok ? (int)i0f : 0;
+    st.swap = p0 < 0;
+    const int lo = st.swap ? -p0 - 1 : p0;
+    st.c0 = S + (size_t)q * g.CS + lo;
+    return st;
+}
+
 template <typename T, bool CHI2>
-__global__ __launch_bounds__(SAMPLE_NT) void k_sample(
-    const c2<T> *__restrict__ S, Geom g, SampleArgs a, const T *__restrict__ u,
+__global__ __launch_bounds__(SAMPLE_NT) void k_sample_sym(
+    const T *__restrict__ S, Geom g, SampleArgs a, const T *__restrict__ u,
     const T *__restrict__ v, const T *__restrict__ re, const T *__restrict__ im,
-    const T *__restrict__ w, c2<T> *__restrict__ vis, double *__restrict__ partials,
-    Control *ctl, double *__restrict__ chi2_out) {
+    const T *__restrict__ w, c2<T> *__restrict__ vis, const int32_t *__restrict__ perm,
+    double *__restrict__ partials, Control *ctl) {
+    constexpr int PPT = SAMPLE_PPT;
     __shared__ double red[SAMPLE_NT / 64];
-    __shared__ int last;
     const int blk = xcd_remap(blockIdx.x, gridDim.x);
-    const int64_t base = (int64_t)blk * (SAMPLE_NT * SAMPLE_PPT) + threadIdx.x;
+    const int64_t base = (int64_t)blk * (SAMPLE_NT * PPT) + threadIdx.x;
+    double uu[PPT], vv[PPT];
+#pragma unroll
+    for (int p = 0; p < PPT; ++p) {
+        const int64_t k = base + p * SAMPLE_NT;
+        const bool in = k < a.M;
+        uu[p] = in ? (double)u[k] : 0.0;
+        vv[p] = in ? (double)v[k] : 0.0;
+    }
+    StencilR<T> st[PPT];
+    c2<T> lo0[PPT], lo1[PPT];
+#pragma unroll
+    for (int p = 0; p < PPT; ++p) {
+        st[p] = locate_r<T>(S, g, a, uu[p], vv[p]);
+        lo0[p] = c2<T>{st[p].c0[0], st[p].c0[1]};
+        lo1[p] = c2<T>{st[p].c0[g.CS], st[p].c0[g.CS + 1]};
+    }
     double acc = 0.0;
     bool bad = false;
 #pragma unroll
-    for (int p = 0; p < SAMPLE_PPT; ++p) {
+    for (int p = 0; p < PPT; ++p) {
         const int64_t k = base + p * SAMPLE_NT;
         if (k < a.M) {
             double Vre, Vim;
-            bool ok;
-            sample_point<T>(S, g, a, (double)u[k], (double)v[k], Vre, Vim, ok);
-            bad |= !ok;
+            if (!st[p].ok) {
+                Vre = __builtin_nan("");
+                Vim = __builtin_nan("");
+                bad = true;
+            } else {
+                // a(q, p~0), a(q, p~0+1), a(q+1, p~0), a(q+1, p~0+1)
+                const double a00 = st[p].swap ? lo0[p].y : lo0[p].x;
+                const double a10 = st[p].swap ? lo0[p].x : lo0[p].y;
+                const double a01 = st[p].swap ? lo1[p].y : lo1[p].x;
+                const double a11 = st[p].swap ? lo1[p].x : lo1[p].y;
+                const double s = st[p].s, t = st[p].t;
+                const double b = (1.0 - t) * ((1.0 - s) * a00 + s * a01) +
+                                 t * ((1.0 - s) * a10 + s * a11);
+                double sn, cs;
+                sincospi(2.0 * (uu[p] * a.dRA + vv[p] * a.dDec), &sn, &cs);
+                Vre = a.cinc * b * cs;
+                Vim = a.cinc * b * sn;
+            }
             if constexpr (CHI2) {
                 const double dr = Vre - (double)re[k];
                 const double di = Vim - (double)im[k];
                 acc += (double)w[k] * (dr * dr + di * di);
             } else {
-                vis[k] = c2<T>{(T)Vre, (T)Vim};
+                vis[perm ? (int64_t)perm[k] : k] = c2<T>{(T)Vre, (T)Vim};
             }
         }
     }
     if (bad) ctl->flag = 1;
     if constexpr (CHI2) {
         const double bs = block_sum(acc, red);
-        if (threadIdx.x == 0) {
-            partials[blk] = bs;
-            __threadfence();
-            const unsigned int ticket = atomicAdd(&ctl->counter, 1u);
-            last = (ticket == gridDim.x - 1);
-        }
-        __syncthreads();
-        if (last) {
-            __threadfence();
-            double s = 0.0;
-            for (int k = threadIdx.x; k < (int)gridDim.x; k += SAMPLE_NT) s += partials[k];
-            const double tot = block_sum(s, red);
-            if (threadIdx.x == 0) {
-                *chi2_out = tot;
-                ctl->counter = 0u;
+        if (threadIdx.x == 0) partials[blk] = bs;
+    }
+}
+
+// Each thread takes SAMPLE_PPT points strided by the block size: all loads
+// are issued before the arithmetic.  CHI2: one partial sum per block,
+// reduced by k_reduce in a fixed order (bitwise repeatable, no fences).
+template <typename T, bool CHI2>
+__global__ __launch_bounds__(SAMPLE_NT) void k_sample(
+    const c2<T> *__restrict__ S, Geom g, SampleArgs a, const T *__restrict__ u,
+    const T *__restrict__ v, const T *__restrict__ re, const T *__restrict__ im,
+    const T *__restrict__ w, c2<T> *__restrict__ vis, const int32_t *__restrict__ perm,
+    double *__restrict__ partials, Control *ctl) {
+    constexpr int PPT = SAMPLE_PPT;
+    __shared__ double red[SAMPLE_NT / 64];
+    const int blk = xcd_remap(blockIdx.x, gridDim.x);
+    const int64_t base = (int64_t)blk * (SAMPLE_NT * PPT) + threadIdx.x;
+    double uu[PPT], vv[PPT];
+#pragma unroll
+    for (int p = 0; p < PPT; ++p) {
+        const int64_t k = base + p * SAMPLE_NT;
+        const bool in = k < a.M;
+        uu[p] = in ? (double)u[k] : 0.0;
+        vv[p] = in ? (double)v[k] : 0.0;
+    }
+    Stencil<T> st[PPT];
+    c2<T> n00[PPT], n10[PPT], n01[PPT], n11[PPT];
+#pragma unroll
+    for (int p = 0; p < PPT; ++p) {
+        st[p] = locate<T>(S, g, a, uu[p], vv[p]);
+        n00[p] = st[p].c0[0];
+        n10[p] = st[p].c0[1];
+        n01[p] = st[p].c0[g.CS];
+        n11[p] = st[p].c0[g.CS + 1];
+    }
+    double acc = 0.0;
+    bool bad = false;
+#pragma unroll
+    for (int p = 0; p < PPT; ++p) {
+        const int64_t k = base + p * SAMPLE_NT;
+        if (k < a.M) {
+            double Vre, Vim;
+            finish<T>(st[p], n00[p], n10[p], n01[p], n11[p], a, uu[p], vv[p], Vre, Vim);
+            bad |= !st[p].ok;
+            if constexpr (CHI2) {
+                const double dr = Vre - (double)re[k];
+                const double di = Vim - (double)im[k];
+                acc += (double)w[k] * (dr * dr + di * di);
+            } else {
+                vis[perm ? (int64_t)perm[k] : k] = c2<T>{(T)Vre, (T)Vim};
             }
         }
     }
+    if (bad) ctl->flag = 1;
+    if constexpr (CHI2) {
+        const double bs = block_sum(acc, red);
+        if (threadIdx.x == 0) partials[blk] = bs;
+    }
+}
+
+// Final chi^2: one block sums the per-block partials in a fixed order.
+__global__ __launch_bounds__(SAMPLE_NT) void k_reduce(const double *__restrict__ partials, int n,
+                                                      double *__restrict__ out) {
+    __shared__ double red[SAMPLE_NT / 64];
+    double s = 0.0;
+    for (int k = threadIdx.x; k < n; k += SAMPLE_NT) s += partials[k];
+    const double tot = block_sum(s, red);
+    if (threadIdx.x == 0) *out = tot;
 }
 
 // ---------------------------------------------------------------------------
@@ -330,28 +562,9 @@ __global__ __launch_bounds__(256) void k_spec_in(const c2<T> *__restrict__ G, Ge
     S[(size_t)q * g.CS + i] = G[(size_t)p * NQ + q];
 }
 
-// max of u^2 + v^2 (non-negative doubles order like their bit patterns)
-template <typename T>
-__global__ __launch_bounds__(256) void k_rho2max(const T *__restrict__ u, const T *__restrict__ v,
-                                                 int64_t M, unsigned long long *out) {
-    double m = 0.0;
-    for (int64_t k = (int64_t)blockIdx.x * 256 + threadIdx.x; k < M;
-         k += (int64_t)gridDim.x * 256) {
-        const double uu = u[k], vv = v[k];
-        const double r2 = uu * uu + vv * vv;
-        m = r2 > m ? r2 : m;
-    }
-#pragma unroll
-    for (int o = 32; o >= 1; o >>= 1) {
-        const double other = __shfl_xor(m, o, 64);
-        m = other > m ? other : m;
-    }
-    if ((threadIdx.x & 63) == 0) atomicMax(out, (unsigned long long)__double_as_longlong(m));
-}
-
 __global__ void k_ctrl_zero(Control *ctl) {
     if (threadIdx.x == 0) {
-        ctl->counter = 0u;
+        ctl->reserved = 0u;
         ctl->flag = 0;
     }
 }
