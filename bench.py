@@ -69,6 +69,9 @@ def main():
     ap.add_argument("--warmup", type=int, default=50)
     ap.add_argument("--latency-samples", type=int, default=300)
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--calib-copy", action="store_true",
+                    help="also run one 256 MiB device-to-device copy (a known-size kernel for "
+                         "scaling HBM byte counters)")
     ap.add_argument("--kind", choices=["profile", "image"], default="profile",
                     help="profile: chi2Profile (default); image: chi2Image of the swept image")
     args = ap.parse_args()
@@ -99,12 +102,23 @@ def main():
     w = f64(case.w)
     ds = gal.Dataset(u, v, re, im, w)
     Q, P = ds.geometry(N, case.dxy)
+    # FFT schedules for this image size and the reachable part of the spectrum
+    frac = ds.rho_max * N * case.dxy / (N / 2 - 1)
+    tune_times = {}
+    tuned = gal.autotune(N, torch.float64, frac, times=tune_times)
     out = torch.empty((), dtype=torch.float64, device=dev)
     if args.kind == "profile":
         call = lambda: ds.chi2Profile(I, case.Rmin, case.dR, N, case.dxy, out=out, **geo)
     else:
         img = gal.sweep(I, case.Rmin, case.dR, N, case.dxy, case.inc)
         call = lambda: ds.chi2Image(img, case.dxy, case.PA, case.dRA, case.dDec, out=out)
+
+    if args.calib_copy:
+        a = torch.ones(32 * 1024 * 1024, dtype=torch.float64, device=dev)
+        b = torch.empty_like(a)
+        b.copy_(a)
+        torch.cuda.synchronize()
+        del a, b
 
     for _ in range(args.warmup):
         call()
@@ -190,7 +204,7 @@ def main():
                                ", M=1e6 uv, FP64, plain one-at-a-time calls on a "
                                "device-resident dataset",
                    "Nxy": N, "Nr": int(Nr), "M": M, "spectrum_cols_Q": Q, "spectrum_rows_P": P,
-                   "chi2": chi2_val},
+                   "chi2": chi2_val, "fft_variants": tuned, "fft_variant_ms": tune_times},
         "latency_ms": {"p50": round(float(np.percentile(lat, 50)), 4),
                        "p99": round(float(np.percentile(lat, 99)), 4)},
         "kernels": {k: {kk: (round(vv, 3) if isinstance(vv, float) else vv)

@@ -211,6 +211,24 @@ int gal_sampleProfile_ds_f(const gal_dataset *ds, const float *I, int Nr, double
                            double dRA, double dDec, float *vis, void *ws, size_t ws_bytes,
                            void *stream);
 
+/* ---- FFT schedule autotuning -------------------------------------------
+ * Every FFT pass exists in NVAR = 3 compiled variants that differ in the
+ * values each thread holds (16, 8 or 4: more threads per transform, more
+ * waves in flight, more radix passes).  gal_autotune_* times all variants of
+ * the four passes (rows of an image, columns, rows and columns of a swept
+ * profile) for one image size on the current device -- with frac the part of
+ * the half spectrum transformed (rho_max / ((Nxy/2 - 1) du), 1 = all) -- and
+ * keeps the fastest for later calls in this process; chosen[4] receives the
+ * choice and times_ms[4 * 3] (nullable) the average launch time of every
+ * variant, -1 where a size has fewer variants.  It allocates and frees
+ * scratch memory and synchronises `stream`.
+ * gal_tune_get / gal_tune_set read and install choices (precision 8 or 4,
+ * variant -1 = built-in default), e.g. from a cache file. */
+int gal_autotune_d(int Nxy, double frac, void *stream, int *chosen, double *times_ms);
+int gal_autotune_f(int Nxy, double frac, void *stream, int *chosen, double *times_ms);
+int gal_tune_get(int precision, int Nxy, int *chosen);
+int gal_tune_set(int precision, int Nxy, const int *chosen);
+
 /* ---- per-kernel timing (HIP events on the launch stream) ----------------
  * When enabled, every kernel launch of the library is bracketed by HIP events
  * recorded on its stream.  gal_timing_read synchronises, and for each kernel

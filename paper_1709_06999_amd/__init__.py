@@ -21,6 +21,8 @@ Angles in radians, uv in wavelengths.  chi2 results stay on the device as
 from __future__ import annotations
 
 import ctypes
+import json
+import os
 
 import torch
 
@@ -30,7 +32,7 @@ from ._native import GalarioError, check
 __all__ = [
     "sweep", "sampleImage", "sampleProfile", "chi2Image", "chi2Profile", "spectrum",
     "sample_spectrum", "Dataset", "Workspace", "read_status", "timing", "GalarioError",
-    "version", "init",
+    "version", "init", "autotune", "tune_get", "tune_set",
 ]
 
 
@@ -354,6 +356,64 @@ class Dataset:
 
 
 # ----------------------------------------------------------------------------
+# FFT schedule autotuning
+def autotune(Nxy: int, dtype=torch.float64, frac: float = 1.0, device=None, times=None) -> list:
+    """Time every FFT variant for this image size on the device and keep the
+    fastest (see gal_autotune_*); returns the chosen variant per pass
+    [rows_image, cols, rows_sym, cols_sym].  With GALARIO_HIP_TUNE_CACHE set
+    to a JSON file path the choice is also stored there.  ``times``, if a
+    dict, receives the per-variant launch times in ms."""
+    dev = torch.device("cuda", torch.cuda.current_device()) if device is None else torch.device(device)
+    chosen = (ctypes.c_int * 4)()
+    tms = (ctypes.c_double * 12)()
+    with torch.cuda.device(dev):
+        check(getattr(_lib(), "gal_autotune" + _sfx(dtype))(int(Nxy), float(frac), _stream(dev),
+                                                             chosen, tms), "autotune")
+    if isinstance(times, dict):
+        names = ["rows_image", "cols", "rows_sym", "cols_sym"]
+        for k in range(4):
+            times[names[k]] = [round(tms[3 * k + v], 5) for v in range(3)]
+    res = [int(c) for c in chosen]
+    path = os.environ.get("GALARIO_HIP_TUNE_CACHE")
+    if path:
+        cache = _read_cache(path)
+        cache[f"{8 if dtype == torch.float64 else 4}:{int(Nxy)}"] = res
+        tmp = path + ".tmp"
+        with open(tmp, "w") as f:
+            json.dump(cache, f, indent=1, sort_keys=True)
+        os.replace(tmp, path)
+    return res
+
+
+def tune_get(Nxy: int, dtype=torch.float64) -> list:
+    out = (ctypes.c_int * 4)()
+    check(_lib().gal_tune_get(8 if dtype == torch.float64 else 4, int(Nxy), out), "tune_get")
+    return [int(c) for c in out]
+
+
+def tune_set(Nxy: int, chosen, dtype=torch.float64):
+    arr = (ctypes.c_int * 4)(*[int(c) for c in chosen])
+    check(_lib().gal_tune_set(8 if dtype == torch.float64 else 4, int(Nxy), arr), "tune_set")
+
+
+def _read_cache(path: str) -> dict:
+    try:
+        with open(path) as f:
+            return json.load(f)
+    except (OSError, ValueError):
+        return {}
+
+
+def _load_tune_cache():
+    path = os.environ.get("GALARIO_HIP_TUNE_CACHE")
+    if not path:
+        return
+    for key, chosen in _read_cache(path).items():
+        prec, n = key.split(":")
+        check(_lib().gal_tune_set(int(prec), int(n), (ctypes.c_int * 4)(*chosen)), "tune cache")
+
+
+# ----------------------------------------------------------------------------
 class timing:
     """Per-kernel HIP-event timing inside the library (for benchmarks)."""
 
@@ -376,3 +436,6 @@ class timing:
         cnt = (ctypes.c_int64 * max(n, 1))()
         n = _lib().gal_timing_read(n, names, ms, cnt)
         return {names[i].decode(): (ms[i], int(cnt[i])) for i in range(n)}
+
+
+_load_tune_cache()

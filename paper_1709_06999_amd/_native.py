@@ -52,6 +52,9 @@ _SIG = {
     "gal_chi2Profile_ds": (I, [P, P, I, D, D, I, D, D, D, D, D, P, P, SZ, P]),
     "gal_sampleImage_ds": (I, [P, P, I, D, D, D, D, D, P, P, SZ, P]),
     "gal_sampleProfile_ds": (I, [P, P, I, D, D, I, D, D, D, D, D, P, P, SZ, P]),
+    "gal_autotune": (I, [I, D, P, ctypes.POINTER(I), ctypes.POINTER(D)]),
+    "gal_tune_get": (I, [I, I, ctypes.POINTER(I)]),
+    "gal_tune_set": (I, [I, I, ctypes.POINTER(I)]),
     "gal_timing_enable": (I, [I]),
     "gal_timing_reset": (I, []),
     "gal_timing_read": (I, [I, ctypes.POINTER(ctypes.c_char_p), ctypes.POINTER(D),
@@ -60,7 +63,7 @@ _SIG = {
 _PRECISION_SUFFIXED = {
     "gal_sweep", "gal_sampleImage", "gal_sampleProfile", "gal_chi2Image", "gal_chi2Profile",
     "gal_spectrum", "gal_sample_spectrum", "gal_dataset_create", "gal_chi2Image_ds",
-    "gal_chi2Profile_ds", "gal_sampleImage_ds", "gal_sampleProfile_ds",
+    "gal_chi2Profile_ds", "gal_sampleImage_ds", "gal_sampleProfile_ds", "gal_autotune",
 }
 
 

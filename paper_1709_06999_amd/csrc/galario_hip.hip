@@ -3,6 +3,7 @@
 // Argument checks, the choice of which part of the half spectrum to
 // transform, workspace carving, kernel launches and per-kernel timing.  All
 // arithmetic of the path runs in the kernels of kernels.h.
+#include <hip/hip_ext.h>
 #include <hip/hip_runtime.h>
 
 #include <cmath>
@@ -13,6 +14,7 @@
 #include <utility>
 #include <mutex>
 #include <string>
+#include <type_traits>
 #include <vector>
 
 #include "../../include/galario_hip.h"
@@ -87,7 +89,8 @@ static int ensure_init() {
 }
 
 // ---------------------------------------------------------------------------
-// per-kernel timing with HIP events on the launch stream
+// kernel launches, with per-kernel timing from the dispatch's own start / end
+// timestamps (hipExtLaunchKernelGGL) when timing is enabled
 struct TimingRec {
     const char *name;
     hipEvent_t a, b;
@@ -108,25 +111,18 @@ static hipEvent_t tm_event() {
     return e;
 }
 
-struct TimedLaunch {
-    const char *name;
-    hipStream_t s;
-    hipEvent_t a = nullptr;
-    TimedLaunch(const char *n, hipStream_t st) : name(n), s(st) {
-        std::lock_guard<std::mutex> lk(g_tm_mu);
-        if (!g_tm_on) return;
-        a = tm_event();
-        if (a) (void)hipEventRecord(a, s);
-    }
-    ~TimedLaunch() {
-        if (!a) return;
-        std::lock_guard<std::mutex> lk(g_tm_mu);
-        hipEvent_t b = tm_event();
-        if (!b) return;
-        (void)hipEventRecord(b, s);
-        g_tm_recs.push_back({name, a, b});
-    }
-};
+static bool tm_begin(hipEvent_t &a, hipEvent_t &b) {
+    std::lock_guard<std::mutex> lk(g_tm_mu);
+    if (!g_tm_on) return false;
+    a = tm_event();
+    b = tm_event();
+    return a && b;
+}
+
+static void tm_end(const char *name, hipEvent_t a, hipEvent_t b) {
+    std::lock_guard<std::mutex> lk(g_tm_mu);
+    g_tm_recs.push_back({name, a, b});
+}
 
 static int check_launch() {
     hipError_t e = hipGetLastError();
@@ -134,129 +130,180 @@ static int check_launch() {
     return GAL_OK;
 }
 
+// Every argument is converted to the kernel's parameter type before launch
+// (pointers by a plain cast: the buffers are reused with several layouts).
+template <typename K, typename A>
+static inline K arg_cast(A &&a) {
+    if constexpr (std::is_pointer<K>::value) return (K)(a);
+    else return static_cast<K>(a);
+}
+
+template <typename... KArgs, typename... Args>
+static int launch(const char *name, void (*kernel)(KArgs...), dim3 grid, dim3 block,
+                  hipStream_t s, Args &&...args) {
+    static_assert(sizeof...(KArgs) == sizeof...(Args), "kernel argument count");
+    if (grid.x == 0) return GAL_OK;
+    hipEvent_t a = nullptr, b = nullptr;
+    if (tm_begin(a, b)) {
+        hipExtLaunchKernelGGL(kernel, grid, block, 0, s, a, b, 0, arg_cast<KArgs>(args)...);
+        tm_end(name, a, b);
+    } else {
+        kernel<<<grid, block, 0, s>>>(arg_cast<KArgs>(args)...);
+    }
+    return check_launch();
+}
+
 // ---------------------------------------------------------------------------
-// per-size FFT shapes: rows (B rows of length N/2 per block, NT threads) and
-// columns (B columns of length N per block, NT threads)
-template <int N>
-struct RowShape;
-template <> struct RowShape<16> { static constexpr int B = 16, NT = 16; };
-template <> struct RowShape<32> { static constexpr int B = 32, NT = 32; };
-template <> struct RowShape<64> { static constexpr int B = 32, NT = 64; };
-template <> struct RowShape<128> { static constexpr int B = 16, NT = 64; };
-template <> struct RowShape<256> { static constexpr int B = 16, NT = 128; };
-template <> struct RowShape<512> { static constexpr int B = 8, NT = 128; };
-template <> struct RowShape<1024> { static constexpr int B = 4, NT = 128; };
-template <> struct RowShape<2048> { static constexpr int B = 4, NT = 256; };
-template <> struct RowShape<4096> { static constexpr int B = 2, NT = 256; };
-template <> struct RowShape<8192> { static constexpr int B = 1, NT = 256; };
-
-template <int N>
-struct ColShape;
-template <> struct ColShape<16> { static constexpr int B = 8, NT = 16; };
-template <> struct ColShape<32> { static constexpr int B = 8, NT = 32; };
-template <> struct ColShape<64> { static constexpr int B = 8, NT = 32; };
-template <> struct ColShape<128> { static constexpr int B = 8, NT = 64; };
-template <> struct ColShape<256> { static constexpr int B = 4, NT = 64; };
-template <> struct ColShape<512> { static constexpr int B = 2, NT = 64; };
-template <> struct ColShape<1024> { static constexpr int B = 1, NT = 64; };
-template <> struct ColShape<2048> { static constexpr int B = 1, NT = 128; };
-template <> struct ColShape<4096> { static constexpr int B = 1, NT = 256; };
-template <> struct ColShape<8192> { static constexpr int B = 1, NT = 512; };
-
+// FFT shapes.  Each pass kernel exists in up to three variants that differ
+// in the values each thread holds (E = 16, 8, 4: fewer values = more
+// threads per transform, more waves in flight, more radix-E passes).  The
+// autotuner (gal_autotune_*) times them per image size and precision; the
+// defaults below are used until it has run.
+enum FftKind { K_ROWS_IMG = 0, K_COLS = 1, K_ROWS_SYM = 2, K_COLS_SYM = 3, NKIND = 4 };
+static const char *kind_name(int k) {
+    static const char *n[NKIND] = {"rows_image", "cols", "rows_sym", "cols_sym"};
+    return n[k];
+}
+constexpr int NVAR = 3;
+constexpr int var_E(int var) { return var == 0 ? 16 : (var == 1 ? 8 : 4); }
 constexpr int min_c(int a, int b) { return a < b ? a : b; }
+constexpr int max_c(int a, int b) { return a > b ? a : b; }
 
-template <typename T, int L, int B, int NT>
-using AutoCfg = FFTCfg<T, L, B, NT, min_c(16, min_c(B * L / NT, L))>;
+// rows of a general image: B rows of length N/2 per block (B >= 4 where the
+// LDS allows, so that the transposed store writes >= 64-byte runs)
+constexpr int rows_B(int N) {
+    return N >= 8192 ? 1 : (N >= 4096 ? 2 : min_c(N, max_c(4, 2048 / N)));
+}
+// complex length-N passes (columns, swept-profile row pairs): B sequences
+constexpr int cols_B(int N) { return max_c(1, 1024 / N); }
+// threads for B sequences of length L with E values each, capped at 1024
+constexpr int shape_E(int B, int L, int E) {
+    return (B * L / E > 1024) ? (B * L / 1024) : (E > B * L ? B * L : E);
+}
 
-template <typename T, int N>
-using RowCfg = AutoCfg<T, N / 2, RowShape<N>::B, RowShape<N>::NT>;
-template <typename T, int N>
-using ColCfg = AutoCfg<T, N, ColShape<N>::B, ColShape<N>::NT>;
+template <typename T, int L, int B, int E>
+using CfgE = FFTCfg<T, L, B, B * L / shape_E(B, L, E), min_c(16, min_c(shape_E(B, L, E), L))>;
 
-// Launch the two FFT passes for one image: src is the image (PROFILE false)
-// or the profile (PROFILE true); result in XT with geometry g.
+template <typename T>
+struct FftJob {
+    const T *src;    // image (rows_image) or profile (rows_sym)
+    SweepArgs sw;
+    Geom g;
+    int Qe;          // even column count (swept-profile passes)
+    void *buf;       // intermediate / spectrum
+    hipStream_t s;
+};
+template <typename T>
+using FftFn = int (*)(const FftJob<T> &);
+
+template <typename T, int N, int VAR>
+static int run_rows_img(const FftJob<T> &j) {
+    constexpr int B = rows_B(N);
+    using C = CfgE<T, N / 2, B, var_E(VAR)>;
+    return launch("k_rows_image", k_rows<T, C, false>, dim3(N / B), dim3(C::NT), j.s, j.src, j.sw,
+                  j.g, j.buf);
+}
+template <typename T, int N, int VAR>
+static int run_cols(const FftJob<T> &j) {
+    constexpr int B = cols_B(N);
+    using C = CfgE<T, N, B, var_E(VAR)>;
+    return launch("k_cols", k_cols<T, C>, dim3((j.g.Q + B - 1) / B), dim3(C::NT), j.s, j.g, j.buf);
+}
+template <typename T, int N, int VAR>
+static int run_rows_sym(const FftJob<T> &j) {
+    constexpr int B = cols_B(N);
+    using C = CfgE<T, N, B, var_E(VAR)>;
+    const int pairs = N / 4 + 1;
+    return launch("k_rows_sym", k_rows_sym<T, C>, dim3((pairs + B - 1) / B), dim3(C::NT), j.s,
+                  j.src, j.sw, j.g, j.Qe, j.buf);
+}
+template <typename T, int N, int VAR>
+static int run_cols_sym(const FftJob<T> &j) {
+    constexpr int B = cols_B(N);
+    using C = CfgE<T, N, B, var_E(VAR)>;
+    const int pairs = j.Qe / 2;
+    return launch("k_cols_sym", k_cols_sym<T, C>, dim3((pairs + B - 1) / B), dim3(C::NT), j.s, j.g,
+                  j.Qe, j.buf);
+}
+
+// variant table [log2 N - 4][kind][var]; small images compile one variant
 template <typename T, int N>
-static int launch_fft(const T *src, bool profile, const SweepArgs &sw, const Geom &g, c2<T> *XT,
-                      hipStream_t s) {
-    using RC = RowCfg<T, N>;
-    using CC = ColCfg<T, N>;
-    {
-        const dim3 grid(N / RC::B);
-        if (profile) {
-            TimedLaunch tl("k_rows_profile", s);
-            k_rows<T, RC, true><<<grid, RC::NT, 0, s>>>(src, sw, g, XT);
-        } else {
-            TimedLaunch tl("k_rows_image", s);
-            k_rows<T, RC, false><<<grid, RC::NT, 0, s>>>(src, sw, g, XT);
+struct VarTable {
+    static constexpr bool many = N >= 256;
+    static FftFn<T> get(int kind, int var) {
+        if (!many) var = 0;
+        switch (kind) {
+            case K_ROWS_IMG:
+                return var == 0 ? run_rows_img<T, N, 0>
+                                : (var == 1 ? run_rows_img<T, N, (many ? 1 : 0)>
+                                            : run_rows_img<T, N, (many ? 2 : 0)>);
+            case K_COLS:
+                return var == 0 ? run_cols<T, N, 0>
+                                : (var == 1 ? run_cols<T, N, (many ? 1 : 0)>
+                                            : run_cols<T, N, (many ? 2 : 0)>);
+            case K_ROWS_SYM:
+                return var == 0 ? run_rows_sym<T, N, 0>
+                                : (var == 1 ? run_rows_sym<T, N, (many ? 1 : 0)>
+                                            : run_rows_sym<T, N, (many ? 2 : 0)>);
+            default:
+                return var == 0 ? run_cols_sym<T, N, 0>
+                                : (var == 1 ? run_cols_sym<T, N, (many ? 1 : 0)>
+                                            : run_cols_sym<T, N, (many ? 2 : 0)>);
         }
-        int rc = check_launch();
-        if (rc) return rc;
     }
-    {
-        const dim3 grid((g.Q + CC::B - 1) / CC::B);
-        TimedLaunch tl("k_cols", s);
-        k_cols<T, CC><<<grid, CC::NT, 0, s>>>(g, XT);
+};
+
+template <typename T>
+static FftFn<T> fft_fn(int N, int kind, int var) {
+    switch (N) {
+        case 16: return VarTable<T, 16>::get(kind, var);
+        case 32: return VarTable<T, 32>::get(kind, var);
+        case 64: return VarTable<T, 64>::get(kind, var);
+        case 128: return VarTable<T, 128>::get(kind, var);
+        case 256: return VarTable<T, 256>::get(kind, var);
+        case 512: return VarTable<T, 512>::get(kind, var);
+        case 1024: return VarTable<T, 1024>::get(kind, var);
+        case 2048: return VarTable<T, 2048>::get(kind, var);
+        case 4096: return VarTable<T, 4096>::get(kind, var);
+        case 8192: return VarTable<T, 8192>::get(kind, var);
+        default: return nullptr;
     }
-    return check_launch();
+}
+
+static int log2i(int N) {
+    int l = 0;
+    while ((1 << l) < N) ++l;
+    return l;
+}
+
+// chosen variant per [precision 0 = double, 1 = float][log2 N][kind]; -1 = default
+static std::mutex g_tune_mu;
+static int g_choice[2][14][NKIND];
+static bool g_choice_init = false;
+
+static int default_var(int N, int kind) {
+    if (N < 256) return 0;
+    return (kind == K_ROWS_IMG) ? 0 : 1;
 }
 
 template <typename T>
-static int dispatch_fft(int N, const T *src, bool profile, const SweepArgs &sw, const Geom &g,
-                        c2<T> *XT, hipStream_t s) {
-    switch (N) {
-        case 16: return launch_fft<T, 16>(src, profile, sw, g, XT, s);
-        case 32: return launch_fft<T, 32>(src, profile, sw, g, XT, s);
-        case 64: return launch_fft<T, 64>(src, profile, sw, g, XT, s);
-        case 128: return launch_fft<T, 128>(src, profile, sw, g, XT, s);
-        case 256: return launch_fft<T, 256>(src, profile, sw, g, XT, s);
-        case 512: return launch_fft<T, 512>(src, profile, sw, g, XT, s);
-        case 1024: return launch_fft<T, 1024>(src, profile, sw, g, XT, s);
-        case 2048: return launch_fft<T, 2048>(src, profile, sw, g, XT, s);
-        case 4096: return launch_fft<T, 4096>(src, profile, sw, g, XT, s);
-        case 8192: return launch_fft<T, 8192>(src, profile, sw, g, XT, s);
-        default: return fail(GAL_ERR_SIZE, "Nxy=%d unsupported", N);
+static int chosen_var(int N, int kind) {
+    std::lock_guard<std::mutex> lk(g_tune_mu);
+    if (!g_choice_init) {
+        for (auto &a : g_choice)
+            for (auto &b : a)
+                for (int &c : b) c = -1;
+        g_choice_init = true;
     }
-}
-
-// Swept-profile transform (real, even spectrum): rows r in [0, N/2] in pairs,
-// then column pairs; result SR[q * CS + p], p in [0, P], q in [0, Qe).
-template <typename T, int N>
-static int launch_fft_sym(const T *I, const SweepArgs &sw, const Geom &g, int Qe, T *XR,
-                          hipStream_t s) {
-    using CC = ColCfg<T, N>;
-    {
-        const int pairs = N / 4 + 1;
-        const dim3 grid((pairs + CC::B - 1) / CC::B);
-        TimedLaunch tl("k_rows_sym", s);
-        k_rows_sym<T, CC><<<grid, CC::NT, 0, s>>>(I, sw, g, Qe, XR);
-    }
-    int rc = check_launch();
-    if (rc) return rc;
-    {
-        const int pairs = Qe / 2;
-        const dim3 grid((pairs + CC::B - 1) / CC::B);
-        TimedLaunch tl("k_cols_sym", s);
-        k_cols_sym<T, CC><<<grid, CC::NT, 0, s>>>(g, Qe, XR);
-    }
-    return check_launch();
+    const int v = g_choice[sizeof(T) == 8 ? 0 : 1][log2i(N)][kind];
+    return v >= 0 ? v : default_var(N, kind);
 }
 
 template <typename T>
-static int dispatch_fft_sym(int N, const T *I, const SweepArgs &sw, const Geom &g, int Qe, T *XR,
-                            hipStream_t s) {
-    switch (N) {
-        case 16: return launch_fft_sym<T, 16>(I, sw, g, Qe, XR, s);
-        case 32: return launch_fft_sym<T, 32>(I, sw, g, Qe, XR, s);
-        case 64: return launch_fft_sym<T, 64>(I, sw, g, Qe, XR, s);
-        case 128: return launch_fft_sym<T, 128>(I, sw, g, Qe, XR, s);
-        case 256: return launch_fft_sym<T, 256>(I, sw, g, Qe, XR, s);
-        case 512: return launch_fft_sym<T, 512>(I, sw, g, Qe, XR, s);
-        case 1024: return launch_fft_sym<T, 1024>(I, sw, g, Qe, XR, s);
-        case 2048: return launch_fft_sym<T, 2048>(I, sw, g, Qe, XR, s);
-        case 4096: return launch_fft_sym<T, 4096>(I, sw, g, Qe, XR, s);
-        case 8192: return launch_fft_sym<T, 8192>(I, sw, g, Qe, XR, s);
-        default: return fail(GAL_ERR_SIZE, "Nxy=%d unsupported", N);
-    }
+static int run_fft(int kind, const FftJob<T> &j) {
+    FftFn<T> f = fft_fn<T>(j.g.N, kind, chosen_var<T>(j.g.N, kind));
+    if (!f) return fail(GAL_ERR_SIZE, "Nxy=%d unsupported", j.g.N);
+    return f(j);
 }
 
 // ---------------------------------------------------------------------------
@@ -365,6 +412,48 @@ struct Obs {
     const int32_t *perm;  // stored point k -> output slot perm[k] (NULL: k)
 };
 
+// Transform: the general image -> complex spectrum in XT (column stride CS);
+// a swept profile -> real spectrum (column stride N/2 + 2).  Returns the
+// geometry the sampler must use.
+template <typename T>
+static int transform(const T *src, bool profile, const SweepArgs &sw, const Geom &g, void *buf,
+                     hipStream_t s, Geom &gs) {
+    FftJob<T> j{src, sw, g, (g.Q + 1) & ~1, buf, s};
+    if (profile) {
+        j.g.CS = g.N / 2 + 2;
+        gs = j.g;
+        int rc = run_fft<T>(K_ROWS_SYM, j);
+        if (rc) return rc;
+        return run_fft<T>(K_COLS_SYM, j);
+    }
+    gs = g;
+    int rc = run_fft<T>(K_ROWS_IMG, j);
+    if (rc) return rc;
+    return run_fft<T>(K_COLS, j);
+}
+
+template <typename T>
+static int sample(bool real_spec, const void *S, const Geom &gs, const SampleArgs &sa,
+                  const Obs<T> &o, T *vis, double *chi2, const WS &w, hipStream_t s) {
+    const dim3 grid((unsigned)sample_blocks(o.M)), blk(SAMPLE_NT);
+    int rc;
+    if (real_spec) {
+        if (!chi2)
+            return launch("k_sample_sym_vis", k_sample_sym<T, false>, grid, blk, s, S, gs, sa, o.u,
+                          o.v, nullptr, nullptr, nullptr, vis, o.perm, w.partials, w.ctl);
+        rc = launch("k_sample_sym_chi2", k_sample_sym<T, true>, grid, blk, s, S, gs, sa, o.u, o.v,
+                    o.re, o.im, o.w, nullptr, nullptr, w.partials, w.ctl);
+    } else {
+        if (!chi2)
+            return launch("k_sample_vis", k_sample<T, false>, grid, blk, s, S, gs, sa, o.u, o.v,
+                          nullptr, nullptr, nullptr, vis, o.perm, w.partials, w.ctl);
+        rc = launch("k_sample_chi2", k_sample<T, true>, grid, blk, s, S, gs, sa, o.u, o.v, o.re,
+                    o.im, o.w, nullptr, nullptr, w.partials, w.ctl);
+    }
+    if (rc) return rc;
+    return launch("k_reduce", k_reduce, dim3(1), dim3(SAMPLE_NT), s, w.partials, (int)grid.x, chi2);
+}
+
 template <typename T>
 static int run_path(const T *src, bool profile, const SweepArgs &sw, const Geom &g, double dxy,
                     const Obs<T> &o, double PA, double dRA, double dDec, double inc, T *vis,
@@ -374,60 +463,94 @@ static int run_path(const T *src, bool profile, const SweepArgs &sw, const Geom 
     WS w;
     rc = carve<T>(ws, ws_bytes_, g.N, o.M, w);
     if (rc) return rc;
-    const SampleArgs sa = make_sample(g, o.M, dxy, PA, dRA, dDec, inc);
-    const dim3 grid((unsigned)sample_blocks(o.M));
-    if (profile) {
-        // real spectrum of the (even) swept image, stored per column with stride N/2 + 2
-        Geom gr = g;
-        gr.CS = g.N / 2 + 2;
-        const int Qe = (g.Q + 1) & ~1;
-        T *XR = (T *)w.xt;
-        rc = dispatch_fft_sym<T>(g.N, src, sw, gr, Qe, XR, s);
-        if (rc) return rc;
-        if (chi2) {
-            {
-                TimedLaunch tl("k_sample_sym_chi2", s);
-                k_sample_sym<T, true><<<grid, SAMPLE_NT, 0, s>>>(XR, gr, sa, o.u, o.v, o.re, o.im,
-                                                                 o.w, nullptr, nullptr, w.partials,
-                                                                 w.ctl);
-            }
-            rc = check_launch();
-            if (rc) return rc;
-            TimedLaunch tl("k_reduce", s);
-            k_reduce<<<1, SAMPLE_NT, 0, s>>>(w.partials, (int)grid.x, chi2);
-        } else {
-            TimedLaunch tl("k_sample_sym_vis", s);
-            k_sample_sym<T, false><<<grid, SAMPLE_NT, 0, s>>>(XR, gr, sa, o.u, o.v, nullptr,
-                                                              nullptr, nullptr, (c2<T> *)vis,
-                                                              o.perm, w.partials, w.ctl);
-        }
-        return check_launch();
-    }
-    c2<T> *XT = (c2<T> *)w.xt;
-    rc = dispatch_fft<T>(g.N, src, profile, sw, g, XT, s);
+    Geom gs;
+    rc = transform<T>(src, profile, sw, g, w.xt, s, gs);
     if (rc) return rc;
-    if (chi2) {
-        {
-            TimedLaunch tl("k_sample_chi2", s);
-            k_sample<T, true><<<grid, SAMPLE_NT, 0, s>>>(XT, g, sa, o.u, o.v, o.re, o.im, o.w,
-                                                         nullptr, nullptr, w.partials, w.ctl);
-        }
-        rc = check_launch();
-        if (rc) return rc;
-        TimedLaunch tl("k_reduce", s);
-        k_reduce<<<1, SAMPLE_NT, 0, s>>>(w.partials, (int)grid.x, chi2);
-    } else {
-        TimedLaunch tl("k_sample_vis", s);
-        k_sample<T, false><<<grid, SAMPLE_NT, 0, s>>>(XT, g, sa, o.u, o.v, nullptr, nullptr,
-                                                      nullptr, (c2<T> *)vis, o.perm, w.partials,
-                                                      w.ctl);
+    const SampleArgs sa = make_sample(g, o.M, dxy, PA, dRA, dDec, inc);
+    return sample<T>(profile, w.xt, gs, sa, o, vis, chi2, w, s);
+}
+
+// ---------------------------------------------------------------------------
+// autotuner: time every variant of every pass for one image size
+template <typename T>
+static int autotune(int N, double frac, void *stream, int *chosen_out, double *times) {
+    if (!pow2_in_range(N)) return fail(GAL_ERR_SIZE, "Nxy=%d unsupported", N);
+    if (!(frac > 0.0 && frac <= 1.0)) return fail(GAL_ERR_SCALAR, "frac must be in (0, 1]");
+    int rc = ensure_init();
+    if (rc) return rc;
+    hipStream_t s = (hipStream_t)stream;
+    const size_t img_bytes = (size_t)N * N * sizeof(T);
+    const size_t buf_bytes = (size_t)(N / 2 + 1) * (N + 2) * sizeof(c2<T>);
+    void *img = nullptr, *buf = nullptr;
+    GAL_HIP(hipMalloc(&img, img_bytes + 64));
+    if (hipMalloc(&buf, buf_bytes) != hipSuccess) {
+        (void)hipFree(img);
+        return fail(GAL_ERR_WORKSPACE, "autotune: out of device memory");
     }
-    return check_launch();
+    (void)hipMemsetAsync(img, 0, img_bytes + 64, s);
+    (void)hipMemsetAsync(buf, 0, buf_bytes, s);
+    // a flat profile of 2 samples covering the image: every pixel inside
+    T prof[2] = {T(1), T(1)};
+    T *I = (T *)((char *)img + img_bytes);
+    (void)hipMemcpyAsync(I, prof, sizeof(prof), hipMemcpyHostToDevice, s);
+    const double dxy = 1.0;
+    const SweepArgs sw = make_sweep(2, 0.0, 2.0 * N, dxy, 0.0);
+    Geom g = geom_full(N);
+    const int m = (int)std::floor(frac * (N / 2 - 1)) + 2;
+    g.Q = min_c(g.Q, m);
+    g.P = min_c(g.P, m);
+    hipEvent_t e0 = nullptr, e1 = nullptr;
+    (void)hipEventCreate(&e0);
+    (void)hipEventCreate(&e1);
+    const bool tm_was = g_tm_on;
+    g_tm_on = false;
+    int best[NKIND];
+    for (int kind = 0; kind < NKIND && rc == GAL_OK; ++kind) {
+        FftJob<T> j{(kind == K_ROWS_SYM) ? I : (const T *)img, sw, g, (g.Q + 1) & ~1, buf, s};
+        if (kind == K_ROWS_SYM || kind == K_COLS_SYM) j.g.CS = N / 2 + 2;
+        float best_ms = 1e30f;
+        best[kind] = 0;
+        const int nvar = N >= 256 ? NVAR : 1;
+        if (times)
+            for (int var = 0; var < NVAR; ++var) times[kind * NVAR + var] = -1.0;
+        for (int var = 0; var < nvar && rc == GAL_OK; ++var) {
+            FftFn<T> f = fft_fn<T>(N, kind, var);
+            for (int it = 0; it < 3 && rc == GAL_OK; ++it) rc = f(j);
+            const int reps = 20;
+            (void)hipEventRecord(e0, s);
+            for (int it = 0; it < reps && rc == GAL_OK; ++it) rc = f(j);
+            (void)hipEventRecord(e1, s);
+            if (hipEventSynchronize(e1) != hipSuccess) rc = fail(GAL_ERR_HIP, "autotune sync");
+            float ms = 0.f;
+            (void)hipEventElapsedTime(&ms, e0, e1);
+            if (times) times[kind * NVAR + var] = (double)ms / reps;
+            if (ms < best_ms) {
+                best_ms = ms;
+                best[kind] = var;
+            }
+        }
+    }
+    g_tm_on = tm_was;
+    (void)hipEventDestroy(e0);
+    (void)hipEventDestroy(e1);
+    (void)hipStreamSynchronize(s);
+    (void)hipFree(img);
+    (void)hipFree(buf);
+    if (rc) return rc;
+    {
+        std::lock_guard<std::mutex> lk(g_tune_mu);
+        for (int kind = 0; kind < NKIND; ++kind) {
+            g_choice[sizeof(T) == 8 ? 0 : 1][log2i(N)][kind] = best[kind];
+            if (chosen_out) chosen_out[kind] = best[kind];
+        }
+    }
+    return GAL_OK;
 }
 
 }  // namespace gal
 
 using namespace gal;
+
 
 // ---------------------------------------------------------------------------
 // datasets
@@ -499,11 +622,8 @@ static int sweep_impl(const T *I, int Nr, double Rmin, double dR, int Nxy, doubl
     hipStream_t s = (hipStream_t)stream;
     const SweepArgs sw = make_sweep(Nr, Rmin, dR, dxy, inc);
     const int64_t n = (int64_t)Nxy * Nxy;
-    {
-        TimedLaunch tl("k_sweep", s);
-        k_sweep<T><<<(unsigned)((n + 255) / 256), 256, 0, s>>>(I, sw, Nxy, image);
-    }
-    return check_launch();
+    return launch("k_sweep", k_sweep<T>, dim3((unsigned)((n + 255) / 256)), dim3(256), s, I, sw,
+                  Nxy, image);
 }
 int gal_sweep_d(const double *I, int Nr, double Rmin, double dR, int Nxy, double dxy, double inc,
                 double *image, void *stream) {
@@ -621,15 +741,12 @@ static int spectrum_impl(const T *image, int Nxy, T *spec, void *ws, size_t ws_b
     if (rc) return rc;
     hipStream_t s = (hipStream_t)stream;
     const Geom g = geom_full(Nxy);
-    c2<T> *XT = (c2<T> *)w.xt;
-    rc = dispatch_fft<T>(Nxy, image, false, SweepArgs{}, g, XT, s);
+    Geom gs;
+    rc = transform<T>(image, false, SweepArgs{}, g, w.xt, s, gs);
     if (rc) return rc;
     const int64_t n = (int64_t)Nxy * (Nxy / 2 + 1);
-    {
-        TimedLaunch tl("k_spec_out", s);
-        k_spec_out<T><<<(unsigned)((n + 255) / 256), 256, 0, s>>>(XT, g, (c2<T> *)spec);
-    }
-    return check_launch();
+    return launch("k_spec_out", k_spec_out<T>, dim3((unsigned)((n + 255) / 256)), dim3(256), s,
+                  w.xt, g, spec);
 }
 int gal_spectrum_d(const double *image, int Nxy, double *spec, void *ws, size_t ws_bytes_,
                    void *stream) {
@@ -653,21 +770,13 @@ static int sample_spectrum_impl(const T *spec, int Nxy, double dxy, const T *u, 
     if (rc) return rc;
     hipStream_t s = (hipStream_t)stream;
     const Geom g = geom_full(Nxy);
-    c2<T> *XT = (c2<T> *)w.xt;
     const int64_t n = (int64_t)(Nxy / 2 + 1) * (2 * g.P + 1);
-    {
-        TimedLaunch tl("k_spec_in", s);
-        k_spec_in<T><<<(unsigned)((n + 255) / 256), 256, 0, s>>>((const c2<T> *)spec, g, XT);
-    }
-    rc = check_launch();
+    rc = launch("k_spec_in", k_spec_in<T>, dim3((unsigned)((n + 255) / 256)), dim3(256), s, spec, g,
+                w.xt);
     if (rc) return rc;
     const SampleArgs sa = make_sample(g, M, dxy, PA, dRA, dDec, inc);
-    {
-        TimedLaunch tl("k_sample_vis", s);
-        k_sample<T, false><<<(unsigned)sample_blocks(M), SAMPLE_NT, 0, s>>>(
-            XT, g, sa, u, v, nullptr, nullptr, nullptr, (c2<T> *)vis, nullptr, w.partials, w.ctl);
-    }
-    return check_launch();
+    const Obs<T> o{u, v, nullptr, nullptr, nullptr, M, nullptr};
+    return sample<T>(false, w.xt, g, sa, o, vis, nullptr, w, s);
 }
 int gal_sample_spectrum_d(const double *spec, int Nxy, double dxy, const double *u, const double *v,
                           int64_t M, double PA, double dRA, double dDec, double inc, double *vis,
@@ -903,6 +1012,33 @@ int gal_sampleProfile_ds_f(const gal_dataset *ds, const float *I, int Nr, double
                            float *vis, void *ws, size_t ws_bytes_, void *stream) {
     return ds_call<float>(ds, I, true, Nr, Rmin, dR, Nxy, dxy, inc, PA, dRA, dDec, vis, nullptr, ws,
                           ws_bytes_, stream);
+}
+
+// ---- autotuning ----------------------------------------------------------
+int gal_autotune_d(int Nxy, double frac, void *stream, int *chosen, double *times_ms) {
+    return autotune<double>(Nxy, frac, stream, chosen, times_ms);
+}
+int gal_autotune_f(int Nxy, double frac, void *stream, int *chosen, double *times_ms) {
+    return autotune<float>(Nxy, frac, stream, chosen, times_ms);
+}
+int gal_tune_get(int precision, int Nxy, int *chosen) {
+    if (!chosen) return fail(GAL_ERR_NULL, "NULL chosen");
+    if (!pow2_in_range(Nxy) || (precision != 8 && precision != 4))
+        return fail(GAL_ERR_SIZE, "bad precision or Nxy");
+    for (int k = 0; k < NKIND; ++k)
+        chosen[k] = precision == 8 ? chosen_var<double>(Nxy, k) : chosen_var<float>(Nxy, k);
+    return GAL_OK;
+}
+int gal_tune_set(int precision, int Nxy, const int *chosen) {
+    if (!chosen) return fail(GAL_ERR_NULL, "NULL chosen");
+    if (!pow2_in_range(Nxy) || (precision != 8 && precision != 4))
+        return fail(GAL_ERR_SIZE, "bad precision or Nxy");
+    for (int k = 0; k < NKIND; ++k)
+        if (chosen[k] < -1 || chosen[k] >= NVAR) return fail(GAL_ERR_SIZE, "variant out of range");
+    (void)chosen_var<double>(Nxy, 0);  // initialise the table
+    std::lock_guard<std::mutex> lk(g_tune_mu);
+    for (int k = 0; k < NKIND; ++k) g_choice[precision == 8 ? 0 : 1][log2i(Nxy)][k] = chosen[k];
+    return GAL_OK;
 }
 
 // ---- timing ---------------------------------------------------------------

@@ -190,17 +190,24 @@ __global__ __launch_bounds__(Cfg::NT) void k_rows_sym(const T *__restrict__ I, S
     const int tid = threadIdx.x;
     const int m0 = xcd_remap(blockIdx.x, gridDim.x) * B;
 
+    // columns c and N - c hold the same pixel: sweep c in [0, N/2] into LDS
+    constexpr int NH = N / 2 + 1;
+    for (int idx = tid; idx < B * NH; idx += NT) {
+        const int b = idx / NH, c = idx % NH;
+        const int r = 2 * (m0 + b);  // rows r, r + 1 (r + 1 < N)
+        lds[b * Cfg::LS + c] = c2<T>{(T)sweep_pixel(I, N, r, c, sw),
+                                     (T)sweep_pixel(I, N, r + 1, c, sw)};
+    }
+    __syncthreads();
     c2<T> v[E];
 #pragma unroll
     for (int i = 0; i < E / R0; ++i) {
         const int gi = tid + i * NT;
         const int b = gi / LR, j = gi % LR;
-        const int r = 2 * (m0 + b);  // rows r, r + 1 (r + 1 <= N/2 + 1 < N)
 #pragma unroll
         for (int t = 0; t < R0; ++t) {
             const int n = j + t * LR;
-            v[i * R0 + t].x = (T)sweep_pixel(I, N, r, n, sw);
-            v[i * R0 + t].y = (T)sweep_pixel(I, N, r + 1, n, sw);
+            v[i * R0 + t] = lds[b * Cfg::LS + (n <= N / 2 ? n : N - n)];
         }
     }
     fft_passes<Cfg, 1>(v, lds, twiddles<T>(), tid);
@@ -358,6 +365,27 @@ __device__ __forceinline__ double block_sum(double x, double *red) {
     return s;
 }
 
+// End of a chi^2 sampling block: the block's partial sum, added to the
+// others in index order by k_reduce (bitwise repeatable).  A last-block
+// reduction inside this kernel would need a device-scope release in every
+// block, which on this chip writes back the L2 once per block and costs more
+// than the second launch.
+__device__ __forceinline__ void chi2_block_end(double acc, double *red, int blk,
+                                               double *__restrict__ partials) {
+    const double bs = block_sum(acc, red);
+    if (threadIdx.x == 0) partials[blk] = bs;
+}
+
+// Final chi^2: one block sums the per-block partials in a fixed order.
+__global__ __launch_bounds__(SAMPLE_NT) void k_reduce(const double *__restrict__ partials, int n,
+                                                      double *__restrict__ out) {
+    __shared__ double red[SAMPLE_NT / 64];
+    double s = 0.0;
+    for (int k = threadIdx.x; k < n; k += SAMPLE_NT) s += partials[k];
+    const double tot = block_sum(s, red);
+    if (threadIdx.x == 0) *out = tot;
+}
+
 // Sampling of the real, p-even spectrum of a swept profile: node (q, p~)
 // holds SR[q * CS + |p~|], so the two rows of a stencil are the adjacent
 // pair starting at min(|p~0|, |p~0 + 1|).
@@ -454,15 +482,11 @@ __global__ __launch_bounds__(SAMPLE_NT) void k_sample_sym(
         }
     }
     if (bad) ctl->flag = 1;
-    if constexpr (CHI2) {
-        const double bs = block_sum(acc, red);
-        if (threadIdx.x == 0) partials[blk] = bs;
-    }
+    if constexpr (CHI2) chi2_block_end(acc, red, blk, partials);
 }
 
 // Each thread takes SAMPLE_PPT points strided by the block size: all loads
-// are issued before the arithmetic.  CHI2: one partial sum per block,
-// reduced by k_reduce in a fixed order (bitwise repeatable, no fences).
+// are issued before the arithmetic.  CHI2: see chi2_block_end.
 template <typename T, bool CHI2>
 __global__ __launch_bounds__(SAMPLE_NT) void k_sample(
     const c2<T> *__restrict__ S, Geom g, SampleArgs a, const T *__restrict__ u,
@@ -510,21 +534,9 @@ __global__ __launch_bounds__(SAMPLE_NT) void k_sample(
         }
     }
     if (bad) ctl->flag = 1;
-    if constexpr (CHI2) {
-        const double bs = block_sum(acc, red);
-        if (threadIdx.x == 0) partials[blk] = bs;
-    }
+    if constexpr (CHI2) chi2_block_end(acc, red, blk, partials);
 }
 
-// Final chi^2: one block sums the per-block partials in a fixed order.
-__global__ __launch_bounds__(SAMPLE_NT) void k_reduce(const double *__restrict__ partials, int n,
-                                                      double *__restrict__ out) {
-    __shared__ double red[SAMPLE_NT / 64];
-    double s = 0.0;
-    for (int k = threadIdx.x; k < n; k += SAMPLE_NT) s += partials[k];
-    const double tot = block_sum(s, red);
-    if (threadIdx.x == 0) *out = tot;
-}
 
 // ---------------------------------------------------------------------------
 // stand-alone sweep (gal_sweep)
