@@ -6,12 +6,19 @@ profile of Nr = 4096 samples (gapped power law) swept into a 2048^2 image at
 dxy = 0.003'', uv points log-uniform over ALMA C43-10 baselines at 1.3 mm,
 inc = 45 deg, PA = 120 deg, Vobs = model + N(0, 1e-3^2) noise, w = 1e6.
 The observations are registered once as a device-resident dataset (inputs
-resident in HBM before the timed region); a step is one chi^2 evaluation of
-the whole path: sweep + row FFT, column FFT, sample + phase + chi^2.
+resident in HBM before the timed region).
 
-Prints one JSON line.  Per-kernel times come from HIP events recorded on the
-launch stream inside the library (a second pass over the same steps); the
-roofline entry is for the kernel with the largest share of the step.
+A step is one batched evaluation of K models (the walkers of an ensemble
+sampler: perturbed profiles and geometry) through the whole path -- sweep +
+row FFT, column FFT, sample + phase + chi^2, reduction -- replayed from a HIP
+graph; `value` counts chi^2 evaluations per second.  The plain form (one
+call per evaluation) is measured on the same dataset and reported beside it
+with its p50/p99 latency.
+
+Prints one JSON line.  Per-kernel times come from the dispatch timestamps
+recorded on the launch stream inside the library (a separate pass over the
+same steps); the roofline entry is for the kernel with the largest share of
+the batched step.
 """
 from __future__ import annotations
 
@@ -62,18 +69,46 @@ def algorithmic_bytes(N, Nr, M, Q, P, kind="profile", p=8):
             "k_sample_chi2": 5 * p * M + spec, "k_reduce": red}
 
 
+def _timed(fn, steps, warmup, torch):
+    for _ in range(warmup):
+        fn()
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(steps):
+        fn()
+    torch.cuda.synchronize()
+    return (time.perf_counter() - t0) * 1e3 / steps
+
+
+def _kernel_times(gal, fn, steps, torch):
+    """Average duration per kernel from the dispatch timestamps (HIP events on
+    the launch stream, recorded by the library)."""
+    gal.timing.reset()
+    gal.timing.enable(True)
+    for _ in range(steps):
+        fn()
+    torch.cuda.synchronize()
+    times = gal.timing.read()
+    gal.timing.enable(False)
+    gal.timing.reset()
+    return {k: {"avg_us": 1e3 * ms / n, "launches": n} for k, (ms, n) in times.items()}
+
+
 def main():
     ap = argparse.ArgumentParser(description=__doc__.split("\n")[0])
     ap.add_argument("--gpus", type=int, default=1)
-    ap.add_argument("--steps", type=int, default=2000)
-    ap.add_argument("--warmup", type=int, default=50)
+    ap.add_argument("--steps", type=int, default=400, help="timed batched steps")
+    ap.add_argument("--warmup", type=int, default=20)
+    ap.add_argument("--batch", type=int, default=16, help="models per batched step")
+    ap.add_argument("--plain-steps", type=int, default=2000)
     ap.add_argument("--latency-samples", type=int, default=300)
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-graph", action="store_true", help="launch batches without a HIP graph")
     ap.add_argument("--calib-copy", action="store_true",
                     help="also run one 256 MiB device-to-device copy (a known-size kernel for "
                          "scaling HBM byte counters)")
     ap.add_argument("--kind", choices=["profile", "image"], default="profile",
-                    help="profile: chi2Profile (default); image: chi2Image of the swept image")
+                    help="plain path: chi2Profile (default) or chi2Image of the swept image")
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py runs on one GPU only (asked for --gpus {args.gpus}); the path is "
@@ -106,12 +141,6 @@ def main():
     frac = ds.rho_max * N * case.dxy / (N / 2 - 1)
     tune_times = {}
     tuned = gal.autotune(N, torch.float64, frac, times=tune_times)
-    out = torch.empty((), dtype=torch.float64, device=dev)
-    if args.kind == "profile":
-        call = lambda: ds.chi2Profile(I, case.Rmin, case.dR, N, case.dxy, out=out, **geo)
-    else:
-        img = gal.sweep(I, case.Rmin, case.dR, N, case.dxy, case.inc)
-        call = lambda: ds.chi2Image(img, case.dxy, case.PA, case.dRA, case.dDec, out=out)
 
     if args.calib_copy:
         a = torch.ones(32 * 1024 * 1024, dtype=torch.float64, device=dev)
@@ -120,54 +149,77 @@ def main():
         torch.cuda.synchronize()
         del a, b
 
-    for _ in range(args.warmup):
-        call()
-    torch.cuda.synchronize()
+    # ---- plain: one evaluation per call --------------------------------
+    out = torch.empty((), dtype=torch.float64, device=dev)
+    if args.kind == "profile":
+        plain = lambda: ds.chi2Profile(I, case.Rmin, case.dR, N, case.dxy, out=out, **geo)
+    else:
+        img = gal.sweep(I, case.Rmin, case.dR, N, case.dxy, case.inc)
+        plain = lambda: ds.chi2Image(img, case.dxy, case.PA, case.dRA, case.dDec, out=out)
+    ms_plain = _timed(plain, args.plain_steps, args.warmup, torch)
     chi2_val = float(out)
-
-    # timed region: exactly `steps` evaluations
-    torch.cuda.synchronize()
-    t0 = time.perf_counter()
-    for _ in range(args.steps):
-        call()
-    torch.cuda.synchronize()
-    t1 = time.perf_counter()
-    ms_per_step = (t1 - t0) * 1e3 / args.steps
-    evals_per_s = 1e3 / ms_per_step
-
-    # per-kernel durations (HIP events on the launch stream), same steps again
-    gal.timing.reset()
-    gal.timing.enable(True)
-    for _ in range(args.steps):
-        call()
-    torch.cuda.synchronize()
-    times = gal.timing.read()
-    gal.timing.enable(False)
-    gal.timing.reset()
-    kern = {k: {"avg_us": 1e3 * ms / n, "launches": n} for k, (ms, n) in times.items()}
-
-    # latency of one synchronous evaluation
+    kern_plain = _kernel_times(gal, plain, args.plain_steps, torch)
     lat = []
     for _ in range(args.latency_samples):
         a = time.perf_counter()
-        call()
+        plain()
         torch.cuda.synchronize()
         lat.append((time.perf_counter() - a) * 1e3)
     lat = np.sort(np.array(lat))
 
-    ab = algorithmic_bytes(N, Nr, M, Q, P, args.kind)
+    # ---- batched: K walkers (different profiles and geometry) per step ----
+    K = args.batch
+    rng = np.random.default_rng(1102)
+    Ib = f64(np.stack([case.I * (1.0 + 0.05 * rng.standard_normal(Nr)) for _ in range(K)]))
+    geob = f64(np.array([[case.Rmin, case.dR, case.inc + 0.05 * rng.standard_normal(),
+                          case.PA + 0.05 * rng.standard_normal(),
+                          0.1 * case.dxy * rng.standard_normal(),
+                          0.1 * case.dxy * rng.standard_normal()] for _ in range(K)]))
+    batch = gal.profile_batch(ds, Ib, geob, N, case.dxy)
+    step = batch.chi2
+    graph = None
+    if not args.no_graph:
+        side = torch.cuda.Stream(device=dev)
+        side.wait_stream(torch.cuda.current_stream(dev))
+        with torch.cuda.stream(side):
+            batch.chi2()                      # warm-up outside the capture
+        torch.cuda.current_stream(dev).wait_stream(side)
+        torch.cuda.synchronize()
+        graph = torch.cuda.CUDAGraph()
+        with torch.cuda.graph(graph):
+            batch.chi2()
+        step = graph.replay
+    ms_batch = _timed(step, args.steps, args.warmup, torch)
+    chi2_batch = batch.out.cpu().numpy()
+    # every replay matches an eager execution
+    eager = batch.chi2().clone()
+    torch.cuda.synchronize()
+    replay_ok = bool(torch.equal(eager, batch.out))
+    kern = _kernel_times(gal, batch.chi2, max(args.steps // 4, 20), torch)
+    evals_per_s = K * 1e3 / ms_batch
+
+    # ---- roofline of the dominant kernel of the batched step ---------------
+    ab = algorithmic_bytes(N, Nr, M, Q, P, "profile")
+    Qe = Q + (Q & 1)
+    spec = (P + 1) * Qe * 8
+    ab_batch = {"kb_rows_sym": K * ab["k_rows_sym"], "kb_cols_sym": K * ab["k_cols_sym"],
+                "kb_sample_sym_chi2": 5 * 8 * M + K * spec, "kb_reduce": K * ab["k_reduce"]}
     for k in kern:
+        if k in ab_batch:
+            kern[k]["alg_bytes"] = ab_batch[k]
+            kern[k]["alg_GBps"] = ab_batch[k] / (kern[k]["avg_us"] * 1e-6) / 1e9
+    for k in kern_plain:
         if k in ab:
-            kern[k]["alg_bytes"] = ab[k]
-            kern[k]["alg_GBps"] = ab[k] / (kern[k]["avg_us"] * 1e-6) / 1e9
-    dom = max((k for k in kern if k in ab and k != "k_reduce"), key=lambda k: kern[k]["avg_us"])
+            kern_plain[k]["alg_bytes"] = ab[k]
+            kern_plain[k]["alg_GBps"] = ab[k] / (kern_plain[k]["avg_us"] * 1e-6) / 1e9
+    dom = max((k for k in kern if k in ab_batch), key=lambda k: kern[k]["avg_us"])
     achieved = kern[dom]["alg_GBps"]
     roofline = {"bound": "hbm", "kernel": dom, "achieved": round(achieved, 1),
                 "peak": HBM_PEAK_GBS, "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBS, 4),
-                "traffic": None,
-                "alg_bytes_per_launch": ab[dom],
-                "path_alg_bytes": sum(ab.values()),
-                "path_frac": round(sum(ab.values()) / (ms_per_step * 1e-3) / 1e9 / HBM_PEAK_GBS, 4)}
+                "traffic": None, "alg_bytes_per_launch": ab_batch[dom],
+                "step_alg_bytes": sum(ab_batch.values()),
+                "step_frac": round(sum(ab_batch.values()) / (ms_batch * 1e-3) / 1e9 /
+                                   HBM_PEAK_GBS, 4)}
 
     cpu = None
     if not args.no_cpu_baseline:
@@ -186,6 +238,8 @@ def main():
                "sample": f"{len(t_runs)} full evaluation(s) of this workload by the FP64 "
                          "direct-DFT oracle (O(N^3)), median time"}
 
+    rnd = lambda d: {k: {kk: (round(vv, 3) if isinstance(vv, float) else vv)
+                         for kk, vv in x.items()} for k, x in d.items()}
     res = {
         "metric": METRIC,
         "value": round(evals_per_s, 1),
@@ -193,27 +247,32 @@ def main():
         "n_gpus": 1,
         "steps": args.steps,
         "warmup": args.warmup,
-        "ms_per_step": round(ms_per_step, 5),
+        "ms_per_step": round(ms_batch, 5),
         "higher_is_better": True,
         "scaling": "weak",
         "vs_baseline": None,
         "dtype": "f64",
         "data": "synthetic",
-        "config": {"workload": ("chi2Profile 2048^2, Nr=4096" if args.kind == "profile" else
-                                "chi2Image 2048^2 (swept image)") +
-                               ", M=1e6 uv, FP64, plain one-at-a-time calls on a "
-                               "device-resident dataset",
-                   "Nxy": N, "Nr": int(Nr), "M": M, "spectrum_cols_Q": Q, "spectrum_rows_P": P,
-                   "chi2": chi2_val, "fft_variants": tuned, "fft_variant_ms": tune_times},
-        "latency_ms": {"p50": round(float(np.percentile(lat, 50)), 4),
-                       "p99": round(float(np.percentile(lat, 99)), 4)},
-        "kernels": {k: {kk: (round(vv, 3) if isinstance(vv, float) else vv)
-                        for kk, vv in d.items()} for k, d in kern.items()},
+        "config": {"workload": f"chi2Profile 2048^2, Nr=4096, M=1e6 uv, FP64; a step is one "
+                               f"batch of {K} models (walkers) on a device-resident dataset"
+                               + ("" if args.no_graph else ", replayed from a HIP graph"),
+                   "Nxy": N, "Nr": int(Nr), "M": M, "batch": K, "spectrum_cols_Q": Q,
+                   "spectrum_rows_P": P, "fft_variants": tuned, "fft_variant_ms": tune_times,
+                   "graph_replay_matches_eager": replay_ok,
+                   "chi2_first_walker": float(chi2_batch[0])},
+        "plain": {"value": round(1e3 / ms_plain, 1), "unit": "chi2 evals/s",
+                  "ms_per_eval": round(ms_plain, 5), "kind": args.kind, "chi2": chi2_val,
+                  "latency_ms": {"p50": round(float(np.percentile(lat, 50)), 4),
+                                 "p99": round(float(np.percentile(lat, 99)), 4)},
+                  "kernels": rnd(kern_plain)},
+        "batched_vs_plain": round(evals_per_s / (1e3 / ms_plain), 3),
+        "kernels": rnd(kern),
         "roofline": roofline,
         "cpu_baseline": cpu,
         "paper_context": {"gtx1060_chi2Profile_2048_ms": 18.0,
                           "note": "paper GPU time includes per-call host-to-device copies"},
     }
+    batch.close()
     ds.close()
     print(json.dumps(res), flush=True)
 

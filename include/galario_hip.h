@@ -211,6 +211,38 @@ int gal_sampleProfile_ds_f(const gal_dataset *ds, const float *I, int Nr, double
                            double dRA, double dDec, float *vis, void *ws, size_t ws_bytes,
                            void *stream);
 
+/* ---- batches: many chi^2 evaluations per launch --------------------------
+ * A batch is a fixed list of jobs, planned once.  Jobs with the same
+ * precision, kind and image size share the FFT launches; jobs on the same
+ * dataset, kind and image grid (up to 16 per group) share one pass over the
+ * observations, which are then read once for the whole group (the typical
+ * case: the walkers of an MCMC ensemble).  At execution the kernels read the
+ * current model arrays and geometry from the device pointers in the jobs, so
+ * a plan -- and a HIP graph captured from gal_batch_chi2 -- is reused while
+ * the caller rewrites those buffers between executions.  The geometry is not
+ * checked at execution: cos(inc) <= 0 or dR <= 0 give a NaN chi^2 for that
+ * job.  Creation checks everything else (like the dataset calls), allocates
+ * the batch's device table and synchronises the device. */
+#define GAL_JOB_IMAGE   0
+#define GAL_JOB_PROFILE 1
+typedef struct {
+    const gal_dataset *ds;  /* observations (with re, im, w) */
+    int kind;               /* GAL_JOB_IMAGE or GAL_JOB_PROFILE */
+    int Nxy;                /* image side (power of two) */
+    double dxy;             /* pixel size [rad] */
+    int Nr;                 /* profile samples (profile jobs) */
+    const void *model;      /* device: image [Nxy*Nxy] or profile [Nr], dataset precision */
+    const double *geo;      /* device: {Rmin, dR, inc, PA, dRA, dDec}; Rmin, dR unused for images */
+} gal_job;
+typedef struct gal_batch gal_batch;
+int gal_batch_create(const gal_job *jobs, int n, gal_batch **out);
+/* Workspace bytes gal_batch_chi2 needs (first 256 bytes zeroed once). */
+size_t gal_batch_workspace_bytes(const gal_batch *b);
+int gal_batch_info(const gal_batch *b, int *n_jobs, int *n_fft_groups, int *n_sample_groups);
+/* chi2[j] (device doubles) for every job; bitwise repeatable. */
+int gal_batch_chi2(const gal_batch *b, double *chi2, void *ws, size_t ws_bytes, void *stream);
+int gal_batch_destroy(gal_batch *b);
+
 /* ---- FFT schedule autotuning -------------------------------------------
  * Every FFT pass exists in NVAR = 3 compiled variants that differ in the
  * values each thread holds (16, 8 or 4: more threads per transform, more

@@ -32,8 +32,12 @@ from ._native import GalarioError, check
 __all__ = [
     "sweep", "sampleImage", "sampleProfile", "chi2Image", "chi2Profile", "spectrum",
     "sample_spectrum", "Dataset", "Workspace", "read_status", "timing", "GalarioError",
-    "version", "init", "autotune", "tune_get", "tune_set",
+    "version", "init", "autotune", "tune_get", "tune_set", "Batch", "profile_batch",
+    "JOB_IMAGE", "JOB_PROFILE",
 ]
+
+JOB_IMAGE = 0
+JOB_PROFILE = 1
 
 
 def _lib():
@@ -353,6 +357,77 @@ class Dataset:
                 float(inc), float(PA), float(dRA), float(dDec), _ptr(out), _ptr(wsb), wsb.numel(),
                 _stream(self.device)), "Dataset.sampleProfile")
         return torch.view_as_complex(out)
+
+
+# ----------------------------------------------------------------------------
+class Batch:
+    """A planned list of chi^2 jobs evaluated together (gal_batch_*).
+
+    ``jobs`` is a list of dicts with keys: ds (Dataset), kind (JOB_IMAGE or
+    JOB_PROFILE), Nxy, dxy, model (device tensor: image [Nxy, Nxy] or
+    profile [Nr]) and geo (device float64 tensor of 6 values: Rmin, dR, inc,
+    PA, dRA, dDec).  The kernels read model and geo at every ``chi2()`` call,
+    so update those tensors in place between calls; the plan (and any HIP
+    graph captured around ``chi2``) stays valid as long as they live."""
+
+    def __init__(self, jobs):
+        if not jobs:
+            raise ValueError("a batch needs at least one job")
+        self.jobs = list(jobs)
+        dev = self.jobs[0]["ds"].device
+        arr = (_native.GalJob * len(self.jobs))()
+        for i, j in enumerate(self.jobs):
+            ds = j["ds"]
+            m, geo = j["model"], j["geo"]
+            _arr(m, "model", ds.dtype, dev)
+            _arr(geo, "geo", torch.float64, dev, 6)
+            arr[i] = _native.GalJob(ds._h.value, int(j["kind"]), int(j["Nxy"]), float(j["dxy"]),
+                                    int(m.numel()) if j["kind"] == JOB_PROFILE else 0,
+                                    m.data_ptr(), geo.data_ptr())
+        self.device = dev
+        h = ctypes.c_void_p(0)
+        with torch.cuda.device(dev):
+            check(_lib().gal_batch_create(arr, len(self.jobs), ctypes.byref(h)), "Batch")
+        self._h = h
+        need = _lib().gal_batch_workspace_bytes(h)
+        self.ws = torch.zeros(int(need), dtype=torch.uint8, device=dev)
+        self.out = torch.empty(len(self.jobs), dtype=torch.float64, device=dev)
+
+    def info(self):
+        n, f, g = ctypes.c_int(0), ctypes.c_int(0), ctypes.c_int(0)
+        check(_lib().gal_batch_info(self._h, ctypes.byref(n), ctypes.byref(f), ctypes.byref(g)),
+              "gal_batch_info")
+        return {"jobs": n.value, "fft_groups": f.value, "sample_groups": g.value}
+
+    def chi2(self, out: torch.Tensor | None = None) -> torch.Tensor:
+        """chi^2 of every job (device float64 tensor [n]), on the current stream."""
+        res = self.out if out is None else out
+        with torch.cuda.device(self.device):
+            check(_lib().gal_batch_chi2(self._h, _ptr(res), _ptr(self.ws), self.ws.numel(),
+                                        _stream(self.device)), "Batch.chi2")
+        return res
+
+    def close(self):
+        if getattr(self, "_h", None) and self._h.value:
+            with torch.cuda.device(self.device):
+                _lib().gal_batch_destroy(self._h)
+            self._h = ctypes.c_void_p(0)
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+def profile_batch(ds: "Dataset", I: torch.Tensor, geo: torch.Tensor, Nxy: int, dxy: float) -> Batch:
+    """K profile jobs on one dataset: I [K, Nr] (dataset dtype), geo [K, 6]
+    float64 rows {Rmin, dR, inc, PA, dRA, dDec}; both updated in place by the
+    caller between evaluations."""
+    if I.dim() != 2 or geo.shape != (I.shape[0], 6):
+        raise ValueError("I must be [K, Nr] and geo [K, 6]")
+    return Batch([{"ds": ds, "kind": JOB_PROFILE, "Nxy": Nxy, "dxy": dxy, "model": I[k],
+                   "geo": geo[k]} for k in range(I.shape[0])])
 
 
 # ----------------------------------------------------------------------------

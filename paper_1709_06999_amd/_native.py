@@ -52,6 +52,11 @@ _SIG = {
     "gal_chi2Profile_ds": (I, [P, P, I, D, D, I, D, D, D, D, D, P, P, SZ, P]),
     "gal_sampleImage_ds": (I, [P, P, I, D, D, D, D, D, P, P, SZ, P]),
     "gal_sampleProfile_ds": (I, [P, P, I, D, D, I, D, D, D, D, D, P, P, SZ, P]),
+    "gal_batch_create": (I, [P, I, ctypes.POINTER(P)]),
+    "gal_batch_workspace_bytes": (SZ, [P]),
+    "gal_batch_info": (I, [P, ctypes.POINTER(I), ctypes.POINTER(I), ctypes.POINTER(I)]),
+    "gal_batch_chi2": (I, [P, P, P, SZ, P]),
+    "gal_batch_destroy": (I, [P]),
     "gal_autotune": (I, [I, D, P, ctypes.POINTER(I), ctypes.POINTER(D)]),
     "gal_tune_get": (I, [I, I, ctypes.POINTER(I)]),
     "gal_tune_set": (I, [I, I, ctypes.POINTER(I)]),
@@ -109,3 +114,10 @@ class GalarioError(RuntimeError):
 def check(rc: int, where: str):
     if rc != GAL_OK:
         raise GalarioError(rc, where)
+
+
+class GalJob(ctypes.Structure):
+    """Mirror of gal_job (include/galario_hip.h)."""
+    _fields_ = [("ds", ctypes.c_void_p), ("kind", ctypes.c_int), ("Nxy", ctypes.c_int),
+                ("dxy", ctypes.c_double), ("Nr", ctypes.c_int), ("model", ctypes.c_void_p),
+                ("geo", ctypes.c_void_p)]

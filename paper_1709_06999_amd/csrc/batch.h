@@ -1,0 +1,201 @@
+// batch.h -- many chi^2 evaluations in one set of launches.
+//
+// A batch is a fixed list of jobs (model + dataset + image size).  Its
+// structure is planned once on the host (gal_batch_create): jobs with the same
+// precision, kind and image size share the FFT launches (one block row per
+// job, blockIdx.y), and jobs on the same dataset, kind and image grid share
+// the sampling launch: a block loads its chunk of observations once and
+// evaluates every job of its group on it, so the uv data is read once per
+// group instead of once per job.  The per-job geometry (Rmin, dR, inc, PA,
+// dRA, dDec) and the model arrays are read from device memory at execution,
+// so one plan (and a HIP graph captured from it) serves every step of a
+// fitter that updates those buffers in place.
+#pragma once
+#include "kernels.h"
+
+namespace gal {
+
+constexpr int KMAX = 16;  // jobs sharing one pass over a dataset
+
+struct JobDesc {
+    const void *src;     // image [N*N] or profile [Nr], dataset precision
+    const double *geo;   // Rmin, dR, inc, PA, dRA, dDec
+    size_t spec_off;     // spectrum slot: byte offset in the workspace
+    size_t part_off;     // partial sums: byte offset in the workspace
+    int kind;            // 0 image, 1 profile
+    int N, Nr, Q, P, CS, Qe;
+    double dxy;
+};
+
+struct SGroup {          // jobs sharing one pass over a dataset
+    const void *u, *v, *re, *im, *w;
+    int64_t M;
+    int blk0, nblk;      // flattened block range of the group
+    int nj;
+    int jobs[KMAX];
+};
+
+__device__ __forceinline__ SweepArgs sweep_from_geo(const double *geo, int Nr, double dxy) {
+    SweepArgs a;
+    a.Nr = Nr;
+    a.Rmin = geo[0];
+    a.inv_dR = 1.0 / geo[1];
+    a.dxy = dxy;
+    a.inv_cos = 1.0 / cos(geo[2]);
+    a.pix_area = dxy * dxy;
+    a.tmax = (double)(Nr - 1);
+    return a;
+}
+
+__device__ __forceinline__ SampleArgs sample_from_job(const JobDesc &j, int64_t M) {
+    SampleArgs a;
+    a.M = M;
+    a.inv_du = (double)j.N * j.dxy;
+    sincos(j.geo[3], &a.spa, &a.cpa);
+    a.cinc = j.kind == 1 ? 1.0 : cos(j.geo[2]);
+    a.dRA = j.geo[4];
+    a.dDec = j.geo[5];
+    a.jmax = min(j.Q - 2, j.N / 2 - 1);
+    a.imin = -min(j.P, j.N / 2);
+    a.imax = min(j.P - 1, j.N / 2 - 2);
+    return a;
+}
+
+__device__ __forceinline__ Geom geom_of(const JobDesc &j) { return Geom{j.N, j.Q, j.P, j.CS}; }
+
+// ---- FFT stage: blockIdx.y selects the job in `list` ----------------------
+template <typename T, typename Cfg>
+__global__ __launch_bounds__(Cfg::NT) void kb_rows_img(const JobDesc *__restrict__ jobs,
+                                                       const int *__restrict__ list, char *ws) {
+    const JobDesc &j = jobs[list[blockIdx.y]];
+    rows_body<T, Cfg, false>((const T *)j.src, SweepArgs{}, geom_of(j),
+                             (c2<T> *)(ws + j.spec_off), xcd_remap(blockIdx.x, gridDim.x));
+}
+
+template <typename T, typename Cfg>
+__global__ __launch_bounds__(Cfg::NT) void kb_cols(const JobDesc *__restrict__ jobs,
+                                                   const int *__restrict__ list, char *ws) {
+    const JobDesc &j = jobs[list[blockIdx.y]];
+    cols_body<T, Cfg>(geom_of(j), (c2<T> *)(ws + j.spec_off), blockIdx.x);
+}
+
+template <typename T, typename Cfg>
+__global__ __launch_bounds__(Cfg::NT) void kb_rows_sym(const JobDesc *__restrict__ jobs,
+                                                       const int *__restrict__ list, char *ws) {
+    const JobDesc &j = jobs[list[blockIdx.y]];
+    const SweepArgs sw = sweep_from_geo(j.geo, j.Nr, j.dxy);
+    rows_sym_body<T, Cfg>((const T *)j.src, sw, geom_of(j), j.Qe, (T *)(ws + j.spec_off),
+                          xcd_remap(blockIdx.x, gridDim.x));
+}
+
+template <typename T, typename Cfg>
+__global__ __launch_bounds__(Cfg::NT) void kb_cols_sym(const JobDesc *__restrict__ jobs,
+                                                       const int *__restrict__ list, char *ws) {
+    const JobDesc &j = jobs[list[blockIdx.y]];
+    cols_sym_body<T, Cfg>(geom_of(j), j.Qe, (T *)(ws + j.spec_off), blockIdx.x);
+}
+
+// ---- sampling stage ------------------------------------------------------
+template <typename T>
+__device__ __forceinline__ double sample_real_at(const T *__restrict__ S, const Geom &g,
+                                                 const SampleArgs &a, double u, double v,
+                                                 bool &ok, double &Vre, double &Vim) {
+    const StencilR<T> st = locate_r<T>(S, g, a, u, v);
+    ok = st.ok;
+    if (!ok) {
+        Vre = __builtin_nan("");
+        Vim = __builtin_nan("");
+        return 0.0;
+    }
+    const T x0 = st.c0[0], x1 = st.c0[1], y0 = st.c0[g.CS], y1 = st.c0[g.CS + 1];
+    const double a00 = st.swap ? x1 : x0, a10 = st.swap ? x0 : x1;
+    const double a01 = st.swap ? y1 : y0, a11 = st.swap ? y0 : y1;
+    const double s = st.s, t = st.t;
+    const double b = (1.0 - t) * ((1.0 - s) * a00 + s * a01) + t * ((1.0 - s) * a10 + s * a11);
+    double sn, cs;
+    sincospi(2.0 * (u * a.dRA + v * a.dDec), &sn, &cs);
+    Vre = a.cinc * b * cs;
+    Vim = a.cinc * b * sn;
+    return 0.0;
+}
+
+// Block -> group by binary search over the groups' first blocks; each thread
+// keeps SAMPLE_PPT points in registers and evaluates every job of the group.
+template <typename T, bool REAL>
+__global__ __launch_bounds__(SAMPLE_NT) void kb_sample_chi2(const JobDesc *__restrict__ jobs,
+                                                            const SGroup *__restrict__ groups,
+                                                            int ngroups, char *ws) {
+    constexpr int PPT = SAMPLE_PPT;
+    __shared__ double red[SAMPLE_NT / 64];
+    int lo = 0, hi = ngroups - 1;
+    while (lo < hi) {
+        const int mid = (lo + hi + 1) >> 1;
+        if (groups[mid].blk0 <= (int)blockIdx.x) lo = mid;
+        else hi = mid - 1;
+    }
+    const SGroup &G = groups[lo];
+    const int chunk = (int)blockIdx.x - G.blk0;
+    const int64_t base = (int64_t)chunk * (SAMPLE_NT * PPT) + threadIdx.x;
+    const T *u = (const T *)G.u, *v = (const T *)G.v;
+    const T *re = (const T *)G.re, *im = (const T *)G.im, *w = (const T *)G.w;
+    double uu[PPT], vv[PPT], rr[PPT], ii[PPT], ww[PPT];
+#pragma unroll
+    for (int p = 0; p < PPT; ++p) {
+        const int64_t k = base + p * SAMPLE_NT;
+        const bool in = k < G.M;
+        uu[p] = in ? (double)u[k] : 0.0;
+        vv[p] = in ? (double)v[k] : 0.0;
+        rr[p] = in ? (double)re[k] : 0.0;
+        ii[p] = in ? (double)im[k] : 0.0;
+        ww[p] = in ? (double)w[k] : 0.0;  // points past M weigh nothing
+    }
+    Control *ctl = (Control *)ws;
+    bool bad = false;
+    for (int jj = 0; jj < G.nj; ++jj) {
+        const JobDesc &J = jobs[G.jobs[jj]];
+        const SampleArgs a = sample_from_job(J, G.M);
+        const Geom g = geom_of(J);
+        double acc = 0.0;
+#pragma unroll
+        for (int p = 0; p < PPT; ++p) {
+            double Vre, Vim;
+            bool ok;
+            if constexpr (REAL) {
+                sample_real_at<T>((const T *)(ws + J.spec_off), g, a, uu[p], vv[p], ok, Vre, Vim);
+            } else {
+                const c2<T> *S = (const c2<T> *)(ws + J.spec_off);
+                const Stencil<T> st = locate<T>(S, g, a, uu[p], vv[p]);
+                ok = st.ok;
+                finish<T>(st, st.c0[0], st.c0[1], st.c0[g.CS], st.c0[g.CS + 1], a, uu[p], vv[p],
+                          Vre, Vim);
+            }
+            const bool in = base + p * SAMPLE_NT < G.M;
+            bad |= in && !ok;
+            if (in) {
+                const double dr = Vre - rr[p], di = Vim - ii[p];
+                acc += ww[p] * (dr * dr + di * di);
+            }
+        }
+        const double bs = block_sum(acc, red);
+        if (threadIdx.x == 0) ((double *)(ws + J.part_off))[chunk] = bs;
+    }
+    if (bad) ctl->flag = 1;
+}
+
+// chi2[j] = sum of job j's partials in index order (one block per job)
+__global__ __launch_bounds__(SAMPLE_NT) void kb_reduce(const JobDesc *__restrict__ jobs,
+                                                       const SGroup *__restrict__ groups,
+                                                       const int *__restrict__ job_group,
+                                                       const char *ws, double *__restrict__ chi2) {
+    __shared__ double red[SAMPLE_NT / 64];
+    const int j = blockIdx.x;
+    const JobDesc &J = jobs[j];
+    const int n = groups[job_group[j]].nblk;
+    const double *part = (const double *)(ws + J.part_off);
+    double s = 0.0;
+    for (int k = threadIdx.x; k < n; k += SAMPLE_NT) s += part[k];
+    const double tot = block_sum(s, red);
+    if (threadIdx.x == 0) chi2[j] = tot;
+}
+
+}  // namespace gal

@@ -166,6 +166,13 @@ struct FFTCfg {
     static constexpr int LS = (B > 1) ? L + 1 : L;
     static_assert(E >= 1 && (B * L) % NT == 0, "bad FFT configuration");
     static_assert(E % ((L < RMAX) ? L : RMAX) == 0, "E must hold whole butterflies");
+    // LDS slot of element e of sequence b.  The Stockham write of the first
+    // pass puts lane j at e = R j + t: a stride of R 16-byte elements that
+    // sends every lane of a wave to the same banks.  XOR-ing the low three
+    // bits of e (one 128-byte bank row holds 8 elements of 16 bytes) with
+    // bits 4..6 gives 8 consecutive lanes 8 different bank groups in those
+    // writes and keeps contiguous runs contiguous, without padding memory.
+    static __device__ __forceinline__ int at(int b, int e) { return b * LS + (e ^ ((e >> 4) & 7)); }
 };
 
 // Load the inputs of the pass with stride NS from LDS into registers.
@@ -179,13 +186,13 @@ __device__ __forceinline__ void fft_gather(c2<T> *v, const c2<T> *lds, int tid) 
         const int g = tid + i * NT;
         const int b = g / LR, j = g % LR;
 #pragma unroll
-        for (int t = 0; t < R; ++t) v[i * R + t] = lds[b * Cfg::LS + j + t * LR];
+        for (int t = 0; t < R; ++t) v[i * R + t] = lds[Cfg::at(b, j + t * LR)];
     }
 }
 
 // Run the passes from stride NS to the end; v holds this pass's inputs.  The
-// natural-order result is left in LDS (row b at lds + b * LS), followed by a
-// barrier.  `tw` is the twiddle table.
+// natural-order result is left in LDS (element e of row b at Cfg::at(b, e)),
+// followed by a barrier.  `tw` is the twiddle table.
 template <typename Cfg, int NS, typename T>
 __device__ __forceinline__ void fft_passes(c2<T> *v, c2<T> *lds, const c2<T> *__restrict__ tw,
                                            int tid) {
@@ -210,9 +217,9 @@ __device__ __forceinline__ void fft_passes(c2<T> *v, c2<T> *lds, const c2<T> *__
         const int g = tid + i * NT;
         const int b = g / LR, j = g % LR;
         const int k = j % NS;
-        const int base = b * Cfg::LS + (j / NS) * NS * R + k;
+        const int base = (j / NS) * NS * R + k;
 #pragma unroll
-        for (int t = 0; t < R; ++t) lds[base + t * NS] = v[i * R + t];
+        for (int t = 0; t < R; ++t) lds[Cfg::at(b, base + t * NS)] = v[i * R + t];
     }
     __syncthreads();
     if constexpr (NS * R < L) {

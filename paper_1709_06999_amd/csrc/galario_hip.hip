@@ -18,6 +18,7 @@
 #include <vector>
 
 #include "../../include/galario_hip.h"
+#include "batch.h"
 #include "kernels.h"
 
 namespace gal {
@@ -307,6 +308,83 @@ static int run_fft(int kind, const FftJob<T> &j) {
 }
 
 // ---------------------------------------------------------------------------
+// batched FFT passes: one launch per (precision, kind, image size) group,
+// blockIdx.y = job of the group
+struct FftJobB {
+    const JobDesc *jobs;
+    const int *list;
+    int count;
+    int maxQ, maxQe;
+    char *ws;
+    hipStream_t s;
+};
+using FftFnB = int (*)(const FftJobB &);
+
+template <typename T, int N, int VAR>
+static int runb_rows_img(const FftJobB &j) {
+    constexpr int B = rows_B(N);
+    using C = CfgE<T, N / 2, B, var_E(VAR)>;
+    return launch("kb_rows_image", kb_rows_img<T, C>, dim3(N / B, j.count), dim3(C::NT), j.s,
+                  j.jobs, j.list, j.ws);
+}
+template <typename T, int N, int VAR>
+static int runb_cols(const FftJobB &j) {
+    constexpr int B = cols_B(N);
+    using C = CfgE<T, N, B, var_E(VAR)>;
+    return launch("kb_cols", kb_cols<T, C>, dim3((j.maxQ + B - 1) / B, j.count), dim3(C::NT), j.s,
+                  j.jobs, j.list, j.ws);
+}
+template <typename T, int N, int VAR>
+static int runb_rows_sym(const FftJobB &j) {
+    constexpr int B = cols_B(N);
+    using C = CfgE<T, N, B, var_E(VAR)>;
+    return launch("kb_rows_sym", kb_rows_sym<T, C>, dim3((N / 4 + 1 + B - 1) / B, j.count),
+                  dim3(C::NT), j.s, j.jobs, j.list, j.ws);
+}
+template <typename T, int N, int VAR>
+static int runb_cols_sym(const FftJobB &j) {
+    constexpr int B = cols_B(N);
+    using C = CfgE<T, N, B, var_E(VAR)>;
+    return launch("kb_cols_sym", kb_cols_sym<T, C>, dim3((j.maxQe / 2 + B - 1) / B, j.count),
+                  dim3(C::NT), j.s, j.jobs, j.list, j.ws);
+}
+
+template <typename T, int N>
+struct VarTableB {
+    static constexpr bool many = N >= 256;
+    template <int V>
+    static FftFnB pick(int kind) {
+        switch (kind) {
+            case K_ROWS_IMG: return runb_rows_img<T, N, V>;
+            case K_COLS: return runb_cols<T, N, V>;
+            case K_ROWS_SYM: return runb_rows_sym<T, N, V>;
+            default: return runb_cols_sym<T, N, V>;
+        }
+    }
+    static FftFnB get(int kind, int var) {
+        if (!many || var == 0) return pick<0>(kind);
+        return var == 1 ? pick<(many ? 1 : 0)>(kind) : pick<(many ? 2 : 0)>(kind);
+    }
+};
+
+template <typename T>
+static FftFnB fft_fn_b(int N, int kind, int var) {
+    switch (N) {
+        case 16: return VarTableB<T, 16>::get(kind, var);
+        case 32: return VarTableB<T, 32>::get(kind, var);
+        case 64: return VarTableB<T, 64>::get(kind, var);
+        case 128: return VarTableB<T, 128>::get(kind, var);
+        case 256: return VarTableB<T, 256>::get(kind, var);
+        case 512: return VarTableB<T, 512>::get(kind, var);
+        case 1024: return VarTableB<T, 1024>::get(kind, var);
+        case 2048: return VarTableB<T, 2048>::get(kind, var);
+        case 4096: return VarTableB<T, 4096>::get(kind, var);
+        case 8192: return VarTableB<T, 8192>::get(kind, var);
+        default: return nullptr;
+    }
+}
+
+// ---------------------------------------------------------------------------
 // workspace: [control 256 B][partials][XT]
 static size_t align256(size_t x) { return (x + 255) & ~(size_t)255; }
 
@@ -562,6 +640,32 @@ struct gal_dataset {
     void *buf;      // one allocation: u, v, re, im, w, perm (locality order)
     void *u, *v, *re, *im, *w;
     int32_t *perm;  // perm[k] = registration index of stored point k
+};
+
+// a planned batch (see batch.h)
+struct gal_batch {
+    int device = 0;
+    int n = 0;
+    std::vector<JobDesc> jobs;
+    std::vector<SGroup> groups;    // sorted by sample class
+    std::vector<int> job_group;    // job -> group
+    struct FGroup {
+        int prec, kind, N, list_off, count, maxQ, maxQe;
+    };
+    std::vector<FGroup> fgroups;
+    std::vector<int> lists;
+    struct SClass {
+        int prec;
+        bool real;
+        int group_off, count, blocks;
+    };
+    std::vector<SClass> sclasses;
+    size_t ws_need = 0;
+    void *dtab = nullptr;          // device copy of jobs | groups | lists | job_group
+    JobDesc *d_jobs = nullptr;
+    SGroup *d_groups = nullptr;
+    int *d_lists = nullptr;
+    int *d_job_group = nullptr;
 };
 
 // The definitions below take their C linkage from the declarations in the
@@ -1012,6 +1116,226 @@ int gal_sampleProfile_ds_f(const gal_dataset *ds, const float *I, int Nr, double
                            float *vis, void *ws, size_t ws_bytes_, void *stream) {
     return ds_call<float>(ds, I, true, Nr, Rmin, dR, Nxy, dxy, inc, PA, dRA, dDec, vis, nullptr, ws,
                           ws_bytes_, stream);
+}
+
+// ---- batches --------------------------------------------------------------
+int gal_batch_create(const gal_job *jobs, int n, gal_batch **out) {
+    if (!out || (n > 0 && !jobs)) return fail(GAL_ERR_NULL, "NULL argument");
+    *out = nullptr;
+    if (n < 1) return fail(GAL_ERR_SIZE, "a batch needs at least one job");
+    int rc = ensure_init();
+    if (rc) return rc;
+    gal_batch *b = new gal_batch();
+    GAL_HIP(hipGetDevice(&b->device));
+    b->n = n;
+    b->jobs.resize(n);
+    b->job_group.assign(n, -1);
+    // per-job checks and geometry
+    for (int i = 0; i < n; ++i) {
+        const gal_job &J = jobs[i];
+        auto bad = [&](int code, const char *what) {
+            delete b;
+            return fail(code, "job %d: %s", i, what);
+        };
+        if (!J.ds || !J.model || !J.geo) return bad(GAL_ERR_NULL, "NULL dataset, model or geo");
+        if (!J.ds->re) return bad(GAL_ERR_UNSUPPORTED, "dataset holds no observations");
+        if (J.kind != 0 && J.kind != 1) return bad(GAL_ERR_UNSUPPORTED, "kind must be 0 or 1");
+        if (!pow2_in_range(J.Nxy)) return bad(GAL_ERR_SIZE, "Nxy unsupported");
+        if (!(J.dxy > 0.0) || !std::isfinite(J.dxy)) return bad(GAL_ERR_SCALAR, "dxy must be > 0");
+        if (J.kind == 1 && J.Nr < 2) return bad(GAL_ERR_SIZE, "Nr < 2");
+        if (J.ds->device != b->device) return bad(GAL_ERR_UNSUPPORTED, "dataset on another device");
+        const double du = 1.0 / ((double)J.Nxy * J.dxy);
+        if (!(J.ds->rho_max < ((double)(J.Nxy / 2) - 1.0) * du))
+            return bad(GAL_ERR_UV_RANGE, "dataset rho_max reaches beyond the half spectrum");
+        const Geom g = geom_pruned(J.Nxy, J.dxy, J.ds->rho_max);
+        JobDesc &d = b->jobs[i];
+        d.src = J.model;
+        d.geo = J.geo;
+        d.kind = J.kind;
+        d.N = J.Nxy;
+        d.Nr = J.kind == 1 ? J.Nr : 0;
+        d.Q = g.Q;
+        d.P = g.P;
+        d.Qe = (g.Q + 1) & ~1;
+        d.CS = J.kind == 1 ? J.Nxy / 2 + 2 : g.CS;
+        d.dxy = J.dxy;
+    }
+    // sample groups: same dataset, kind and grid, at most KMAX jobs each
+    for (int i = 0; i < n; ++i) {
+        if (b->job_group[i] >= 0) continue;
+        const gal_job &Ji = jobs[i];
+        SGroup G{};
+        G.u = Ji.ds->u;
+        G.v = Ji.ds->v;
+        G.re = Ji.ds->re;
+        G.im = Ji.ds->im;
+        G.w = Ji.ds->w;
+        G.M = Ji.ds->M;
+        G.nj = 0;
+        for (int k = i; k < n && G.nj < KMAX; ++k) {
+            const gal_job &Jk = jobs[k];
+            if (b->job_group[k] >= 0 || Jk.ds != Ji.ds || Jk.kind != Ji.kind ||
+                Jk.Nxy != Ji.Nxy || Jk.dxy != Ji.dxy)
+                continue;
+            b->job_group[k] = (int)b->groups.size();
+            G.jobs[G.nj++] = k;
+        }
+        G.nblk = (int)sample_blocks(G.M);
+        b->groups.push_back(G);
+    }
+    // order groups by sample class (precision, real spectrum) and number blocks
+    std::vector<int> order(b->groups.size());
+    for (size_t g = 0; g < order.size(); ++g) order[g] = (int)g;
+    auto cls = [&](int g) {
+        const JobDesc &d = b->jobs[b->groups[g].jobs[0]];
+        const int prec = jobs[b->groups[g].jobs[0]].ds->precision;
+        return (prec == 8 ? 0 : 2) + (d.kind == 1 ? 1 : 0);
+    };
+    std::stable_sort(order.begin(), order.end(), [&](int a, int c) { return cls(a) < cls(c); });
+    std::vector<SGroup> sorted;
+    std::vector<int> remap(order.size());
+    for (size_t k = 0; k < order.size(); ++k) {
+        remap[order[k]] = (int)k;
+        sorted.push_back(b->groups[order[k]]);
+    }
+    b->groups.swap(sorted);
+    for (int i = 0; i < n; ++i) b->job_group[i] = remap[b->job_group[i]];
+    for (size_t g = 0; g < b->groups.size(); ++g) {
+        const int c = cls((int)g);
+        if (b->sclasses.empty() || (b->sclasses.back().prec == (c < 2 ? 8 : 4) &&
+                                    b->sclasses.back().real == ((c & 1) == 1)) == false) {
+            b->sclasses.push_back({c < 2 ? 8 : 4, (c & 1) == 1, (int)g, 0, 0});
+        }
+        gal_batch::SClass &sc = b->sclasses.back();
+        b->groups[g].blk0 = sc.blocks;
+        sc.blocks += b->groups[g].nblk;
+        sc.count += 1;
+    }
+    // FFT groups: same precision, kind and size
+    for (int i = 0; i < n; ++i) {
+        const int prec = jobs[i].ds->precision;
+        bool found = false;
+        for (auto &f : b->fgroups)
+            if (f.prec == prec && f.kind == jobs[i].kind && f.N == jobs[i].Nxy) found = true;
+        if (found) continue;
+        gal_batch::FGroup f{prec, jobs[i].kind, jobs[i].Nxy, (int)b->lists.size(), 0, 0, 0};
+        for (int k = i; k < n; ++k)
+            if (jobs[k].ds->precision == prec && jobs[k].kind == f.kind && jobs[k].Nxy == f.N) {
+                b->lists.push_back(k);
+                f.count += 1;
+                f.maxQ = max_c(f.maxQ, b->jobs[k].Q);
+                f.maxQe = max_c(f.maxQe, b->jobs[k].Qe);
+            }
+        b->fgroups.push_back(f);
+    }
+    // workspace: control | partials per job | spectrum slot per job
+    size_t off = 256;
+    for (int i = 0; i < n; ++i) {
+        b->jobs[i].part_off = off;
+        off += align256((size_t)b->groups[b->job_group[i]].nblk * sizeof(double));
+    }
+    for (int i = 0; i < n; ++i) {
+        const JobDesc &d = b->jobs[i];
+        const size_t el = (size_t)jobs[i].ds->precision;
+        const size_t bytes = d.kind == 1 ? (size_t)d.Qe * d.CS * el : (size_t)d.Q * d.CS * 2 * el;
+        b->jobs[i].spec_off = off;
+        off += align256(bytes);
+    }
+    b->ws_need = off;
+    // device tables
+    const size_t s1 = align256(sizeof(JobDesc) * n);
+    const size_t s2 = align256(sizeof(SGroup) * b->groups.size());
+    const size_t s3 = align256(sizeof(int) * b->lists.size());
+    const size_t s4 = align256(sizeof(int) * n);
+    if (hipMalloc(&b->dtab, s1 + s2 + s3 + s4) != hipSuccess) {
+        delete b;
+        return fail(GAL_ERR_WORKSPACE, "out of device memory for a batch table");
+    }
+    char *p = (char *)b->dtab;
+    b->d_jobs = (JobDesc *)p;
+    b->d_groups = (SGroup *)(p + s1);
+    b->d_lists = (int *)(p + s1 + s2);
+    b->d_job_group = (int *)(p + s1 + s2 + s3);
+    bool ok = hipMemcpy(b->d_jobs, b->jobs.data(), sizeof(JobDesc) * n, hipMemcpyHostToDevice) ==
+                  hipSuccess &&
+              hipMemcpy(b->d_groups, b->groups.data(), sizeof(SGroup) * b->groups.size(),
+                        hipMemcpyHostToDevice) == hipSuccess &&
+              hipMemcpy(b->d_lists, b->lists.data(), sizeof(int) * b->lists.size(),
+                        hipMemcpyHostToDevice) == hipSuccess &&
+              hipMemcpy(b->d_job_group, b->job_group.data(), sizeof(int) * n,
+                        hipMemcpyHostToDevice) == hipSuccess;
+    if (!ok) {
+        (void)hipFree(b->dtab);
+        delete b;
+        return fail(GAL_ERR_HIP, "batch table upload failed");
+    }
+    *out = b;
+    return GAL_OK;
+}
+
+size_t gal_batch_workspace_bytes(const gal_batch *b) { return b ? b->ws_need : 0; }
+
+int gal_batch_info(const gal_batch *b, int *n_jobs, int *n_fft_groups, int *n_sample_groups) {
+    if (!b) return fail(GAL_ERR_NULL, "NULL batch");
+    if (n_jobs) *n_jobs = b->n;
+    if (n_fft_groups) *n_fft_groups = (int)b->fgroups.size();
+    if (n_sample_groups) *n_sample_groups = (int)b->groups.size();
+    return GAL_OK;
+}
+
+template <typename T>
+static int batch_fft(const gal_batch *b, const gal_batch::FGroup &f, char *ws, hipStream_t s) {
+    FftJobB j{b->d_jobs, b->d_lists + f.list_off, f.count, f.maxQ, f.maxQe, ws, s};
+    const int k1 = f.kind == 1 ? K_ROWS_SYM : K_ROWS_IMG;
+    const int k2 = f.kind == 1 ? K_COLS_SYM : K_COLS;
+    FftFnB r = fft_fn_b<T>(f.N, k1, chosen_var<T>(f.N, k1));
+    FftFnB c = fft_fn_b<T>(f.N, k2, chosen_var<T>(f.N, k2));
+    if (!r || !c) return fail(GAL_ERR_SIZE, "Nxy=%d unsupported", f.N);
+    int rc = r(j);
+    if (rc) return rc;
+    return c(j);
+}
+
+int gal_batch_chi2(const gal_batch *b, double *chi2, void *ws, size_t ws_bytes_, void *stream) {
+    if (!b || !chi2 || !ws) return fail(GAL_ERR_NULL, "NULL argument");
+    if (ws_bytes_ < b->ws_need)
+        return fail(GAL_ERR_WORKSPACE, "workspace of %zu bytes, need %zu", ws_bytes_, b->ws_need);
+    hipStream_t s = (hipStream_t)stream;
+    char *w = (char *)ws;
+    int rc = GAL_OK;
+    for (const auto &f : b->fgroups) {
+        rc = f.prec == 8 ? batch_fft<double>(b, f, w, s) : batch_fft<float>(b, f, w, s);
+        if (rc) return rc;
+    }
+    for (const auto &c : b->sclasses) {
+        const SGroup *g = b->d_groups + c.group_off;
+        const dim3 grid(c.blocks), blk(SAMPLE_NT);
+        if (c.prec == 8)
+            rc = c.real ? launch("kb_sample_sym_chi2", kb_sample_chi2<double, true>, grid, blk, s,
+                                 b->d_jobs, g, c.count, w)
+                        : launch("kb_sample_chi2", kb_sample_chi2<double, false>, grid, blk, s,
+                                 b->d_jobs, g, c.count, w);
+        else
+            rc = c.real ? launch("kb_sample_sym_chi2", kb_sample_chi2<float, true>, grid, blk, s,
+                                 b->d_jobs, g, c.count, w)
+                        : launch("kb_sample_chi2", kb_sample_chi2<float, false>, grid, blk, s,
+                                 b->d_jobs, g, c.count, w);
+        if (rc) return rc;
+    }
+    return launch("kb_reduce", kb_reduce, dim3(b->n), dim3(SAMPLE_NT), s, b->d_jobs, b->d_groups,
+                  b->d_job_group, w, chi2);
+}
+
+int gal_batch_destroy(gal_batch *b) {
+    if (!b) return GAL_OK;
+    int cur = 0;
+    GAL_HIP(hipGetDevice(&cur));
+    if (cur != b->device) GAL_HIP(hipSetDevice(b->device));
+    hipError_t e = hipFree(b->dtab);
+    if (cur != b->device) (void)hipSetDevice(cur);
+    delete b;
+    if (e != hipSuccess) return fail(GAL_ERR_HIP, "hipFree: %s", hipGetErrorString(e));
+    return GAL_OK;
 }
 
 // ---- autotuning ----------------------------------------------------------

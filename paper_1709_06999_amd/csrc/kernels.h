@@ -79,15 +79,15 @@ __device__ __forceinline__ double sweep_pixel(const T *__restrict__ I, int N, in
 //   X[q] = (Z[q] + conj Z[L-q]) / 2 - i W_N^q (Z[q] - conj Z[L-q]) / 2.
 // Output XT[q * CS + r] = (-1)^q X_r[q] for q < Q.
 template <typename T, typename Cfg, bool PROFILE>
-__global__ __launch_bounds__(Cfg::NT) void k_rows(const T *__restrict__ src, SweepArgs sw,
-                                                  Geom g, c2<T> *__restrict__ XT) {
+__device__ __forceinline__ void rows_body(const T *__restrict__ src, const SweepArgs &sw,
+                                          const Geom &g, c2<T> *__restrict__ XT, int blk) {
     constexpr int L = Cfg::L, B = Cfg::B, NT = Cfg::NT, E = Cfg::E;
     constexpr int N = 2 * L;
     constexpr int R0 = pass_radix(L, 1, Cfg::RMAX);
     constexpr int LR = L / R0;
     __shared__ c2<T> lds[B * Cfg::LS];
     const int tid = threadIdx.x;
-    const int r0 = xcd_remap(blockIdx.x, gridDim.x) * B;
+    const int r0 = blk * B;
 
     c2<T> v[E];
 #pragma unroll
@@ -113,8 +113,8 @@ __global__ __launch_bounds__(Cfg::NT) void k_rows(const T *__restrict__ src, Swe
     const T half = T(0.5);
     for (int idx = tid; idx < g.Q * B; idx += NT) {
         const int q = idx / B, b = idx % B;
-        const c2<T> zk = lds[b * Cfg::LS + (q & (L - 1))];
-        const c2<T> zc = cconj(lds[b * Cfg::LS + ((L - q) & (L - 1))]);
+        const c2<T> zk = lds[Cfg::at(b, q & (L - 1))];
+        const c2<T> zc = cconj(lds[Cfg::at(b, (L - q) & (L - 1))]);
         const c2<T> s = cadd(zk, zc);
         const c2<T> d = cmul(wN[q], csub(zk, zc));
         c2<T> X = {half * (s.x + d.y), half * (s.y - d.x)};
@@ -123,18 +123,25 @@ __global__ __launch_bounds__(Cfg::NT) void k_rows(const T *__restrict__ src, Swe
     }
 }
 
+template <typename T, typename Cfg, bool PROFILE>
+__global__ __launch_bounds__(Cfg::NT) void k_rows(const T *__restrict__ src, SweepArgs sw,
+                                                  Geom g, c2<T> *__restrict__ XT) {
+    rows_body<T, Cfg, PROFILE>(src, sw, g, XT, xcd_remap(blockIdx.x, gridDim.x));
+}
+
 // ---------------------------------------------------------------------------
 // Column pass, in place.  Block of B columns q0..q0+B-1, each a length-N
 // complex FFT over the rows; output rows i in [0, 2P] hold p~ = i - P with
 // sign (-1)^p~.
 template <typename T, typename Cfg>
-__global__ __launch_bounds__(Cfg::NT) void k_cols(Geom g, c2<T> *__restrict__ XT) {
+__device__ __forceinline__ void cols_body(const Geom &g, c2<T> *__restrict__ XT, int blk) {
     constexpr int L = Cfg::L, B = Cfg::B, NT = Cfg::NT, E = Cfg::E;
     constexpr int R0 = pass_radix(L, 1, Cfg::RMAX);
     constexpr int LR = L / R0;
     __shared__ c2<T> lds[B * Cfg::LS];
     const int tid = threadIdx.x;
-    const int q0 = blockIdx.x * B;
+    const int q0 = blk * B;
+    if (q0 >= g.Q) return;
 
     c2<T> v[E];
 #pragma unroll
@@ -157,10 +164,15 @@ __global__ __launch_bounds__(Cfg::NT) void k_cols(Geom g, c2<T> *__restrict__ XT
         if (q >= g.Q) continue;
         const int pt = i - g.P;
         const int p = pt < 0 ? pt + L : pt;
-        c2<T> X = lds[b * Cfg::LS + p];
+        c2<T> X = lds[Cfg::at(b, p)];
         if (pt & 1) X = {-X.x, -X.y};
         XT[(size_t)q * g.CS + i] = X;
     }
+}
+
+template <typename T, typename Cfg>
+__global__ __launch_bounds__(Cfg::NT) void k_cols(Geom g, c2<T> *__restrict__ XT) {
+    cols_body<T, Cfg>(g, XT, blockIdx.x);
 }
 
 // ---------------------------------------------------------------------------
@@ -180,23 +192,23 @@ __global__ __launch_bounds__(Cfg::NT) void k_cols(Geom g, c2<T> *__restrict__ XT
 // shift sign (-1)^q) for r in [0, N/2], q in [0, Qe) (Qe = Q rounded up to
 // even so that the column pass can pair columns).
 template <typename T, typename Cfg>
-__global__ __launch_bounds__(Cfg::NT) void k_rows_sym(const T *__restrict__ I, SweepArgs sw,
-                                                      Geom g, int Qe, T *__restrict__ XR) {
+__device__ __forceinline__ void rows_sym_body(const T *__restrict__ I, const SweepArgs &sw,
+                                              const Geom &g, int Qe, T *__restrict__ XR, int blk) {
     constexpr int L = Cfg::L, B = Cfg::B, NT = Cfg::NT, E = Cfg::E;
     constexpr int N = L;
     constexpr int R0 = pass_radix(L, 1, Cfg::RMAX);
     constexpr int LR = L / R0;
     __shared__ c2<T> lds[B * Cfg::LS];
     const int tid = threadIdx.x;
-    const int m0 = xcd_remap(blockIdx.x, gridDim.x) * B;
+    const int m0 = blk * B;
 
     // columns c and N - c hold the same pixel: sweep c in [0, N/2] into LDS
     constexpr int NH = N / 2 + 1;
     for (int idx = tid; idx < B * NH; idx += NT) {
         const int b = idx / NH, c = idx % NH;
         const int r = 2 * (m0 + b);  // rows r, r + 1 (r + 1 < N)
-        lds[b * Cfg::LS + c] = c2<T>{(T)sweep_pixel(I, N, r, c, sw),
-                                     (T)sweep_pixel(I, N, r + 1, c, sw)};
+        lds[Cfg::at(b, c)] = c2<T>{(T)sweep_pixel(I, N, r, c, sw),
+                                   (T)sweep_pixel(I, N, r + 1, c, sw)};
     }
     __syncthreads();
     c2<T> v[E];
@@ -207,7 +219,7 @@ __global__ __launch_bounds__(Cfg::NT) void k_rows_sym(const T *__restrict__ I, S
 #pragma unroll
         for (int t = 0; t < R0; ++t) {
             const int n = j + t * LR;
-            v[i * R0 + t] = lds[b * Cfg::LS + (n <= N / 2 ? n : N - n)];
+            v[i * R0 + t] = lds[Cfg::at(b, n <= N / 2 ? n : N - n)];
         }
     }
     fft_passes<Cfg, 1>(v, lds, twiddles<T>(), tid);
@@ -217,25 +229,32 @@ __global__ __launch_bounds__(Cfg::NT) void k_rows_sym(const T *__restrict__ I, S
         const int q = idx / RB, rr = idx % RB;
         const int r = 2 * m0 + rr;
         if (r > N / 2) continue;
-        const c2<T> z = lds[(rr >> 1) * Cfg::LS + q];
+        const c2<T> z = lds[Cfg::at(rr >> 1, q)];
         T x = (rr & 1) ? z.y : z.x;
         if (q & 1) x = -x;
         XR[(size_t)q * g.CS + r] = x;
     }
 }
 
+template <typename T, typename Cfg>
+__global__ __launch_bounds__(Cfg::NT) void k_rows_sym(const T *__restrict__ I, SweepArgs sw,
+                                                      Geom g, int Qe, T *__restrict__ XR) {
+    rows_sym_body<T, Cfg>(I, sw, g, Qe, XR, xcd_remap(blockIdx.x, gridDim.x));
+}
+
 // Column pass of a swept profile, in place: pair of columns (2m, 2m+1),
 // input over r in [0, N) from the stored half r' = min(r, N - r); output
 // SR[q * CS + p] = (-1)^p G[p][q] for p in [0, P].
 template <typename T, typename Cfg>
-__global__ __launch_bounds__(Cfg::NT) void k_cols_sym(Geom g, int Qe, T *__restrict__ XR) {
+__device__ __forceinline__ void cols_sym_body(const Geom &g, int Qe, T *__restrict__ XR, int blk) {
     constexpr int L = Cfg::L, B = Cfg::B, NT = Cfg::NT, E = Cfg::E;
     constexpr int N = L;
     constexpr int R0 = pass_radix(L, 1, Cfg::RMAX);
     constexpr int LR = L / R0;
     __shared__ c2<T> lds[B * Cfg::LS];
     const int tid = threadIdx.x;
-    const int m0 = blockIdx.x * B;
+    const int m0 = blk * B;
+    if (2 * m0 >= Qe) return;
 
     c2<T> v[E];
 #pragma unroll
@@ -262,11 +281,16 @@ __global__ __launch_bounds__(Cfg::NT) void k_cols_sym(Geom g, int Qe, T *__restr
         const int cb = idx / NP, p = idx % NP;
         const int q = 2 * m0 + cb;
         if (q >= Qe) continue;
-        const c2<T> z = lds[(cb >> 1) * Cfg::LS + p];
+        const c2<T> z = lds[Cfg::at(cb >> 1, p)];
         T x = (cb & 1) ? z.y : z.x;
         if (p & 1) x = -x;
         XR[(size_t)q * g.CS + p] = x;
     }
+}
+
+template <typename T, typename Cfg>
+__global__ __launch_bounds__(Cfg::NT) void k_cols_sym(Geom g, int Qe, T *__restrict__ XR) {
+    cols_sym_body<T, Cfg>(g, Qe, XR, blockIdx.x);
 }
 
 // ---------------------------------------------------------------------------

@@ -1,0 +1,111 @@
+"""Batched evaluation: every job of a batch equals its one-at-a-time call and
+the oracle; mixed kinds, sizes, datasets and precisions in one plan; the plan
+reads updated model and geometry buffers at every execution."""
+import numpy as np
+import pytest
+
+import oracle
+import workloads as wl
+from gpu_util import chi2_bound, device, rounded, t
+
+pytestmark = pytest.mark.gpu
+
+
+def _gal():
+    import paper_1709_06999_amd as gal
+
+    return gal
+
+
+def _geo(case):
+    return [case.Rmin, case.dR, case.inc, case.PA, case.dRA, case.dDec]
+
+
+def _obs(case, dtype):
+    if case.kind == "image":
+        Vo = oracle.sampleImage(rounded(case.image, dtype), case.dxy, rounded(case.u, dtype),
+                                rounded(case.v, dtype), case.PA, case.dRA, case.dDec, case.inc)
+    else:
+        Vo = oracle.sampleProfile(rounded(case.I, dtype), case.Rmin, case.dR, case.N, case.dxy,
+                                  rounded(case.u, dtype), rounded(case.v, dtype), case.inc, case.PA,
+                                  case.dRA, case.dDec)
+    return Vo
+
+
+def test_walkers_on_one_dataset_match_single_calls_and_oracle():
+    dev = device()
+    gal = _gal()
+    import torch
+
+    d = np.float64
+    base = wl.random_case(256, 40000, seed=900, kind="profile", fill=0.7)
+    Vo0 = _obs(base, d)
+    re, im = Vo0.real + base.noise_re, Vo0.imag + base.noise_im
+    ds = gal.Dataset(*(t(a, d, dev) for a in (base.u, base.v, re, im, base.w)))
+    K = 12
+    rng = np.random.default_rng(901)
+    I = np.stack([base.I * rng.uniform(0.8, 1.2, base.I.size) for _ in range(K)])
+    geo = np.array([[base.Rmin, base.dR, rng.uniform(0, 1.2), rng.uniform(0, np.pi),
+                     rng.normal(0, 3 * base.dxy), rng.normal(0, 3 * base.dxy)] for _ in range(K)])
+    It, gt = t(I, d, dev), torch.as_tensor(geo, device=dev)
+    b = gal.profile_batch(ds, It, gt, base.N, base.dxy)
+    assert b.info() == {"jobs": K, "fft_groups": 1, "sample_groups": 1}
+    c2b = b.chi2().cpu().numpy()
+    for k in range(K):
+        c2s = float(ds.chi2Profile(It[k], geo[k, 0], geo[k, 1], base.N, base.dxy, geo[k, 2],
+                                   geo[k, 3], geo[k, 4], geo[k, 5]))
+        assert abs(c2b[k] - c2s) <= 1e-12 * c2s
+        Vo = oracle.sampleProfile(I[k], geo[k, 0], geo[k, 1], base.N, base.dxy, base.u, base.v,
+                                  geo[k, 2], geo[k, 3], geo[k, 4], geo[k, 5])
+        Vg = ds.sampleProfile(It[k], geo[k, 0], geo[k, 1], base.N, base.dxy, geo[k, 2],
+                              geo[k, 3], geo[k, 4], geo[k, 5]).cpu().numpy()
+        c2o = oracle.chi2(Vo, re, im, base.w)
+        assert abs(c2b[k] - c2o) <= chi2_bound(c2o, Vg - Vo, base.w)
+    # the plan reads the buffers at execution: change them in place
+    It.mul_(0.5)
+    gt[:, 3] += 0.3
+    c2b2 = b.chi2().cpu().numpy()
+    for k in (0, K - 1):
+        g = gt[k].cpu().numpy()
+        c2s = float(ds.chi2Profile(It[k], g[0], g[1], base.N, base.dxy, g[2], g[3], g[4], g[5]))
+        assert abs(c2b2[k] - c2s) <= 1e-12 * c2s
+    # bitwise repeatable
+    assert np.array_equal(b.chi2().cpu().numpy(), c2b2)
+    b.close()
+    ds.close()
+
+
+def test_mixed_batch_kinds_sizes_datasets_precisions():
+    dev = device()
+    gal = _gal()
+    import torch
+
+    specs = [(128, 7001, "image", np.float64), (256, 12001, "profile", np.float64),
+             (64, 3001, "image", np.float32), (512, 20001, "profile", np.float32),
+             (256, 12001, "image", np.float64), (1024, 9001, "profile", np.float64)]
+    jobs, refs, keep = [], [], []
+    for i, (N, M, kind, d) in enumerate(specs):
+        case = wl.random_case(N, M, seed=950 + i, kind=kind, fill=0.8)
+        Vo = _obs(case, d)
+        re, im, w = rounded(Vo.real + case.noise_re, d), rounded(Vo.imag + case.noise_im, d), \
+            rounded(case.w, d)
+        ds = gal.Dataset(*(t(a, d, dev) for a in (case.u, case.v, re, im, w)))
+        model = t(case.image if kind == "image" else case.I, d, dev)
+        geo = torch.as_tensor(_geo(case), dtype=torch.float64, device=dev)
+        jobs.append({"ds": ds, "kind": gal.JOB_IMAGE if kind == "image" else gal.JOB_PROFILE,
+                     "Nxy": N, "dxy": case.dxy, "model": model, "geo": geo})
+        keep.append((ds, model, geo))
+        if kind == "image":
+            c2s = float(ds.chi2Image(model, case.dxy, case.PA, case.dRA, case.dDec, case.inc))
+        else:
+            c2s = float(ds.chi2Profile(model, case.Rmin, case.dR, N, case.dxy, case.inc, case.PA,
+                                       case.dRA, case.dDec))
+        refs.append(c2s)
+    b = gal.Batch(jobs)
+    info = b.info()
+    assert info["jobs"] == len(specs) and info["fft_groups"] == len(specs)
+    c2b = b.chi2().cpu().numpy()
+    for k, (c2s, spec) in enumerate(zip(refs, specs)):
+        tol = 1e-12 if spec[3] == np.float64 else 1e-6
+        assert abs(c2b[k] - c2s) <= tol * c2s, (k, spec, c2b[k], c2s)
+    b.close()
