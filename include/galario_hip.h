@@ -211,6 +211,52 @@ int gal_sampleProfile_ds_f(const gal_dataset *ds, const float *I, int Nr, double
                            double dRA, double dDec, float *vis, void *ws, size_t ws_bytes,
                            void *stream);
 
+/* ---- gradients (not in the paper) ----------------------------------------
+ * chi^2 and its gradient with respect to the image pixels (grad[Nxy*Nxy],
+ * layout of the image) or to the profile values (grad[Nr]).  chi^2 is exactly
+ * quadratic in both, and the gradient is the exact transpose of the forward
+ * map: the residuals w_k (Vobs_k - V_k) scattered onto the bilinear nodes of
+ * the half spectrum (with the phase and mirror of each point), the
+ * transposed transforms, and for profiles the transposed sweep
+ *   dchi2/dI_j = sum_pixels dchi2/dimg * dimg/dI_j.
+ * The scatter and the profile bins use floating-point atomics, so gradients
+ * are not bitwise repeatable (chi^2 is).  Profile gradients need Nr <= 8192.
+ * Workspace: gal_grad_workspace_bytes_* (first 256 bytes zeroed once). */
+size_t gal_grad_workspace_bytes_d(int Nxy, int64_t M, int Nr);
+size_t gal_grad_workspace_bytes_f(int Nxy, int64_t M, int Nr);
+int gal_chi2Image_grad_d(const double *image, int Nxy, double dxy, const double *u,
+                         const double *v, const double *re, const double *im, const double *w,
+                         int64_t M, double PA, double dRA, double dDec, double inc,
+                         double *chi2, double *grad, void *ws, size_t ws_bytes, void *stream);
+int gal_chi2Image_grad_f(const float *image, int Nxy, double dxy, const float *u,
+                         const float *v, const float *re, const float *im, const float *w,
+                         int64_t M, double PA, double dRA, double dDec, double inc,
+                         double *chi2, float *grad, void *ws, size_t ws_bytes, void *stream);
+int gal_chi2Profile_grad_d(const double *I, int Nr, double Rmin, double dR, int Nxy, double dxy,
+                           const double *u, const double *v, const double *re, const double *im,
+                           const double *w, int64_t M, double inc, double PA, double dRA,
+                           double dDec, double *chi2, double *grad, void *ws, size_t ws_bytes,
+                           void *stream);
+int gal_chi2Profile_grad_f(const float *I, int Nr, double Rmin, double dR, int Nxy, double dxy,
+                           const float *u, const float *v, const float *re, const float *im,
+                           const float *w, int64_t M, double inc, double PA, double dRA,
+                           double dDec, double *chi2, float *grad, void *ws, size_t ws_bytes,
+                           void *stream);
+int gal_chi2Image_grad_ds_d(const gal_dataset *ds, const double *image, int Nxy, double dxy,
+                            double PA, double dRA, double dDec, double inc, double *chi2,
+                            double *grad, void *ws, size_t ws_bytes, void *stream);
+int gal_chi2Image_grad_ds_f(const gal_dataset *ds, const float *image, int Nxy, double dxy,
+                            double PA, double dRA, double dDec, double inc, double *chi2,
+                            float *grad, void *ws, size_t ws_bytes, void *stream);
+int gal_chi2Profile_grad_ds_d(const gal_dataset *ds, const double *I, int Nr, double Rmin,
+                              double dR, int Nxy, double dxy, double inc, double PA, double dRA,
+                              double dDec, double *chi2, double *grad, void *ws, size_t ws_bytes,
+                              void *stream);
+int gal_chi2Profile_grad_ds_f(const gal_dataset *ds, const float *I, int Nr, double Rmin,
+                              double dR, int Nxy, double dxy, double inc, double PA, double dRA,
+                              double dDec, double *chi2, float *grad, void *ws, size_t ws_bytes,
+                              void *stream);
+
 /* ---- batches: many chi^2 evaluations per launch --------------------------
  * A batch is a fixed list of jobs, planned once.  Jobs with the same
  * precision, kind and image size share the FFT launches; jobs on the same

@@ -33,7 +33,7 @@ __all__ = [
     "sweep", "sampleImage", "sampleProfile", "chi2Image", "chi2Profile", "spectrum",
     "sample_spectrum", "Dataset", "Workspace", "read_status", "timing", "GalarioError",
     "version", "init", "autotune", "tune_get", "tune_set", "Batch", "profile_batch",
-    "JOB_IMAGE", "JOB_PROFILE",
+    "JOB_IMAGE", "JOB_PROFILE", "chi2Image_grad", "chi2Profile_grad", "chi2_profile", "chi2_image",
 ]
 
 JOB_IMAGE = 0
@@ -101,10 +101,16 @@ class Workspace:
         self.dtype = dtype
         self.buf = torch.zeros(0, dtype=torch.uint8, device=self.device)
 
-    def reserve(self, Nxy: int, M: int) -> torch.Tensor:
-        need = getattr(_lib(), "gal_workspace_bytes" + _sfx(self.dtype))(int(Nxy), int(M))
+    def reserve(self, Nxy: int, M: int, grad_Nr: int | None = None) -> torch.Tensor:
+        """Grow to the bytes a call needs (grad_Nr: a gradient call, with the
+        profile length or 0 for images)."""
+        if grad_Nr is None:
+            need = getattr(_lib(), "gal_workspace_bytes" + _sfx(self.dtype))(int(Nxy), int(M))
+        else:
+            need = getattr(_lib(), "gal_grad_workspace_bytes" + _sfx(self.dtype))(
+                int(Nxy), int(M), int(grad_Nr))
         if need == 0:
-            raise GalarioError(-2, f"gal_workspace_bytes(Nxy={Nxy}, M={M})")
+            raise GalarioError(-2, f"workspace size (Nxy={Nxy}, M={M})")
         if self.buf.numel() < need:
             self.buf = torch.zeros(int(need), dtype=torch.uint8, device=self.device)
         return self.buf
@@ -221,6 +227,47 @@ def chi2Profile(I, Rmin, dR, Nxy, dxy, u, v, re, im, w, inc=0.0, PA=0.0, dRA=0.0
     return res
 
 
+def chi2Image_grad(image, dxy, u, v, re, im, w, PA=0.0, dRA=0.0, dDec=0.0, inc=0.0,
+                   ws: Workspace | None = None):
+    """(chi^2 as a 0-d device tensor, d chi^2 / d image [Nxy, Nxy])."""
+    dev = _device_of(image)
+    dt = image.dtype
+    N = image.shape[0]
+    _arr(image, "image", dt, dev, N * N)
+    M = u.numel()
+    for t_, n in ((u, "u"), (v, "v"), (re, "Re"), (im, "Im"), (w, "w")):
+        _arr(t_, n, dt, dev, M)
+    c2 = torch.empty((), dtype=torch.float64, device=dev)
+    g = torch.empty_like(image)
+    wsb = _ws(dev, dt, ws).reserve(N, M, 0)
+    with torch.cuda.device(dev):
+        check(getattr(_lib(), "gal_chi2Image_grad" + _sfx(dt))(
+            _ptr(image), N, float(dxy), _ptr(u), _ptr(v), _ptr(re), _ptr(im), _ptr(w), M,
+            float(PA), float(dRA), float(dDec), float(inc), _ptr(c2), _ptr(g), _ptr(wsb),
+            wsb.numel(), _stream(dev)), "chi2Image_grad")
+    return c2, g
+
+
+def chi2Profile_grad(I, Rmin, dR, Nxy, dxy, u, v, re, im, w, inc=0.0, PA=0.0, dRA=0.0, dDec=0.0,
+                     ws: Workspace | None = None):
+    """(chi^2 as a 0-d device tensor, d chi^2 / d I [Nr])."""
+    dev = _device_of(I)
+    dt = I.dtype
+    _arr(I, "I", dt, dev)
+    M = u.numel()
+    for t_, n in ((u, "u"), (v, "v"), (re, "Re"), (im, "Im"), (w, "w")):
+        _arr(t_, n, dt, dev, M)
+    c2 = torch.empty((), dtype=torch.float64, device=dev)
+    g = torch.empty_like(I)
+    wsb = _ws(dev, dt, ws).reserve(Nxy, M, I.numel())
+    with torch.cuda.device(dev):
+        check(getattr(_lib(), "gal_chi2Profile_grad" + _sfx(dt))(
+            _ptr(I), I.numel(), float(Rmin), float(dR), int(Nxy), float(dxy), _ptr(u), _ptr(v),
+            _ptr(re), _ptr(im), _ptr(w), M, float(inc), float(PA), float(dRA), float(dDec),
+            _ptr(c2), _ptr(g), _ptr(wsb), wsb.numel(), _stream(dev)), "chi2Profile_grad")
+    return c2, g
+
+
 def spectrum(image, ws: Workspace | None = None):
     """Half spectrum G [Nxy, Nxy/2+1] (complex) of the image with its origin at
     pixel (Nxy/2, Nxy/2); row p is frequency p - Nxy [p >= Nxy/2]."""
@@ -333,6 +380,35 @@ class Dataset:
                 float(inc), float(PA), float(dRA), float(dDec), _ptr(res), _ptr(wsb), wsb.numel(),
                 _stream(self.device)), "Dataset.chi2Profile")
         return res
+
+    def chi2Image_grad(self, image, dxy, PA=0.0, dRA=0.0, dDec=0.0, inc=0.0,
+                       ws: Workspace | None = None):
+        """(chi^2 0-d tensor, d chi^2 / d image)."""
+        self._chk(image, "image")
+        N = image.shape[0]
+        c2 = torch.empty((), dtype=torch.float64, device=self.device)
+        g = torch.empty_like(image)
+        wsb = _ws(self.device, self.dtype, ws).reserve(N, self.M, 0)
+        with torch.cuda.device(self.device):
+            check(getattr(_lib(), "gal_chi2Image_grad_ds" + _sfx(self.dtype))(
+                self._h, _ptr(image), N, float(dxy), float(PA), float(dRA), float(dDec), float(inc),
+                _ptr(c2), _ptr(g), _ptr(wsb), wsb.numel(), _stream(self.device)),
+                "Dataset.chi2Image_grad")
+        return c2, g
+
+    def chi2Profile_grad(self, I, Rmin, dR, Nxy, dxy, inc=0.0, PA=0.0, dRA=0.0, dDec=0.0,
+                         ws: Workspace | None = None):
+        """(chi^2 0-d tensor, d chi^2 / d I)."""
+        self._chk(I, "I")
+        c2 = torch.empty((), dtype=torch.float64, device=self.device)
+        g = torch.empty_like(I)
+        wsb = _ws(self.device, self.dtype, ws).reserve(Nxy, self.M, I.numel())
+        with torch.cuda.device(self.device):
+            check(getattr(_lib(), "gal_chi2Profile_grad_ds" + _sfx(self.dtype))(
+                self._h, _ptr(I), I.numel(), float(Rmin), float(dR), int(Nxy), float(dxy),
+                float(inc), float(PA), float(dRA), float(dDec), _ptr(c2), _ptr(g), _ptr(wsb),
+                wsb.numel(), _stream(self.device)), "Dataset.chi2Profile_grad")
+        return c2, g
 
     def sampleImage(self, image, dxy, PA=0.0, dRA=0.0, dDec=0.0, inc=0.0,
                     ws: Workspace | None = None):
@@ -511,6 +587,45 @@ class timing:
         cnt = (ctypes.c_int64 * max(n, 1))()
         n = _lib().gal_timing_read(n, names, ms, cnt)
         return {names[i].decode(): (ms[i], int(cnt[i])) for i in range(n)}
+
+
+# ----------------------------------------------------------------------------
+# autograd: chi^2 of a profile / image on a dataset, differentiable in the model
+class _Chi2Profile(torch.autograd.Function):
+    @staticmethod
+    def forward(ctx, I, ds, Rmin, dR, Nxy, dxy, inc, PA, dRA, dDec):
+        c2, g = ds.chi2Profile_grad(I.detach().contiguous(), Rmin, dR, Nxy, dxy, inc, PA, dRA,
+                                    dDec)
+        ctx.save_for_backward(g)
+        return c2
+
+    @staticmethod
+    def backward(ctx, gout):
+        (g,) = ctx.saved_tensors
+        return (gout.to(g.dtype) * g,) + (None,) * 9
+
+
+class _Chi2Image(torch.autograd.Function):
+    @staticmethod
+    def forward(ctx, image, ds, dxy, PA, dRA, dDec, inc):
+        c2, g = ds.chi2Image_grad(image.detach().contiguous(), dxy, PA, dRA, dDec, inc)
+        ctx.save_for_backward(g)
+        return c2
+
+    @staticmethod
+    def backward(ctx, gout):
+        (g,) = ctx.saved_tensors
+        return (gout.to(g.dtype) * g,) + (None,) * 6
+
+
+def chi2_profile(ds: "Dataset", I, Rmin, dR, Nxy, dxy, inc=0.0, PA=0.0, dRA=0.0, dDec=0.0):
+    """Differentiable chi^2 of a radial profile on a dataset (d/dI by the adjoint)."""
+    return _Chi2Profile.apply(I, ds, Rmin, dR, Nxy, dxy, inc, PA, dRA, dDec)
+
+
+def chi2_image(ds: "Dataset", image, dxy, PA=0.0, dRA=0.0, dDec=0.0, inc=0.0):
+    """Differentiable chi^2 of an image on a dataset (d/dimage by the adjoint)."""
+    return _Chi2Image.apply(image, ds, dxy, PA, dRA, dDec, inc)
 
 
 _load_tune_cache()

@@ -52,6 +52,13 @@ _SIG = {
     "gal_chi2Profile_ds": (I, [P, P, I, D, D, I, D, D, D, D, D, P, P, SZ, P]),
     "gal_sampleImage_ds": (I, [P, P, I, D, D, D, D, D, P, P, SZ, P]),
     "gal_sampleProfile_ds": (I, [P, P, I, D, D, I, D, D, D, D, D, P, P, SZ, P]),
+    "gal_grad_workspace_bytes_d": (SZ, [I, I64, I]),
+    "gal_grad_workspace_bytes_f": (SZ, [I, I64, I]),
+    "gal_chi2Image_grad": (I, [P, I, D, P, P, P, P, P, I64, D, D, D, D, P, P, P, SZ, P]),
+    "gal_chi2Profile_grad": (I, [P, I, D, D, I, D, P, P, P, P, P, I64, D, D, D, D, P, P, P, SZ,
+                                 P]),
+    "gal_chi2Image_grad_ds": (I, [P, P, I, D, D, D, D, D, P, P, P, SZ, P]),
+    "gal_chi2Profile_grad_ds": (I, [P, P, I, D, D, I, D, D, D, D, D, P, P, P, SZ, P]),
     "gal_batch_create": (I, [P, I, ctypes.POINTER(P)]),
     "gal_batch_workspace_bytes": (SZ, [P]),
     "gal_batch_info": (I, [P, ctypes.POINTER(I), ctypes.POINTER(I), ctypes.POINTER(I)]),
@@ -69,6 +76,7 @@ _PRECISION_SUFFIXED = {
     "gal_sweep", "gal_sampleImage", "gal_sampleProfile", "gal_chi2Image", "gal_chi2Profile",
     "gal_spectrum", "gal_sample_spectrum", "gal_dataset_create", "gal_chi2Image_ds",
     "gal_chi2Profile_ds", "gal_sampleImage_ds", "gal_sampleProfile_ds", "gal_autotune",
+    "gal_chi2Image_grad", "gal_chi2Profile_grad", "gal_chi2Image_grad_ds", "gal_chi2Profile_grad_ds",
 }
 
 

@@ -1,0 +1,388 @@
+// adjoint.h -- gradient of chi^2 with respect to the image pixels and to the
+// profile values (the paper gives no gradient; this is the exact transpose of
+// the forward path, written for the same data layouts).
+//
+// chi^2 = sum_k w_k |R_k|^2, R_k = Vobs_k - V_k, and V_k is linear in the
+// image, so d chi^2 / d img = -2 sum_k w_k Re(conj(R_k) dV_k / d img).
+//
+// General image (complex half spectrum S, node n = (q, p~)):
+//   V_k = cinc e^{i theta_k} F_k(sum_n beta_kn S_n), F_k = conj for mirrored
+//   points, and S_n = sum_x img[x] E_n(x), E_n = exp(-2 pi i (p~ (r-N/2) +
+//   q (c-N/2)) / N).  Then
+//     d chi^2 / d img[x] = -2 Re sum_n A_n E_n(x),
+//     A_n = sum_k w_k cinc beta_kn a_k,  a_k = conj(R_k) e^{i theta_k}
+//   (mirrored: a_k = R_k e^{-i theta_k}).  A is scattered onto the stored
+//   nodes, transformed along p for every kept column (length-N FFT, all rows
+//   r) and then along q for every row: Re of a length-N FFT of a sequence
+//   that is zero beyond q >= Q, done two rows at a time through its Hermitian
+//   extension (whose transform is real).
+//
+// Swept profile (real spectrum S_R[p][q], p >= 0, node p~ read at |p~|):
+//   along even images G[p][q] = sum img cos(phi_p(r)) cos(phi_q(c)), so
+//     d chi^2 / d img[r][c] (even part) = -2 sum_{p,q} A_R[p][q] cos phi_p(r) cos phi_q(c),
+//     A_R[p][q] = sum_k w_k beta_kn Re(conj(R_k) e^{i theta_k}) over nodes at (|p~|, q),
+//   two real cosine transforms (even extensions packed two at a time), on the
+//   quadrant r, c in [0, N/2] only; then the transpose of the sweep sums the
+//   pixel gradient into the profile bins (each quadrant pixel stands for its
+//   mirrors: weight m(r) m(c), m = 1 on the rows/columns 0 and N/2, else 2).
+#pragma once
+#include "kernels.h"
+
+namespace gal {
+
+template <typename T>
+__global__ __launch_bounds__(256) void k_zero(T *__restrict__ p, int64_t n) {
+    for (int64_t i = (int64_t)blockIdx.x * 256 + threadIdx.x; i < n; i += (int64_t)gridDim.x * 256)
+        p[i] = T(0);
+}
+
+// ---- sampling + scatter ----------------------------------------------------
+// Forward sample of every point (chi^2 partials as in k_sample*), then the
+// residual's contribution to the adjoint grid A (same layout as the spectrum).
+template <typename T, bool REAL>
+__global__ __launch_bounds__(SAMPLE_NT) void k_sample_scatter(
+    const T *__restrict__ S, T *__restrict__ A, Geom g, SampleArgs a, const T *__restrict__ u,
+    const T *__restrict__ v, const T *__restrict__ re, const T *__restrict__ im,
+    const T *__restrict__ w, double *__restrict__ partials, Control *ctl) {
+    __shared__ double red[SAMPLE_NT / 64];
+    const int blk = xcd_remap(blockIdx.x, gridDim.x);
+    const int64_t base = (int64_t)blk * (SAMPLE_NT * SAMPLE_PPT) + threadIdx.x;
+    double acc = 0.0;
+    bool bad = false;
+    for (int p = 0; p < SAMPLE_PPT; ++p) {
+        const int64_t k = base + p * SAMPLE_NT;
+        if (k >= a.M) continue;
+        const double uu = u[k], vv = v[k];
+        double sn, cs;
+        sincospi(2.0 * (uu * a.dRA + vv * a.dDec), &sn, &cs);
+        double Vre, Vim;
+        if constexpr (REAL) {
+            const StencilR<T> st = locate_r<T>(S, g, a, uu, vv);
+            if (!st.ok) {
+                bad = true;
+                acc = __builtin_nan("");
+                continue;
+            }
+            const T x0 = st.c0[0], x1 = st.c0[1], y0 = st.c0[g.CS], y1 = st.c0[g.CS + 1];
+            const double a00 = st.swap ? x1 : x0, a10 = st.swap ? x0 : x1;
+            const double a01 = st.swap ? y1 : y0, a11 = st.swap ? y0 : y1;
+            const double s = st.s, t = st.t;
+            const double b = (1.0 - t) * ((1.0 - s) * a00 + s * a01) +
+                             t * ((1.0 - s) * a10 + s * a11);
+            Vre = a.cinc * b * cs;
+            Vim = a.cinc * b * sn;
+            const double rr = (double)re[k] - Vre, ri = (double)im[k] - Vim;
+            acc += (double)w[k] * (rr * rr + ri * ri);
+            // Re(conj(R) e^{i theta}) = rr cs + ri sn; node weights; rows lo, lo+1
+            const double h = (double)w[k] * a.cinc * (rr * cs + ri * sn);
+            const double w_p0 = (1.0 - t), w_p1 = t;                   // rows p~0, p~0+1
+            const double wl = st.swap ? w_p1 : w_p0, wh = st.swap ? w_p0 : w_p1;  // lo, lo+1
+            T *c0 = A + (st.c0 - S);
+            atomicAdd(c0, (T)(h * wl * (1.0 - s)));
+            atomicAdd(c0 + 1, (T)(h * wh * (1.0 - s)));
+            atomicAdd(c0 + g.CS, (T)(h * wl * s));
+            atomicAdd(c0 + g.CS + 1, (T)(h * wh * s));
+        } else {
+            const c2<T> *Sc = (const c2<T> *)S;
+            const Stencil<T> st = locate<T>(Sc, g, a, uu, vv);
+            if (!st.ok) {
+                bad = true;
+                acc = __builtin_nan("");
+                continue;
+            }
+            const c2<T> n00 = st.c0[0], n10 = st.c0[1], n01 = st.c0[g.CS], n11 = st.c0[g.CS + 1];
+            const double s = st.s, t = st.t;
+            const double w00 = (1.0 - t) * (1.0 - s), w01 = (1.0 - t) * s;
+            const double w10 = t * (1.0 - s), w11 = t * s;
+            double br = w00 * n00.x + w01 * n01.x + w10 * n10.x + w11 * n11.x;
+            double bi = w00 * n00.y + w01 * n01.y + w10 * n10.y + w11 * n11.y;
+            if (st.mirror) bi = -bi;
+            br *= a.cinc;
+            bi *= a.cinc;
+            Vre = br * cs - bi * sn;
+            Vim = br * sn + bi * cs;
+            const double rr = (double)re[k] - Vre, ri = (double)im[k] - Vim;
+            acc += (double)w[k] * (rr * rr + ri * ri);
+            // a = conj(R) e^{i theta} (direct) or R e^{-i theta} (mirrored)
+            const double ar = rr * cs + ri * sn;
+            const double ai = st.mirror ? (ri * cs - rr * sn) : (rr * sn - ri * cs);
+            const double h = (double)w[k] * a.cinc;
+            T *c0 = (T *)(A + 2 * (st.c0 - Sc));
+            const double wts[4] = {w00, w10, w01, w11};
+            const int offs[4] = {0, 1, g.CS, g.CS + 1};
+#pragma unroll
+            for (int n = 0; n < 4; ++n) {
+                atomicAdd(c0 + 2 * offs[n], (T)(h * wts[n] * ar));
+                atomicAdd(c0 + 2 * offs[n] + 1, (T)(h * wts[n] * ai));
+            }
+        }
+    }
+    if (bad) ctl->flag = 1;
+    const double bs = block_sum(acc, red);
+    if (threadIdx.x == 0) partials[blk] = bs;
+}
+
+// ---- general image: columns ------------------------------------------------
+// Column q of A (rows i = p~ + P, i in [0, 2P]) -> H[r][q] = sum_p~ A (-1)^p~
+// exp(-2 pi i p~ r / N) for all r in [0, N), written in place (stride CS).
+template <typename T, typename Cfg>
+__device__ __forceinline__ void adj_cols_body(const Geom &g, c2<T> *__restrict__ A, int blk) {
+    constexpr int L = Cfg::L, B = Cfg::B, NT = Cfg::NT, E = Cfg::E;
+    constexpr int N = L;
+    constexpr int R0 = pass_radix(L, 1, Cfg::RMAX);
+    constexpr int LR = L / R0;
+    __shared__ c2<T> lds[B * Cfg::LS];
+    const int tid = threadIdx.x;
+    const int q0 = blk * B;
+    if (q0 >= g.Q) return;
+    c2<T> v[E];
+#pragma unroll
+    for (int i = 0; i < E / R0; ++i) {
+        const int gi = tid + i * NT;
+        const int b = gi / LR, j = gi % LR;
+        const int q = q0 + b;
+#pragma unroll
+        for (int t = 0; t < R0; ++t) {
+            const int n = j + t * LR;             // frequency index p = p~ mod N
+            const int pt = n < N / 2 ? n : n - N; // p~ in [-N/2, N/2)
+            c2<T> x{T(0), T(0)};
+            if (q < g.Q) {
+                if (pt >= -g.P && pt <= g.P) x = A[(size_t)q * g.CS + pt + g.P];
+                if (pt == -N / 2 && g.P >= N / 2) {  // p~ = +N/2 is the same frequency
+                    const c2<T> y = A[(size_t)q * g.CS + N / 2 + g.P];
+                    x = cadd(x, y);
+                }
+                if (pt & 1) x = {-x.x, -x.y};
+            }
+            v[i * R0 + t] = x;
+        }
+    }
+    fft_passes<Cfg, 1>(v, lds, twiddles<T>(), tid);
+    for (int idx = tid; idx < N * B; idx += NT) {
+        const int b = idx / N, r = idx % N;
+        const int q = q0 + b;
+        if (q >= g.Q) continue;
+        A[(size_t)q * g.CS + r] = lds[Cfg::at(b, r)];
+    }
+}
+
+template <typename T, typename Cfg>
+__global__ __launch_bounds__(Cfg::NT) void k_adj_cols(Geom g, c2<T> *__restrict__ A) {
+    adj_cols_body<T, Cfg>(g, A, blockIdx.x);
+}
+
+// ---- general image: rows ---------------------------------------------------
+// Rows 2m, 2m+1: h_r[q] = (-1)^q H[r][q] (q < Q), Hermitian extension x_r
+// (x[0] = Re h[0], x[q] = h[q]/2, x[N-q] = conj(h[q])/2, x[N/2] = Re h[N/2]),
+// z = x_{2m} + i x_{2m+1}; grad[r][c] = -2 Re / Im of FFT(z)[c].
+template <typename T, typename Cfg>
+__device__ __forceinline__ void adj_rows_body(const Geom &g, const c2<T> *__restrict__ H,
+                                              T *__restrict__ grad, int blk) {
+    constexpr int L = Cfg::L, B = Cfg::B, NT = Cfg::NT, E = Cfg::E;
+    constexpr int N = L;
+    constexpr int R0 = pass_radix(L, 1, Cfg::RMAX);
+    constexpr int LR = L / R0;
+    __shared__ c2<T> lds[B * Cfg::LS];
+    const int tid = threadIdx.x;
+    const int m0 = blk * B;
+    const T half = T(0.5);
+    c2<T> v[E];
+#pragma unroll
+    for (int i = 0; i < E / R0; ++i) {
+        const int gi = tid + i * NT;
+        const int b = gi / LR, j = gi % LR;
+        const int r = 2 * (m0 + b);
+#pragma unroll
+        for (int t = 0; t < R0; ++t) {
+            const int n = j + t * LR;
+            c2<T> z{T(0), T(0)};
+            const int qq = n <= N / 2 ? n : N - n;
+            if (r < N && qq < g.Q) {
+                c2<T> h1 = H[(size_t)qq * g.CS + r], h2 = H[(size_t)qq * g.CS + r + 1];
+                if (qq & 1) {
+                    h1 = {-h1.x, -h1.y};
+                    h2 = {-h2.x, -h2.y};
+                }
+                if (qq == 0 || qq == N / 2) {
+                    z = {h1.x, h2.x};
+                } else if (n < N / 2) {  // h1/2 + i h2/2
+                    z = {half * (h1.x - h2.y), half * (h1.y + h2.x)};
+                } else {                 // conj(h1)/2 + i conj(h2)/2
+                    z = {half * (h1.x + h2.y), half * (h2.x - h1.y)};
+                }
+            }
+            v[i * R0 + t] = z;
+        }
+    }
+    fft_passes<Cfg, 1>(v, lds, twiddles<T>(), tid);
+    for (int idx = tid; idx < 2 * B * N; idx += NT) {
+        const int rb = idx / N, c = idx % N;
+        const int r = 2 * m0 + rb;
+        if (r >= N) continue;
+        const c2<T> z = lds[Cfg::at(rb >> 1, c)];
+        grad[(size_t)r * N + c] = T(-2) * ((rb & 1) ? z.y : z.x);
+    }
+}
+
+template <typename T, typename Cfg>
+__global__ __launch_bounds__(Cfg::NT) void k_adj_rows(Geom g, const c2<T> *__restrict__ H,
+                                                      T *__restrict__ grad) {
+    adj_rows_body<T, Cfg>(g, H, grad, blockIdx.x);
+}
+
+// ---- swept profile: columns -------------------------------------------------
+// Column pair (2m, 2m+1) of A_R (p in [0, P]): even extension over p of
+// (-1)^p A_R[p][q] halved off p = 0 (and p = N/2), packed re/im; its
+// transform is H[r][q] = sum_p A_R[p][q] (-1)^p cos(2 pi p r / N), kept for
+// r in [0, N/2] in place.
+template <typename T, typename Cfg>
+__device__ __forceinline__ void adj_cols_sym_body(const Geom &g, int Qe, T *__restrict__ A,
+                                                  int blk) {
+    constexpr int L = Cfg::L, B = Cfg::B, NT = Cfg::NT, E = Cfg::E;
+    constexpr int N = L;
+    constexpr int R0 = pass_radix(L, 1, Cfg::RMAX);
+    constexpr int LR = L / R0;
+    __shared__ c2<T> lds[B * Cfg::LS];
+    const int tid = threadIdx.x;
+    const int m0 = blk * B;
+    if (2 * m0 >= Qe) return;
+    const T half = T(0.5);
+    c2<T> v[E];
+#pragma unroll
+    for (int i = 0; i < E / R0; ++i) {
+        const int gi = tid + i * NT;
+        const int b = gi / LR, j = gi % LR;
+        const int q = 2 * (m0 + b);
+#pragma unroll
+        for (int t = 0; t < R0; ++t) {
+            const int n = j + t * LR;
+            const int pp = n <= N / 2 ? n : N - n;
+            c2<T> x{T(0), T(0)};
+            if (q < Qe && pp <= g.P) {
+                x = {A[(size_t)q * g.CS + pp], A[(size_t)(q + 1) * g.CS + pp]};
+                if (pp & 1) x = {-x.x, -x.y};
+                if (pp != 0 && pp != N / 2) x = {half * x.x, half * x.y};
+            }
+            v[i * R0 + t] = x;
+        }
+    }
+    fft_passes<Cfg, 1>(v, lds, twiddles<T>(), tid);
+    constexpr int NH = N / 2 + 1;
+    for (int idx = tid; idx < NH * 2 * B; idx += NT) {
+        const int cb = idx / NH, r = idx % NH;
+        const int q = 2 * m0 + cb;
+        if (q >= Qe) continue;
+        const c2<T> z = lds[Cfg::at(cb >> 1, r)];
+        A[(size_t)q * g.CS + r] = (cb & 1) ? z.y : z.x;
+    }
+}
+
+template <typename T, typename Cfg>
+__global__ __launch_bounds__(Cfg::NT) void k_adj_cols_sym(Geom g, int Qe, T *__restrict__ A) {
+    adj_cols_sym_body<T, Cfg>(g, Qe, A, blockIdx.x);
+}
+
+// ---- swept profile: rows and the transposed sweep ----------------------------
+// Quadrant rows 2m, 2m+1 (<= N/2): even extension over q of (-1)^q H[r][q]
+// (halved off q = 0, N/2), packed; g[r][c] = -2 x transform, c in [0, N/2].
+// Each pixel then adds m(r) m(c) g dxy^2 (1 - f) to bin j and ... f to bin j+1
+// (centre pixel: (1 + Rmin/dR) to bin 0 and -Rmin/dR to bin 1) in an LDS
+// histogram, flushed to gI with one atomic per touched bin.
+template <typename T, typename Cfg>
+__device__ __forceinline__ void adj_rows_sym_body(const Geom &g, const T *__restrict__ H,
+                                                  const SweepArgs &sw, double *__restrict__ gI,
+                                                  double *hist, int blk) {
+    constexpr int L = Cfg::L, B = Cfg::B, NT = Cfg::NT, E = Cfg::E;
+    constexpr int N = L;
+    constexpr int R0 = pass_radix(L, 1, Cfg::RMAX);
+    constexpr int LR = L / R0;
+    __shared__ c2<T> lds[B * Cfg::LS];
+    __shared__ int jlo_s, jhi_s;
+    const int tid = threadIdx.x;
+    const int m0 = blk * B;
+    const T half = T(0.5);
+    const int Qr = g.Q;  // kept columns
+    c2<T> v[E];
+#pragma unroll
+    for (int i = 0; i < E / R0; ++i) {
+        const int gi = tid + i * NT;
+        const int b = gi / LR, j = gi % LR;
+        const int r = 2 * (m0 + b);
+#pragma unroll
+        for (int t = 0; t < R0; ++t) {
+            const int n = j + t * LR;
+            const int qq = n <= N / 2 ? n : N - n;
+            c2<T> x{T(0), T(0)};
+            if (r <= N / 2 && qq < Qr) {
+                const T h1 = H[(size_t)qq * g.CS + r];
+                const T h2 = (r + 1 <= N / 2) ? H[(size_t)qq * g.CS + r + 1] : T(0);
+                x = {h1, h2};
+                if (qq & 1) x = {-x.x, -x.y};
+                if (qq != 0 && qq != N / 2) x = {half * x.x, half * x.y};
+            }
+            v[i * R0 + t] = x;
+        }
+    }
+    for (int k = tid; k < sw.Nr; k += NT) hist[k] = 0.0;
+    if (tid == 0) {
+        jlo_s = sw.Nr;
+        jhi_s = -1;
+    }
+    fft_passes<Cfg, 1>(v, lds, twiddles<T>(), tid);  // ends with a barrier
+    constexpr int NH = N / 2 + 1;
+    int jlo = sw.Nr, jhi = -1;
+    for (int idx = tid; idx < 2 * B * NH; idx += NT) {
+        const int rb = idx / NH, c = idx % NH;
+        const int r = 2 * m0 + rb;
+        if (r > N / 2) continue;
+        const c2<T> z = lds[Cfg::at(rb >> 1, c)];
+        const double gpix = -2.0 * (double)((rb & 1) ? z.y : z.x);
+        const double mult = ((r == 0 || r == N / 2) ? 1.0 : 2.0) * ((c == 0 || c == N / 2) ? 1.0 : 2.0);
+        const double gw = gpix * mult * sw.pix_area;
+        if (r == N / 2 && c == N / 2) {
+            atomicAdd(&hist[0], gw * (1.0 + sw.Rmin * sw.inv_dR));
+            atomicAdd(&hist[1], gw * (-sw.Rmin * sw.inv_dR));
+            jlo = 0;
+            jhi = jhi > 1 ? jhi : 1;
+            continue;
+        }
+        const double x = (double)(N / 2 - c) * sw.dxy;
+        const double y = (double)(N / 2 - r) * sw.dxy;
+        const double xs = x * sw.inv_cos;
+        const double rho = sqrt(xs * xs + y * y);
+        const double tt = (rho - sw.Rmin) * sw.inv_dR;
+        if (tt >= 0.0 && tt <= sw.tmax) {
+            int j = (int)tt;
+            j = j < sw.Nr - 2 ? j : sw.Nr - 2;
+            const double f = tt - (double)j;
+            atomicAdd(&hist[j], gw * (1.0 - f));
+            atomicAdd(&hist[j + 1], gw * f);
+            jlo = j < jlo ? j : jlo;
+            jhi = j + 1 > jhi ? j + 1 : jhi;
+        }
+    }
+    atomicMin(&jlo_s, jlo);
+    atomicMax(&jhi_s, jhi);
+    __syncthreads();
+    for (int k = jlo_s + tid; k <= jhi_s; k += NT) {
+        const double h = hist[k];
+        if (h != 0.0) atomicAdd(&gI[k], h);
+    }
+}
+
+template <typename T, typename Cfg>
+__global__ __launch_bounds__(Cfg::NT) void k_adj_rows_sym(Geom g, const T *__restrict__ H,
+                                                          SweepArgs sw, double *__restrict__ gI) {
+    extern __shared__ double hist[];
+    adj_rows_sym_body<T, Cfg>(g, H, sw, gI, hist, blockIdx.x);
+}
+
+// profile gradient in the array type (FP32 callers get a float copy)
+template <typename T>
+__global__ __launch_bounds__(256) void k_cast_out(const double *__restrict__ a, T *__restrict__ b,
+                                                  int n) {
+    const int i = blockIdx.x * 256 + threadIdx.x;
+    if (i < n) b[i] = (T)a[i];
+}
+
+}  // namespace gal

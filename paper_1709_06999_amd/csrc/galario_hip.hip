@@ -18,6 +18,7 @@
 #include <vector>
 
 #include "../../include/galario_hip.h"
+#include "adjoint.h"
 #include "batch.h"
 #include "kernels.h"
 
@@ -140,18 +141,24 @@ static inline K arg_cast(A &&a) {
 }
 
 template <typename... KArgs, typename... Args>
-static int launch(const char *name, void (*kernel)(KArgs...), dim3 grid, dim3 block,
-                  hipStream_t s, Args &&...args) {
+static int launch_sm(const char *name, void (*kernel)(KArgs...), dim3 grid, dim3 block,
+                     unsigned shmem, hipStream_t s, Args &&...args) {
     static_assert(sizeof...(KArgs) == sizeof...(Args), "kernel argument count");
-    if (grid.x == 0) return GAL_OK;
+    if (grid.x == 0 || grid.y == 0) return GAL_OK;
     hipEvent_t a = nullptr, b = nullptr;
     if (tm_begin(a, b)) {
-        hipExtLaunchKernelGGL(kernel, grid, block, 0, s, a, b, 0, arg_cast<KArgs>(args)...);
+        hipExtLaunchKernelGGL(kernel, grid, block, shmem, s, a, b, 0, arg_cast<KArgs>(args)...);
         tm_end(name, a, b);
     } else {
-        kernel<<<grid, block, 0, s>>>(arg_cast<KArgs>(args)...);
+        kernel<<<grid, block, shmem, s>>>(arg_cast<KArgs>(args)...);
     }
     return check_launch();
+}
+
+template <typename... KArgs, typename... Args>
+static int launch(const char *name, void (*kernel)(KArgs...), dim3 grid, dim3 block,
+                  hipStream_t s, Args &&...args) {
+    return launch_sm(name, kernel, grid, block, 0u, s, static_cast<Args &&>(args)...);
 }
 
 // ---------------------------------------------------------------------------
@@ -546,6 +553,112 @@ static int run_path(const T *src, bool profile, const SweepArgs &sw, const Geom 
     if (rc) return rc;
     const SampleArgs sa = make_sample(g, o.M, dxy, PA, dRA, dDec, inc);
     return sample<T>(profile, w.xt, gs, sa, o, vis, chi2, w, s);
+}
+
+// ---------------------------------------------------------------------------
+// gradient path: forward transform, sample + scatter of the residuals, the
+// transposed passes (adjoint.h).  Workspace: [control][partials][S][A][gI]
+constexpr int GRAD_NR_MAX = 8192;  // profile bins held in LDS by the transposed sweep
+
+template <typename T>
+static size_t grad_ws_bytes(int N, int64_t M, int Nr) {
+    const size_t xt = align256((size_t)(N / 2 + 1) * (size_t)(N + 2) * sizeof(c2<T>));
+    return ws_bytes<T>(N, M) + xt + align256((size_t)(Nr > 0 ? Nr : 1) * sizeof(double));
+}
+
+template <typename T, int N>
+static int launch_adjoint(bool profile, const Geom &gs, int Qe, const SweepArgs &sw, void *A,
+                          T *grad, double *gI, hipStream_t s) {
+    constexpr int B = cols_B(N);
+    using C = CfgE<T, N, B, 8>;
+    if (profile) {
+        int rc = launch("k_adj_cols_sym", k_adj_cols_sym<T, C>, dim3((Qe / 2 + B - 1) / B),
+                        dim3(C::NT), s, gs, Qe, A);
+        if (rc) return rc;
+        const int pairs = N / 4 + 1;
+        return launch_sm("k_adj_rows_sym", k_adj_rows_sym<T, C>, dim3((pairs + B - 1) / B),
+                         dim3(C::NT), (unsigned)(sw.Nr * sizeof(double)), s, gs, A, sw, gI);
+    }
+    int rc = launch("k_adj_cols", k_adj_cols<T, C>, dim3((gs.Q + B - 1) / B), dim3(C::NT), s, gs,
+                    A);
+    if (rc) return rc;
+    return launch("k_adj_rows", k_adj_rows<T, C>, dim3((N / 2 + B - 1) / B), dim3(C::NT), s, gs,
+                  A, grad);
+}
+
+template <typename T>
+static int dispatch_adjoint(bool profile, const Geom &gs, int Qe, const SweepArgs &sw, void *A,
+                            T *grad, double *gI, hipStream_t s) {
+    switch (gs.N) {
+        case 16: return launch_adjoint<T, 16>(profile, gs, Qe, sw, A, grad, gI, s);
+        case 32: return launch_adjoint<T, 32>(profile, gs, Qe, sw, A, grad, gI, s);
+        case 64: return launch_adjoint<T, 64>(profile, gs, Qe, sw, A, grad, gI, s);
+        case 128: return launch_adjoint<T, 128>(profile, gs, Qe, sw, A, grad, gI, s);
+        case 256: return launch_adjoint<T, 256>(profile, gs, Qe, sw, A, grad, gI, s);
+        case 512: return launch_adjoint<T, 512>(profile, gs, Qe, sw, A, grad, gI, s);
+        case 1024: return launch_adjoint<T, 1024>(profile, gs, Qe, sw, A, grad, gI, s);
+        case 2048: return launch_adjoint<T, 2048>(profile, gs, Qe, sw, A, grad, gI, s);
+        case 4096: return launch_adjoint<T, 4096>(profile, gs, Qe, sw, A, grad, gI, s);
+        case 8192: return launch_adjoint<T, 8192>(profile, gs, Qe, sw, A, grad, gI, s);
+        default: return fail(GAL_ERR_SIZE, "Nxy=%d unsupported", gs.N);
+    }
+}
+
+template <typename T>
+static int grad_path(const T *src, bool profile, const SweepArgs &sw, const Geom &g, double dxy,
+                     const Obs<T> &o, double PA, double dRA, double dDec, double inc,
+                     double *chi2, T *grad, void *ws, size_t ws_bytes_, hipStream_t s) {
+    int rc = ensure_init();
+    if (rc) return rc;
+    if (profile && sw.Nr > GRAD_NR_MAX)
+        return fail(GAL_ERR_SIZE, "profile gradient: Nr=%d above %d", sw.Nr, GRAD_NR_MAX);
+    if (profile) {
+        // the transposed sweep keeps Nr bins in LDS beside the FFT buffer
+        const size_t lds = (size_t)cols_B(g.N) * (size_t)g.N * sizeof(c2<T>) +
+                           (size_t)sw.Nr * sizeof(double);
+        if (lds > (size_t)160 * 1024)
+            return fail(GAL_ERR_SIZE, "profile gradient: Nr=%d too large for Nxy=%d", sw.Nr, g.N);
+    }
+    const int Nr = profile ? sw.Nr : 0;
+    const size_t need = grad_ws_bytes<T>(g.N, o.M, Nr);
+    if (!ws) return fail(GAL_ERR_NULL, "workspace is NULL");
+    if (ws_bytes_ < need)
+        return fail(GAL_ERR_WORKSPACE, "workspace of %zu bytes, need %zu", ws_bytes_, need);
+    WS w;
+    rc = carve<T>(ws, ws_bytes_, g.N, o.M, w);
+    if (rc) return rc;
+    const size_t xt = align256((size_t)(g.N / 2 + 1) * (size_t)(g.N + 2) * sizeof(c2<T>));
+    void *A = (char *)w.xt + xt;
+    double *gI = (double *)((char *)A + xt);
+    Geom gs;
+    rc = transform<T>(src, profile, sw, g, w.xt, s, gs);
+    if (rc) return rc;
+    const int Qe = (g.Q + 1) & ~1;
+    const int64_t a_elems = profile ? (int64_t)Qe * gs.CS : (int64_t)2 * gs.Q * gs.CS;
+    rc = launch("k_zero", k_zero<T>, dim3(256), dim3(256), s, A, a_elems);
+    if (rc) return rc;
+    const SampleArgs sa = make_sample(g, o.M, dxy, PA, dRA, dDec, inc);
+    const dim3 grid((unsigned)sample_blocks(o.M)), blk(SAMPLE_NT);
+    if (profile)
+        rc = launch("k_sample_scatter_sym", k_sample_scatter<T, true>, grid, blk, s, w.xt, A, gs,
+                    sa, o.u, o.v, o.re, o.im, o.w, w.partials, w.ctl);
+    else
+        rc = launch("k_sample_scatter", k_sample_scatter<T, false>, grid, blk, s, w.xt, A, gs, sa,
+                    o.u, o.v, o.re, o.im, o.w, w.partials, w.ctl);
+    if (rc) return rc;
+    rc = launch("k_reduce", k_reduce, dim3(1), dim3(SAMPLE_NT), s, w.partials, (int)grid.x, chi2);
+    if (rc) return rc;
+    double *gacc = profile ? (sizeof(T) == 8 ? (double *)grad : gI) : nullptr;
+    if (profile) {
+        rc = launch("k_zero", k_zero<double>, dim3(16), dim3(256), s, gacc, (int64_t)Nr);
+        if (rc) return rc;
+    }
+    rc = dispatch_adjoint<T>(profile, gs, Qe, sw, A, grad, gacc, s);
+    if (rc) return rc;
+    if (profile && sizeof(T) != 8)
+        rc = launch("k_cast_out", k_cast_out<T>, dim3((Nr + 255) / 256), dim3(256), s, gI, grad,
+                    Nr);
+    return rc;
 }
 
 // ---------------------------------------------------------------------------
@@ -1117,6 +1230,121 @@ int gal_sampleProfile_ds_f(const gal_dataset *ds, const float *I, int Nr, double
     return ds_call<float>(ds, I, true, Nr, Rmin, dR, Nxy, dxy, inc, PA, dRA, dDec, vis, nullptr, ws,
                           ws_bytes_, stream);
 }
+
+// ---- gradients ------------------------------------------------------------
+size_t gal_grad_workspace_bytes_d(int Nxy, int64_t M, int Nr) {
+    if (!pow2_in_range(Nxy) || M < 0 || Nr < 0) return 0;
+    return grad_ws_bytes<double>(Nxy, M, Nr);
+}
+size_t gal_grad_workspace_bytes_f(int Nxy, int64_t M, int Nr) {
+    if (!pow2_in_range(Nxy) || M < 0 || Nr < 0) return 0;
+    return grad_ws_bytes<float>(Nxy, M, Nr);
+}
+
+template <typename T>
+static int image_grad_call(const T *image, int Nxy, double dxy, const Obs<T> &o, double PA,
+                           double dRA, double dDec, double inc, double *chi2, T *grad, void *ws,
+                           size_t ws_bytes_, void *stream, const Geom *gpruned) {
+    if (!image || !chi2 || !grad) return fail(GAL_ERR_NULL, "NULL array");
+    if (o.M > 0 && (!o.u || !o.v || !o.re || !o.im || !o.w))
+        return fail(GAL_ERR_NULL, "NULL observation array");
+    if (o.M < 0) return fail(GAL_ERR_SIZE, "M < 0");
+    int rc = check_image_scalars(Nxy, dxy, PA, dRA, dDec, inc);
+    if (rc) return rc;
+    const Geom g = gpruned ? *gpruned : geom_full(Nxy);
+    return grad_path<T>(image, false, SweepArgs{}, g, dxy, o, PA, dRA, dDec, inc, chi2, grad, ws,
+                        ws_bytes_, (hipStream_t)stream);
+}
+
+template <typename T>
+static int profile_grad_call(const T *I, int Nr, double Rmin, double dR, int Nxy, double dxy,
+                             const Obs<T> &o, double inc, double PA, double dRA, double dDec,
+                             double *chi2, T *grad, void *ws, size_t ws_bytes_, void *stream,
+                             const Geom *gpruned) {
+    if (!I || !chi2 || !grad) return fail(GAL_ERR_NULL, "NULL array");
+    if (o.M > 0 && (!o.u || !o.v || !o.re || !o.im || !o.w))
+        return fail(GAL_ERR_NULL, "NULL observation array");
+    if (o.M < 0) return fail(GAL_ERR_SIZE, "M < 0");
+    int rc = check_image_scalars(Nxy, dxy, PA, dRA, dDec, inc);
+    if (rc) return rc;
+    rc = check_profile(Nr, Rmin, dR);
+    if (rc) return rc;
+    const Geom g = gpruned ? *gpruned : geom_full(Nxy);
+    return grad_path<T>(I, true, make_sweep(Nr, Rmin, dR, dxy, inc), g, dxy, o, PA, dRA, dDec, 0.0,
+                        chi2, grad, ws, ws_bytes_, (hipStream_t)stream);
+}
+
+#define GAL_IMAGE_GRAD(SFX, T)                                                                  \
+    int gal_chi2Image_grad_##SFX(const T *image, int Nxy, double dxy, const T *u, const T *v,   \
+                                 const T *re, const T *im, const T *w, int64_t M, double PA,    \
+                                 double dRA, double dDec, double inc, double *chi2, T *grad,    \
+                                 void *ws, size_t ws_bytes_, void *stream) {                    \
+        return image_grad_call<T>(image, Nxy, dxy, Obs<T>{u, v, re, im, w, M, nullptr}, PA, dRA, \
+                                  dDec, inc, chi2, grad, ws, ws_bytes_, stream, nullptr);       \
+    }
+GAL_IMAGE_GRAD(d, double)
+GAL_IMAGE_GRAD(f, float)
+
+#define GAL_PROFILE_GRAD(SFX, T)                                                                \
+    int gal_chi2Profile_grad_##SFX(const T *I, int Nr, double Rmin, double dR, int Nxy,         \
+                                   double dxy, const T *u, const T *v, const T *re,             \
+                                   const T *im, const T *w, int64_t M, double inc, double PA,   \
+                                   double dRA, double dDec, double *chi2, T *grad, void *ws,    \
+                                   size_t ws_bytes_, void *stream) {                            \
+        return profile_grad_call<T>(I, Nr, Rmin, dR, Nxy, dxy,                                  \
+                                    Obs<T>{u, v, re, im, w, M, nullptr}, inc, PA, dRA, dDec,    \
+                                    chi2, grad, ws, ws_bytes_, stream, nullptr);                \
+    }
+GAL_PROFILE_GRAD(d, double)
+GAL_PROFILE_GRAD(f, float)
+
+template <typename T>
+static int ds_grad(const gal_dataset *ds, int Nxy, double dxy, Geom &g, Obs<T> &o) {
+    if (!ds) return fail(GAL_ERR_NULL, "NULL dataset");
+    if (ds->precision != (int)sizeof(T))
+        return fail(GAL_ERR_UNSUPPORTED, "dataset precision %d differs from the call", ds->precision);
+    if (!ds->re) return fail(GAL_ERR_UNSUPPORTED, "dataset holds no observations");
+    if (!pow2_in_range(Nxy)) return fail(GAL_ERR_SIZE, "Nxy=%d unsupported", Nxy);
+    if (!(dxy > 0.0) || !std::isfinite(dxy)) return fail(GAL_ERR_SCALAR, "dxy must be > 0");
+    const double du = 1.0 / ((double)Nxy * dxy);
+    if (!(ds->rho_max < ((double)(Nxy / 2) - 1.0) * du))
+        return fail(GAL_ERR_UV_RANGE, "rho_max = %.6g lambda reaches beyond the half spectrum",
+                    ds->rho_max);
+    g = geom_pruned(Nxy, dxy, ds->rho_max);
+    o = Obs<T>{(const T *)ds->u, (const T *)ds->v, (const T *)ds->re, (const T *)ds->im,
+               (const T *)ds->w, ds->M, nullptr};
+    return GAL_OK;
+}
+
+#define GAL_IMAGE_GRAD_DS(SFX, T)                                                               \
+    int gal_chi2Image_grad_ds_##SFX(const gal_dataset *ds, const T *image, int Nxy, double dxy, \
+                                    double PA, double dRA, double dDec, double inc,             \
+                                    double *chi2, T *grad, void *ws, size_t ws_bytes_,          \
+                                    void *stream) {                                             \
+        Geom g;                                                                                 \
+        Obs<T> o;                                                                               \
+        int rc = ds_grad<T>(ds, Nxy, dxy, g, o);                                                \
+        if (rc) return rc;                                                                      \
+        return image_grad_call<T>(image, Nxy, dxy, o, PA, dRA, dDec, inc, chi2, grad, ws,       \
+                                  ws_bytes_, stream, &g);                                       \
+    }
+GAL_IMAGE_GRAD_DS(d, double)
+GAL_IMAGE_GRAD_DS(f, float)
+
+#define GAL_PROFILE_GRAD_DS(SFX, T)                                                             \
+    int gal_chi2Profile_grad_ds_##SFX(const gal_dataset *ds, const T *I, int Nr, double Rmin,   \
+                                      double dR, int Nxy, double dxy, double inc, double PA,    \
+                                      double dRA, double dDec, double *chi2, T *grad, void *ws, \
+                                      size_t ws_bytes_, void *stream) {                         \
+        Geom g;                                                                                 \
+        Obs<T> o;                                                                               \
+        int rc = ds_grad<T>(ds, Nxy, dxy, g, o);                                                \
+        if (rc) return rc;                                                                      \
+        return profile_grad_call<T>(I, Nr, Rmin, dR, Nxy, dxy, o, inc, PA, dRA, dDec, chi2,     \
+                                    grad, ws, ws_bytes_, stream, &g);                           \
+    }
+GAL_PROFILE_GRAD_DS(d, double)
+GAL_PROFILE_GRAD_DS(f, float)
 
 // ---- batches --------------------------------------------------------------
 int gal_batch_create(const gal_job *jobs, int n, gal_batch **out) {

@@ -1,0 +1,163 @@
+"""GPU gradients (the adjoint path) against the oracle's transposed map,
+against exact central differences of the GPU chi^2 (chi^2 is quadratic in
+the model, so central differences have no truncation error), and through
+torch.autograd.  Bar: relative l2 error <= 1e-8 in FP64."""
+import numpy as np
+import pytest
+
+import oracle
+import workloads as wl
+from gpu_util import device, rounded, t
+
+pytestmark = pytest.mark.gpu
+
+
+def _gal():
+    import paper_1709_06999_amd as gal
+
+    return gal
+
+
+def _rel(a, b):
+    return float(np.linalg.norm(a - b) / max(np.linalg.norm(b), 1e-300))
+
+
+def _obs(case, offset=0.05):
+    # observations away from the model so that the residuals are not noise only
+    if case.kind == "image":
+        Vo = oracle.sampleImage(case.image, case.dxy, case.u, case.v, case.PA, case.dRA,
+                                case.dDec, case.inc)
+    else:
+        Vo = oracle.sampleProfile(case.I, case.Rmin, case.dR, case.N, case.dxy, case.u, case.v,
+                                  case.inc, case.PA, case.dRA, case.dDec)
+    return (1.0 + offset) * Vo.real + case.noise_re, (1.0 - offset) * Vo.imag + case.noise_im
+
+
+@pytest.mark.parametrize("N,M", [(16, 300), (64, 5001), (256, 20003)])
+@pytest.mark.parametrize("path", ["raw", "dataset"])
+def test_image_gradient_matches_oracle(N, M, path):
+    dev = device()
+    gal = _gal()
+    d = np.float64
+    case = wl.random_case(N, M, seed=1700 + N, fill=0.85)
+    re, im = _obs(case)
+    c2o, go = oracle.grad_image(case.image, case.dxy, case.u, case.v, re, im, case.w, case.PA,
+                                case.dRA, case.dDec, case.inc)
+    args = [t(a, d, dev) for a in (case.u, case.v, re, im, case.w)]
+    img = t(case.image, d, dev)
+    kw = dict(PA=case.PA, dRA=case.dRA, dDec=case.dDec, inc=case.inc)
+    if path == "raw":
+        c2g, gg = gal.chi2Image_grad(img, case.dxy, *args, **kw)
+    else:
+        ds = gal.Dataset(*args)
+        c2g, gg = ds.chi2Image_grad(img, case.dxy, **kw)
+    assert abs(float(c2g) - c2o) <= 1e-10 * c2o
+    assert _rel(gg.cpu().numpy(), go) <= 1e-8
+
+
+@pytest.mark.parametrize("N,M,Nr", [(16, 400, 12), (64, 5001, 70), (256, 20003, 301)])
+@pytest.mark.parametrize("path", ["raw", "dataset"])
+def test_profile_gradient_matches_oracle(N, M, Nr, path):
+    dev = device()
+    gal = _gal()
+    d = np.float64
+    case = wl.random_case(N, M, seed=1800 + N, kind="profile", Nr=Nr, fill=0.85)
+    re, im = _obs(case)
+    c2o, go = oracle.grad_profile(case.I, case.Rmin, case.dR, N, case.dxy, case.u, case.v, re,
+                                  im, case.w, case.inc, case.PA, case.dRA, case.dDec)
+    args = [t(a, d, dev) for a in (case.u, case.v, re, im, case.w)]
+    I = t(case.I, d, dev)
+    kw = dict(inc=case.inc, PA=case.PA, dRA=case.dRA, dDec=case.dDec)
+    if path == "raw":
+        c2g, gg = gal.chi2Profile_grad(I, case.Rmin, case.dR, N, case.dxy, *args, **kw)
+    else:
+        ds = gal.Dataset(*args)
+        c2g, gg = ds.chi2Profile_grad(I, case.Rmin, case.dR, N, case.dxy, **kw)
+    assert abs(float(c2g) - c2o) <= 1e-10 * c2o
+    assert _rel(gg.cpu().numpy(), go) <= 1e-8, _rel(gg.cpu().numpy(), go)
+
+
+def test_profile_gradient_central_differences_on_gpu():
+    # chi^2 is quadratic in I: (chi2(I + h e_j) - chi2(I - h e_j)) / 2h is exact
+    dev = device()
+    gal = _gal()
+    d = np.float64
+    case = wl.random_case(512, 50000, seed=1900, kind="profile", Nr=700, fill=0.8)
+    re, im = _obs(case, offset=0.2)
+    ds = gal.Dataset(*(t(a, d, dev) for a in (case.u, case.v, re, im, case.w)))
+    I = t(case.I, d, dev)
+    kw = dict(inc=case.inc, PA=case.PA, dRA=case.dRA, dDec=case.dDec)
+    _, g = ds.chi2Profile_grad(I, case.Rmin, case.dR, 512, case.dxy, **kw)
+    g = g.cpu().numpy()
+    rng = np.random.default_rng(1901)
+    idx = rng.choice(case.I.size, 32, replace=False)
+    h = 0.1 * np.max(np.abs(case.I))
+    fd = []
+    for j in idx:
+        Ip, Im = I.clone(), I.clone()
+        Ip[j] += h
+        Im[j] -= h
+        fp = float(ds.chi2Profile(Ip, case.Rmin, case.dR, 512, case.dxy, **kw))
+        fm = float(ds.chi2Profile(Im, case.Rmin, case.dR, 512, case.dxy, **kw))
+        fd.append((fp - fm) / (2 * h))
+    fd = np.array(fd)
+    assert _rel(g[idx], fd) < 1e-6, _rel(g[idx], fd)
+
+
+def test_autograd_through_profile_and_image():
+    dev = device()
+    gal = _gal()
+    import torch
+
+    d = np.float64
+    case = wl.random_case(128, 8000, seed=2000, kind="profile", Nr=150)
+    re, im = _obs(case)
+    ds = gal.Dataset(*(t(a, d, dev) for a in (case.u, case.v, re, im, case.w)))
+    I = t(case.I, d, dev).requires_grad_(True)
+    loss = 0.5 * gal.chi2_profile(ds, I, case.Rmin, case.dR, 128, case.dxy, case.inc, case.PA,
+                                  case.dRA, case.dDec)
+    (gI,) = torch.autograd.grad(loss, I)
+    _, go = oracle.grad_profile(case.I, case.Rmin, case.dR, 128, case.dxy, case.u, case.v, re, im,
+                                case.w, case.inc, case.PA, case.dRA, case.dDec)
+    assert _rel(gI.cpu().numpy(), 0.5 * go) <= 1e-8
+    img = gal.sweep(I.detach(), case.Rmin, case.dR, 128, case.dxy, case.inc).requires_grad_(True)
+    loss2 = gal.chi2_image(ds, img, case.dxy, case.PA, case.dRA, case.dDec)
+    (gimg,) = torch.autograd.grad(loss2, img)
+    _, gio = oracle.grad_image(img.detach().cpu().numpy(), case.dxy, case.u, case.v, re, im,
+                               case.w, case.PA, case.dRA, case.dDec)
+    assert _rel(gimg.cpu().numpy(), gio) <= 1e-8
+
+
+def test_fp32_gradients_close_to_fp64_oracle():
+    dev = device()
+    gal = _gal()
+    f = np.float32
+    case = wl.random_case(128, 10000, seed=2100, kind="profile", Nr=120)
+    re, im = _obs(case, offset=0.3)
+    ds = gal.Dataset(*(t(a, f, dev) for a in (case.u, case.v, re, im, case.w)))
+    _, g = ds.chi2Profile_grad(t(case.I, f, dev), case.Rmin, case.dR, 128, case.dxy, case.inc,
+                               case.PA, case.dRA, case.dDec)
+    _, go = oracle.grad_profile(rounded(case.I, f), case.Rmin, case.dR, 128, case.dxy,
+                                rounded(case.u, f), rounded(case.v, f), rounded(re, f),
+                                rounded(im, f), rounded(case.w, f), case.inc, case.PA, case.dRA,
+                                case.dDec)
+    assert _rel(g.cpu().numpy().astype(np.float64), go) <= 1e-3
+
+
+def test_config1_profile_gradient_full_size():
+    # the benchmark workload (2048^2, M = 1e6, Nr = 4096) against the oracle
+    dev = device()
+    gal = _gal()
+    d = np.float64
+    c = wl.config1()
+    Vo = oracle.sampleProfile(c.I, c.Rmin, c.dR, c.N, c.dxy, c.u, c.v, c.inc, c.PA, c.dRA, c.dDec)
+    re, im = 1.02 * Vo.real + c.noise_re, Vo.imag + c.noise_im
+    c2o, go = oracle.grad_profile(c.I, c.Rmin, c.dR, c.N, c.dxy, c.u, c.v, re, im, c.w, c.inc,
+                                  c.PA, c.dRA, c.dDec)
+    ds = gal.Dataset(*(t(a, d, dev) for a in (c.u, c.v, re, im, c.w)))
+    c2g, g = ds.chi2Profile_grad(t(c.I, d, dev), c.Rmin, c.dR, c.N, c.dxy, c.inc, c.PA, c.dRA,
+                                 c.dDec)
+    err = _rel(g.cpu().numpy(), go)
+    print(f"config1 gradient: rel l2 {err:.3e}, chi2 {float(c2g):.15g} vs {c2o:.15g}", flush=True)
+    assert abs(float(c2g) - c2o) <= 1e-10 * c2o
+    assert err <= 1e-8
