@@ -94,6 +94,59 @@ def _kernel_times(gal, fn, steps, torch):
     return {k: {"avg_us": 1e3 * ms / n, "launches": n} for k, (ms, n) in times.items()}
 
 
+def serve_bench(gal, torch, np, dev, rates, n_req, warm, grad_frac, n_datasets, max_M):
+    """Poisson stream of chi2Profile (+ gradient) requests against resident
+    datasets, served by the continuous-batching loop; latency and throughput
+    per arrival rate."""
+    import workloads as wl
+    from paper_1709_06999_amd.serve import GpuExecutor, Request, Server
+
+    ex = GpuExecutor(dev, torch.float64, max_batch=16, max_inflight=4)
+    f64 = lambda a: torch.as_tensor(np.ascontiguousarray(a, dtype=np.float64), device=dev)
+    # each dataset observes a fixed "true" profile at 2048^2 (model from the library) plus noise
+    truth = wl.serve_requests(1, seed=1549)[0]
+    Nm = 2048
+    for dset in wl.serve_datasets(n_datasets, (100_000, max_M)):
+        u, v = f64(dset["u"]), f64(dset["v"])
+        Vm = gal.sampleProfile(f64(truth["I"]), truth["Rmin"], truth["dR"] * (truth["Nxy"] / Nm),
+                               Nm, truth["dxy"], u, v, truth["inc"], truth["PA"])
+        ex.add_dataset(dset["name"], dset["u"], dset["v"],
+                       Vm.real.cpu().numpy() + dset["noise_re"],
+                       Vm.imag.cpu().numpy() + dset["noise_im"], dset["w"])
+    rng = np.random.default_rng(1550)
+    out = {}
+    for rate in rates:
+        params = wl.serve_requests(n_req + warm, seed=int(1551 + rate))
+        srv = Server(ex, max_batch=16, max_inflight=4).start()
+        gaps = rng.exponential(1.0 / rate, n_req + warm)
+        t_next = time.perf_counter()
+        futs = []
+        for i, prm in enumerate(params):
+            t_next += gaps[i]
+            while time.perf_counter() < t_next:
+                pass
+            futs.append(srv.submit(Request(grad=bool(rng.random() < grad_frac), **prm)))
+            if i == warm - 1:
+                for f in futs:
+                    f.result(timeout=120)
+                srv.latencies.clear()
+                srv.completed = 0
+                srv._t_first = None
+        for f in futs:
+            f.result(timeout=300)
+        srv.stop()
+        st = srv.stats()
+        out[str(rate)] = {"offered_req_per_s": rate,
+                          "evals_per_s": round(st["evals_per_s"], 1) if st["evals_per_s"] else None,
+                          "p50_ms": round(st["p50_ms"], 3), "p99_ms": round(st["p99_ms"], 3),
+                          "requests": st["completed"], "micro_batches": st["batches"],
+                          "peak_hbm_MB": round(st["peak_hbm_bytes"] / 1e6, 1)}
+    return {"workload": f"{n_datasets} resident datasets (M log-uniform in [1e5, {max_M:.0e}]), "
+                        "requests: chi2Profile with Nxy in {512, 1024, 2048}, Nr in [512, 4096], "
+                        f"{int(100 * grad_frac)}% with the adjoint gradient, Poisson arrivals",
+            "per_rate": out}
+
+
 def main():
     ap = argparse.ArgumentParser(description=__doc__.split("\n")[0])
     ap.add_argument("--gpus", type=int, default=1)
@@ -107,6 +160,10 @@ def main():
     ap.add_argument("--calib-copy", action="store_true",
                     help="also run one 256 MiB device-to-device copy (a known-size kernel for "
                          "scaling HBM byte counters)")
+    ap.add_argument("--no-serve", action="store_true", help="skip the served-load section")
+    ap.add_argument("--serve-rates", default="500,2000,5000",
+                    help="Poisson arrival rates (requests/s) of the served-load section")
+    ap.add_argument("--serve-requests", type=int, default=1000, help="timed requests per rate")
     ap.add_argument("--kind", choices=["profile", "image"], default="profile",
                     help="plain path: chi2Profile (default) or chi2Image of the swept image")
     args = ap.parse_args()
@@ -125,7 +182,7 @@ def main():
     dev = torch.device("cuda", 0)
     torch.cuda.set_device(dev)
     gal.init(0)
-    case = wl.config1()
+    case = wl.profile_2048()
     N, M, Nr = case.N, case.M, case.I.size
     f64 = lambda a: torch.as_tensor(np.ascontiguousarray(a, dtype=np.float64), device=dev)
     I, u, v = f64(case.I), f64(case.u), f64(case.v)
@@ -221,6 +278,11 @@ def main():
                 "step_frac": round(sum(ab_batch.values()) / (ms_batch * 1e-3) / 1e9 /
                                    HBM_PEAK_GBS, 4)}
 
+    served = None
+    if not args.no_serve:
+        served = serve_bench(gal, torch, np, dev, [int(r) for r in args.serve_rates.split(",")],
+                             args.serve_requests, 200, 0.5, 8, 2_000_000)
+
     cpu = None
     if not args.no_cpu_baseline:
         import oracle
@@ -266,6 +328,7 @@ def main():
                                  "p99": round(float(np.percentile(lat, 99)), 4)},
                   "kernels": rnd(kern_plain)},
         "batched_vs_plain": round(evals_per_s / (1e3 / ms_plain), 3),
+        "served": served,
         "kernels": rnd(kern),
         "roofline": roofline,
         "cpu_baseline": cpu,

@@ -57,6 +57,17 @@ class Request:
         return (self.dataset, int(self.Nxy), float(self.dxy), int(np.size(self.I)), bool(self.grad))
 
 
+def _settle(fut: Future, result=None, exc: BaseException | None = None):
+    """Resolve a future unless the client cancelled it meanwhile."""
+    try:
+        if exc is not None:
+            fut.set_exception(exc)
+        else:
+            fut.set_result(result)
+    except Exception:  # InvalidStateError: cancelled concurrently
+        pass
+
+
 class Server:
     """Continuous-batching scheduler (see the module docstring)."""
 
@@ -128,6 +139,9 @@ class Server:
 
     # -- scheduler ---------------------------------------------------------
     def _loop(self):
+        bind = getattr(self.ex, "bind_thread", None)
+        if bind is not None:
+            bind()
         while self._run:
             progressed = False
             with self._lock:
@@ -141,7 +155,7 @@ class Server:
                     if r.future.cancelled():
                         continue
                     if r.deadline is not None and now > r.deadline:
-                        r.future.set_exception(TimeoutError("deadline passed while queued"))
+                        _settle(r.future, exc=TimeoutError("deadline passed while queued"))
                         self.expired += 1
                         continue
                     keep.append(r)
@@ -154,8 +168,7 @@ class Server:
                     results = self.ex.collect(handle)
                     t = time.perf_counter()
                     for r, res in zip(reqs, results):
-                        if not r.future.cancelled():
-                            r.future.set_result(res)
+                        _settle(r.future, res)
                         self.latencies.append(t - r.arrival)
                     self.completed += len(reqs)
                     self._t_last = t
@@ -173,7 +186,7 @@ class Server:
                 fp_one = self.ex.footprint([head])
                 if fp_one > self.budget:
                     self._pending.popleft()
-                    head.future.set_exception(MemoryError(
+                    _settle(head.future, exc=MemoryError(
                         f"request needs {fp_one} bytes of device memory, budget {self.budget}"))
                     self.rejected += 1
                     continue
@@ -189,7 +202,7 @@ class Server:
                     handle = self.ex.launch(group, slot)
                 except Exception as e:  # launch errors go to the callers
                     for r in group:
-                        r.future.set_exception(e)
+                        _settle(r.future, exc=e)
                     self._free_slots.append(slot)
                     continue
                 if self._t_first is None:
@@ -228,6 +241,9 @@ class GpuExecutor:
     def default_budget(self) -> int:
         free, total = self.torch.cuda.mem_get_info(self.device)
         return int(0.8 * free)
+
+    def bind_thread(self):
+        self.torch.cuda.set_device(self.device)
 
     def add_dataset(self, name, u, v, re, im, w):
         t = lambda a: self.torch.as_tensor(np.ascontiguousarray(a), dtype=self.dtype,

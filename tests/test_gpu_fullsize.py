@@ -25,10 +25,10 @@ def _gal():
     return gal
 
 
-def test_config0_chi2Image_256_full_oracle():
+def test_gaussian_image_256_M1e4_full_oracle():
     dev = device()
     gal = _gal()
-    c = wl.config0()
+    c = wl.gaussian_image_256()
     d = np.float64
     kw = dict(PA=c.PA, dRA=c.dRA, dDec=c.dDec, inc=c.inc)
     Vo = oracle.sampleImage(c.image, c.dxy, c.u, c.v, **kw)
@@ -38,29 +38,29 @@ def test_config0_chi2Image_256_full_oracle():
     args = [t(a, d, dev) for a in (c.u, c.v, re, im, c.w)]
     c2g = float(gal.chi2Image(img, c.dxy, *args, **kw))
     Vg = gal.sampleImage(img, c.dxy, args[0], args[1], **kw).cpu().numpy()
-    assert_vis_close(Vg, Vo, d, "config0 raw")
+    assert_vis_close(Vg, Vo, d, "gaussian 256 raw")
     assert abs(c2g - c2o) <= chi2_bound(c2o, Vg - Vo, c.w)
     ds = gal.Dataset(*args)
     c2d = float(ds.chi2Image(img, c.dxy, **kw))
     Vd = ds.sampleImage(img, c.dxy, **kw).cpu().numpy()
-    assert_vis_close(Vd, Vo, d, "config0 dataset")
+    assert_vis_close(Vd, Vo, d, "gaussian 256 dataset")
     assert abs(c2d - c2o) <= chi2_bound(c2o, Vd - Vo, c.w)
     # chi^2 at the noise level: E = 2M, sd = 2 sqrt(M)
     assert abs(c2o - 2 * c.M) < 6 * 2 * np.sqrt(c.M)
 
 
 @pytest.fixture(scope="module")
-def config1_oracle():
-    c = wl.config1()
+def profile_2048_oracle():
+    c = wl.profile_2048()
     Vo = oracle.sampleProfile(c.I, c.Rmin, c.dR, c.N, c.dxy, c.u, c.v, c.inc, c.PA, c.dRA, c.dDec)
     return c, Vo
 
 
 @pytest.mark.parametrize("dtype", [np.float64, np.float32])
-def test_config1_chi2Profile_2048_M1e6_full_oracle(config1_oracle, dtype):
+def test_profile_2048_M1e6_full_oracle(profile_2048_oracle, dtype):
     dev = device()
     gal = _gal()
-    c, Vo64 = config1_oracle
+    c, Vo64 = profile_2048_oracle
     if dtype == np.float32:
         Vo = oracle.sampleProfile(rounded(c.I, dtype), c.Rmin, c.dR, c.N, c.dxy,
                                   rounded(c.u, dtype), rounded(c.v, dtype), c.inc, c.PA, c.dRA,
@@ -74,12 +74,12 @@ def test_config1_chi2Profile_2048_M1e6_full_oracle(config1_oracle, dtype):
     I = t(c.I, dtype, dev)
     kw = dict(inc=c.inc, PA=c.PA, dRA=c.dRA, dDec=c.dDec)
     Vd = ds.sampleProfile(I, c.Rmin, c.dR, c.N, c.dxy, **kw).cpu().numpy()
-    err = assert_vis_close(Vd, Vo, dtype, "config1")
+    err = assert_vis_close(Vd, Vo, dtype, "profile 2048")
     c2d = float(ds.chi2Profile(I, c.Rmin, c.dR, c.N, c.dxy, **kw))
     c2o = oracle.chi2(Vo, re, im, w)
     dV = np.abs(Vd - Vo) + (np.abs(Vd) * 2.0**-23 if dtype == np.float32 else 0.0)
     assert abs(c2d - c2o) <= chi2_bound(c2o, dV, w), (c2d, c2o)
-    print(f"config1 {np.dtype(dtype).name}: max|dV|/max|V| = {err:.3e}, chi2 gpu {c2d:.15g} "
+    print(f"profile 2048 {np.dtype(dtype).name}: max|dV|/max|V| = {err:.3e}, chi2 gpu {c2d:.15g} "
           f"oracle {c2o:.15g}", flush=True)
     # the same through the raw-array call (full spectrum)
     c2r = float(gal.chi2Profile(I, c.Rmin, c.dR, c.N, c.dxy, *(t(a, dtype, dev) for a in
@@ -89,15 +89,15 @@ def test_config1_chi2Profile_2048_M1e6_full_oracle(config1_oracle, dtype):
 
 
 @pytest.fixture(scope="module")
-def config2_case():
-    return wl.config2()
+def blobs_4096_case():
+    return wl.blobs_4096()
 
 
 @pytest.mark.parametrize("dtype", [np.float64, np.float32])
-def test_config2_chi2Image_4096_M5e6_sampled(config2_case, dtype):
+def test_blobs_4096_M5e6_sampled(blobs_4096_case, dtype):
     dev = device()
     gal = _gal()
-    c = config2_case
+    c = blobs_4096_case
     # observations: noise only (a full oracle model at 5e6 points is not needed
     # for parity; the model enters through V, checked point by point)
     re, im, w = rounded(c.noise_re, dtype), rounded(c.noise_im, dtype), rounded(c.w, dtype)

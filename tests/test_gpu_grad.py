@@ -144,12 +144,12 @@ def test_fp32_gradients_close_to_fp64_oracle():
     assert _rel(g.cpu().numpy().astype(np.float64), go) <= 1e-3
 
 
-def test_config1_profile_gradient_full_size():
+def test_profile_2048_gradient_full_size():
     # the benchmark workload (2048^2, M = 1e6, Nr = 4096) against the oracle
     dev = device()
     gal = _gal()
     d = np.float64
-    c = wl.config1()
+    c = wl.profile_2048()
     Vo = oracle.sampleProfile(c.I, c.Rmin, c.dR, c.N, c.dxy, c.u, c.v, c.inc, c.PA, c.dRA, c.dDec)
     re, im = 1.02 * Vo.real + c.noise_re, Vo.imag + c.noise_im
     c2o, go = oracle.grad_profile(c.I, c.Rmin, c.dR, c.N, c.dxy, c.u, c.v, re, im, c.w, c.inc,
@@ -158,6 +158,6 @@ def test_config1_profile_gradient_full_size():
     c2g, g = ds.chi2Profile_grad(t(c.I, d, dev), c.Rmin, c.dR, c.N, c.dxy, c.inc, c.PA, c.dRA,
                                  c.dDec)
     err = _rel(g.cpu().numpy(), go)
-    print(f"config1 gradient: rel l2 {err:.3e}, chi2 {float(c2g):.15g} vs {c2o:.15g}", flush=True)
+    print(f"profile 2048 gradient: rel l2 {err:.3e}, chi2 {float(c2g):.15g} vs {c2o:.15g}", flush=True)
     assert abs(float(c2g) - c2o) <= 1e-10 * c2o
     assert err <= 1e-8

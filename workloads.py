@@ -160,7 +160,7 @@ class Workload:
         return int(self.u.size)
 
 
-def config0() -> Workload:
+def gaussian_image_256() -> Workload:
     """chi2Image, 256^2 FP64: elliptical Gaussian (1 Jy, sigma 0.2'' N-S and
     0.2'' cos 30 deg E-W, i.e. a 30 deg inclination in the image itself),
     dxy = 0.01'', M = 10^4 uniform in a disk of radius 0.4 / dxy,
@@ -170,13 +170,13 @@ def config0() -> Workload:
     img = gaussian_image(N, dxy, 1.0, sig * math.cos(30 * DEG), sig)
     u, v = uv_uniform_disk(10_000, 0.4 / dxy, seed=1000)
     nre, nim, w = noise(u.size, 1e-3, seed=1001)
-    return Workload("config0_chi2Image_256_M1e4", "image", N, dxy, u, v, nre, nim, w,
+    return Workload("gaussian_chi2Image_256_M1e4", "image", N, dxy, u, v, nre, nim, w,
                     PA=60 * DEG, inc=0.0, dRA=0.05 * ARCSEC, dDec=0.05 * ARCSEC, image=img,
                     meta={"image_inclination_deg": 30.0})
 
 
-def config1_profile(Nr: int = 4096):
-    """The gapped power-law profile of config 1 in Jy/sr, normalised to a
+def gapped_profile(Nr: int = 4096):
+    """The gapped power-law profile in Jy/sr, normalised to a
     face-on flux of 1 Jy, on r_j = Rmin + j dR out to 5.4''."""
     Rmin_as = 1e-4
     Rmax_as = 5.4
@@ -187,26 +187,26 @@ def config1_profile(Nr: int = 4096):
     return I, Rmin_as * ARCSEC, dR_as * ARCSEC
 
 
-def config1(M: int = 1_000_000) -> Workload:
+def profile_2048(M: int = 1_000_000) -> Workload:
     """chi2Profile, 2048^2 FP64: Nr = 4096 profile, dxy = 0.003'', M = 10^6
     uv points log-uniform in [1.877e5, 1.2457e7] lambda (ALMA C43-10 at
     1.3 mm), inc = 45 deg, PA = 120 deg, noise sigma 1e-3 Jy."""
     N, dxy = 2048, 0.003 * ARCSEC
-    I, Rmin, dR = config1_profile()
+    I, Rmin, dR = gapped_profile()
     u, v = uv_log_uniform(M, 1.877e5, 1.2457e7, seed=1100)
     nre, nim, w = noise(u.size, 1e-3, seed=1101)
-    return Workload("config1_chi2Profile_2048_M1e6", "profile", N, dxy, u, v, nre, nim, w,
+    return Workload("gapped_chi2Profile_2048_M1e6", "profile", N, dxy, u, v, nre, nim, w,
                     PA=120 * DEG, inc=45 * DEG, I=I, Rmin=Rmin, dR=dR)
 
 
-def config2(M: int = 5_000_000) -> Workload:
+def blobs_4096(M: int = 5_000_000) -> Workload:
     """chi2Image, 4096^2: 200 Gaussian blobs, dxy = 0.013'' (ALMA C43-6),
     M = 5e6 log-uniform in [1.123e4, 1.936e6] lambda, noise sigma 1e-3 Jy."""
     N, dxy = 4096, 0.013 * ARCSEC
     img = blob_image(N, dxy, 200, seed=1200)
     u, v = uv_log_uniform(M, 1.123e4, 1.936e6, seed=1201)
     nre, nim, w = noise(u.size, 1e-3, seed=1202)
-    return Workload("config2_chi2Image_4096_M5e6", "image", N, dxy, u, v, nre, nim, w,
+    return Workload("blobs_chi2Image_4096_M5e6", "image", N, dxy, u, v, nre, nim, w,
                     PA=0.0, inc=0.0, image=img)
 
 
@@ -240,3 +240,51 @@ def random_case(N: int, M: int, seed: int, kind: str = "image", fill: float = 0.
     I = np.exp(-((r / (0.15 * N * dxy)) ** 2)) * (1.0 + 0.3 * rng.random(Nr)) / dxy**2
     return Workload(f"random_profile_N{N}_M{M}_s{seed}", "profile", N, dxy, u, v, nre, nim, w,
                     PA=PA, inc=inc, dRA=dRA, dDec=dDec, I=I, Rmin=Rmin, dR=dR)
+
+
+# ----------------------------------------------------------------------------
+# served load: 8 resident datasets and a Poisson stream of profile requests
+SERVE_DXY = 1.0 / (2.0 * 2.5e6)   # rad: f_max = 2.5 at rho_max = 1e6 lambda for every N
+
+
+def serve_datasets(n: int = 8, M_range=(100_000, 2_000_000), seed0: int = 1500):
+    """Datasets d: M_d log-uniform in M_range, uv log-uniform radius in
+    [2e4, 1e6] lambda, noise sigma 1e-3 (observed = model + noise, the model
+    supplied by the caller)."""
+    out = []
+    for d in range(n):
+        rng = np.random.default_rng(seed0 + d)
+        M = int(round(math.exp(rng.uniform(math.log(M_range[0]), math.log(M_range[1])))))
+        u, v = uv_log_uniform(M, 2e4, 1e6, seed=seed0 + 100 + d)
+        nre, nim, w = noise(M, 1e-3, seed=seed0 + 200 + d)
+        out.append({"name": f"d{d}", "u": u, "v": v, "noise_re": nre, "noise_im": nim, "w": w})
+    return out
+
+
+def serve_requests(n: int, seed: int, n_datasets: int = 8):
+    """Request parameters: dataset uniform, Nxy in {512, 1024, 2048}, Nr in
+    U{512..4096}, a gapped power-law profile with random gap positions and
+    depths, Rmin = 1e-4 N dxy, R_max = 1.05 (N/2) dxy sqrt(1/cos^2 i + 1),
+    inc ~ U[0, 70 deg], PA ~ U[0, 180 deg), offsets ~ N(0, (5 dxy)^2)."""
+    rng = np.random.default_rng(seed)
+    dxy = SERVE_DXY
+    reqs = []
+    for _ in range(n):
+        d = int(rng.integers(0, n_datasets))
+        N = int(rng.choice([512, 1024, 2048]))
+        Nr = int(rng.integers(512, 4097))
+        inc = rng.uniform(0.0, 70.0) * DEG
+        PA = rng.uniform(0.0, 180.0) * DEG
+        dRA, dDec = rng.normal(0.0, 5 * dxy, 2)
+        Rmin = 1e-4 * N * dxy
+        Rmax = 1.05 * (N / 2) * dxy * math.sqrt(1.0 / math.cos(inc) ** 2 + 1.0)
+        dR = (Rmax - Rmin) / (Nr - 1)
+        r_as = (Rmin + dR * np.arange(Nr)) / ARCSEC
+        scale = (N / 2) * dxy / ARCSEC / 5.0            # profile scale relative to the field
+        gaps = ((rng.uniform(0.2, 0.8) * scale, 0.02 * scale, rng.uniform(0.3, 0.9)),
+                (rng.uniform(0.2, 0.8) * scale, 0.04 * scale, rng.uniform(0.3, 0.9)))
+        I = gapped_powerlaw_profile(r_as / scale, gaps=tuple((g[0] / scale, g[1] / scale, g[2])
+                                                              for g in gaps)) * 1e10
+        reqs.append({"dataset": f"d{d}", "I": I, "Rmin": Rmin, "dR": dR, "Nxy": N, "dxy": dxy,
+                     "inc": inc, "PA": PA, "dRA": float(dRA), "dDec": float(dDec)})
+    return reqs
