@@ -288,6 +288,17 @@ int gal_batch_info(const gal_batch *b, int *n_jobs, int *n_fft_groups, int *n_sa
 /* chi2[j] (device doubles) for every job; bitwise repeatable. */
 int gal_batch_chi2(const gal_batch *b, double *chi2, void *ws, size_t ws_bytes, void *stream);
 int gal_batch_destroy(gal_batch *b);
+/* One-shot execution of a job list (any mix of kinds, sizes, datasets and
+ * precisions), planned on the host at every call; the plan's device table
+ * travels in the workspace (copied with hipMemcpyAsync from host memory that
+ * may be freed when the call returns), so nothing is allocated.  grads
+ * (nullable) holds one gradient output per job (device, dataset precision:
+ * image [Nxy*Nxy] or profile [Nr]; NULL = chi^2 only); gradient jobs run the
+ * adjoint path of the gradient calls above.  Workspace:
+ * gal_batch_exec_workspace_bytes (first 256 bytes zeroed once; 0 on error). */
+size_t gal_batch_exec_workspace_bytes(const gal_job *jobs, int n, void *const *grads);
+int gal_batch_exec(const gal_job *jobs, int n, double *chi2, void *const *grads, void *ws,
+                   size_t ws_bytes, void *stream);
 
 /* ---- FFT schedule autotuning -------------------------------------------
  * Every FFT pass exists in NVAR = 3 compiled variants that differ in the

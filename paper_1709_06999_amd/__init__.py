@@ -33,7 +33,7 @@ __all__ = [
     "sweep", "sampleImage", "sampleProfile", "chi2Image", "chi2Profile", "spectrum",
     "sample_spectrum", "Dataset", "Workspace", "read_status", "timing", "GalarioError",
     "version", "init", "autotune", "tune_get", "tune_set", "Batch", "profile_batch",
-    "JOB_IMAGE", "JOB_PROFILE", "chi2Image_grad", "chi2Profile_grad", "chi2_profile", "chi2_image",
+    "JOB_IMAGE", "JOB_PROFILE", "batch_exec", "chi2Image_grad", "chi2Profile_grad", "chi2_profile", "chi2_image",
 ]
 
 JOB_IMAGE = 0
@@ -111,6 +111,9 @@ class Workspace:
                 int(Nxy), int(M), int(grad_Nr))
         if need == 0:
             raise GalarioError(-2, f"workspace size (Nxy={Nxy}, M={M})")
+        return self.reserve_bytes(need)
+
+    def reserve_bytes(self, need: int) -> torch.Tensor:
         if self.buf.numel() < need:
             self.buf = torch.zeros(int(need), dtype=torch.uint8, device=self.device)
         return self.buf
@@ -436,6 +439,21 @@ class Dataset:
 
 
 # ----------------------------------------------------------------------------
+def _job_array(jobs, dev: torch.device):
+    arr = (_native.GalJob * len(jobs))()
+    for i, j in enumerate(jobs):
+        ds = j["ds"]
+        if ds.device != dev:
+            raise ValueError(f"job {i}: dataset on {ds.device}, expected {dev}")
+        m, geo = j["model"], j["geo"]
+        _arr(m, "model", ds.dtype, dev)
+        _arr(geo, "geo", torch.float64, dev, 6)
+        arr[i] = _native.GalJob(ds._h.value, int(j["kind"]), int(j["Nxy"]), float(j["dxy"]),
+                                int(m.numel()) if j["kind"] == JOB_PROFILE else 0,
+                                m.data_ptr(), geo.data_ptr())
+    return arr
+
+
 class Batch:
     """A planned list of chi^2 jobs evaluated together (gal_batch_*).
 
@@ -451,15 +469,7 @@ class Batch:
             raise ValueError("a batch needs at least one job")
         self.jobs = list(jobs)
         dev = self.jobs[0]["ds"].device
-        arr = (_native.GalJob * len(self.jobs))()
-        for i, j in enumerate(self.jobs):
-            ds = j["ds"]
-            m, geo = j["model"], j["geo"]
-            _arr(m, "model", ds.dtype, dev)
-            _arr(geo, "geo", torch.float64, dev, 6)
-            arr[i] = _native.GalJob(ds._h.value, int(j["kind"]), int(j["Nxy"]), float(j["dxy"]),
-                                    int(m.numel()) if j["kind"] == JOB_PROFILE else 0,
-                                    m.data_ptr(), geo.data_ptr())
+        arr = _job_array(self.jobs, dev)
         self.device = dev
         h = ctypes.c_void_p(0)
         with torch.cuda.device(dev):
@@ -504,6 +514,48 @@ def profile_batch(ds: "Dataset", I: torch.Tensor, geo: torch.Tensor, Nxy: int, d
         raise ValueError("I must be [K, Nr] and geo [K, 6]")
     return Batch([{"ds": ds, "kind": JOB_PROFILE, "Nxy": Nxy, "dxy": dxy, "model": I[k],
                    "geo": geo[k]} for k in range(I.shape[0])])
+
+
+_exec_ws: dict = {}
+
+
+def batch_exec(jobs, grads=None, out: torch.Tensor | None = None,
+               ws: Workspace | None = None) -> torch.Tensor:
+    """One-shot chi^2 (and optional gradients) of a job list, planned at this
+    call (gal_batch_exec): any mix of kinds, sizes, datasets and precisions.
+
+    ``jobs`` as for ``Batch``; ``grads`` (optional) is a list with one entry
+    per job: None (chi^2 only) or a device tensor of the model's shape and
+    dtype that receives d chi^2 / d model.  Returns chi^2 as a device float64
+    tensor [n], on the current stream.  Nothing is allocated beyond the
+    (growing, per-device) workspace."""
+    jobs = list(jobs)
+    if not jobs:
+        raise ValueError("batch_exec needs at least one job")
+    dev = jobs[0]["ds"].device
+    arr = _job_array(jobs, dev)
+    gp = None
+    if grads is not None:
+        if len(grads) != len(jobs):
+            raise ValueError("grads needs one entry per job")
+        gp = (ctypes.c_void_p * len(jobs))()
+        for i, (j, g) in enumerate(zip(jobs, grads)):
+            if g is not None:
+                _arr(g, "grad", j["ds"].dtype, dev, j["model"].numel())
+                gp[i] = g.data_ptr()
+    need = _lib().gal_batch_exec_workspace_bytes(arr, len(jobs), gp)
+    if need == 0:
+        raise GalarioError(-2, "batch_exec plan")
+    if ws is None:
+        key = dev.index if dev.index is not None else torch.cuda.current_device()
+        ws = _exec_ws.setdefault(key, Workspace(torch.device("cuda", key), torch.float64))
+    buf = ws.reserve_bytes(int(need))
+    res = torch.empty(len(jobs), dtype=torch.float64, device=dev) if out is None else out
+    _arr(res, "out", torch.float64, dev, len(jobs))
+    with torch.cuda.device(dev):
+        check(_lib().gal_batch_exec(arr, len(jobs), _ptr(res), gp, _ptr(buf), buf.numel(),
+                                    _stream(dev)), "batch_exec")
+    return res
 
 
 # ----------------------------------------------------------------------------

@@ -64,6 +64,8 @@ _SIG = {
     "gal_batch_info": (I, [P, ctypes.POINTER(I), ctypes.POINTER(I), ctypes.POINTER(I)]),
     "gal_batch_chi2": (I, [P, P, P, SZ, P]),
     "gal_batch_destroy": (I, [P]),
+    "gal_batch_exec_workspace_bytes": (SZ, [P, I, P]),
+    "gal_batch_exec": (I, [P, I, P, P, P, SZ, P]),
     "gal_autotune": (I, [I, D, P, ctypes.POINTER(I), ctypes.POINTER(D)]),
     "gal_tune_get": (I, [I, I, ctypes.POINTER(I)]),
     "gal_tune_set": (I, [I, I, ctypes.POINTER(I)]),

@@ -11,6 +11,7 @@
 // so one plan (and a HIP graph captured from it) serves every step of a
 // fitter that updates those buffers in place.
 #pragma once
+#include "adjoint.h"
 #include "kernels.h"
 
 namespace gal {
@@ -20,8 +21,11 @@ constexpr int KMAX = 16;  // jobs sharing one pass over a dataset
 struct JobDesc {
     const void *src;     // image [N*N] or profile [Nr], dataset precision
     const double *geo;   // Rmin, dR, inc, PA, dRA, dDec
+    void *grad;          // gradient output (dataset precision), NULL: chi^2 only
     size_t spec_off;     // spectrum slot: byte offset in the workspace
     size_t part_off;     // partial sums: byte offset in the workspace
+    size_t a_off;        // scatter grid of a gradient job
+    size_t gi_off;       // profile-bin accumulator (double) of a gradient profile job
     int kind;            // 0 image, 1 profile
     int N, Nr, Q, P, CS, Qe;
     double dxy;
@@ -119,9 +123,38 @@ __device__ __forceinline__ double sample_real_at(const T *__restrict__ S, const 
     return 0.0;
 }
 
+// Residual of one point scattered onto the four nodes of its stencil (the
+// adjoint of the sampling; see adjoint.h for the derivation).
+template <typename T>
+__device__ __forceinline__ void scatter_real(T *A, const T *S, const StencilR<T> &st, int CS,
+                                             double h) {
+    const double s = st.s, t = st.t;
+    const double wl = st.swap ? t : (1.0 - t), wh = st.swap ? (1.0 - t) : t;
+    T *c0 = A + (st.c0 - S);
+    atomicAdd(c0, (T)(h * wl * (1.0 - s)));
+    atomicAdd(c0 + 1, (T)(h * wh * (1.0 - s)));
+    atomicAdd(c0 + CS, (T)(h * wl * s));
+    atomicAdd(c0 + CS + 1, (T)(h * wh * s));
+}
+
+template <typename T>
+__device__ __forceinline__ void scatter_cplx(T *A, const c2<T> *S, const Stencil<T> &st, int CS,
+                                             double h, double ar, double ai) {
+    const double s = st.s, t = st.t;
+    const double wts[4] = {(1.0 - t) * (1.0 - s), t * (1.0 - s), (1.0 - t) * s, t * s};
+    const int offs[4] = {0, 1, CS, CS + 1};
+    T *c0 = A + 2 * (st.c0 - S);
+#pragma unroll
+    for (int n = 0; n < 4; ++n) {
+        atomicAdd(c0 + 2 * offs[n], (T)(h * wts[n] * ar));
+        atomicAdd(c0 + 2 * offs[n] + 1, (T)(h * wts[n] * ai));
+    }
+}
+
 // Block -> group by binary search over the groups' first blocks; each thread
 // keeps SAMPLE_PPT points in registers and evaluates every job of the group.
-template <typename T, bool REAL>
+// GRAD: jobs with a gradient output also scatter their residuals.
+template <typename T, bool REAL, bool GRAD>
 __global__ __launch_bounds__(SAMPLE_NT) void kb_sample_chi2(const JobDesc *__restrict__ jobs,
                                                             const SGroup *__restrict__ groups,
                                                             int ngroups, char *ws) {
@@ -160,16 +193,34 @@ __global__ __launch_bounds__(SAMPLE_NT) void kb_sample_chi2(const JobDesc *__res
         for (int p = 0; p < PPT; ++p) {
             double Vre, Vim;
             bool ok;
+            const bool in = base + p * SAMPLE_NT < G.M;
             if constexpr (REAL) {
-                sample_real_at<T>((const T *)(ws + J.spec_off), g, a, uu[p], vv[p], ok, Vre, Vim);
+                const T *S = (const T *)(ws + J.spec_off);
+                sample_real_at<T>(S, g, a, uu[p], vv[p], ok, Vre, Vim);
+                if (GRAD && J.grad && in && ok) {
+                    // Re(conj(R) e^{i theta}) with e^{i theta} = V / (cinc b)
+                    const StencilR<T> st = locate_r<T>(S, g, a, uu[p], vv[p]);
+                    double sn, cs;
+                    sincospi(2.0 * (uu[p] * a.dRA + vv[p] * a.dDec), &sn, &cs);
+                    const double R0 = rr[p] - Vre, R1 = ii[p] - Vim;
+                    scatter_real<T>((T *)(ws + J.a_off), S, st, g.CS,
+                                    ww[p] * a.cinc * (R0 * cs + R1 * sn));
+                }
             } else {
                 const c2<T> *S = (const c2<T> *)(ws + J.spec_off);
                 const Stencil<T> st = locate<T>(S, g, a, uu[p], vv[p]);
                 ok = st.ok;
                 finish<T>(st, st.c0[0], st.c0[1], st.c0[g.CS], st.c0[g.CS + 1], a, uu[p], vv[p],
                           Vre, Vim);
+                if (GRAD && J.grad && in && ok) {
+                    double sn, cs;
+                    sincospi(2.0 * (uu[p] * a.dRA + vv[p] * a.dDec), &sn, &cs);
+                    const double R0 = rr[p] - Vre, R1 = ii[p] - Vim;
+                    const double ar = R0 * cs + R1 * sn;
+                    const double ai = st.mirror ? (R1 * cs - R0 * sn) : (R0 * sn - R1 * cs);
+                    scatter_cplx<T>((T *)(ws + J.a_off), S, st, g.CS, ww[p] * a.cinc, ar, ai);
+                }
             }
-            const bool in = base + p * SAMPLE_NT < G.M;
             bad |= in && !ok;
             if (in) {
                 const double dr = Vre - rr[p], di = Vim - ii[p];
@@ -196,6 +247,49 @@ __global__ __launch_bounds__(SAMPLE_NT) void kb_reduce(const JobDesc *__restrict
     for (int k = threadIdx.x; k < n; k += SAMPLE_NT) s += part[k];
     const double tot = block_sum(s, red);
     if (threadIdx.x == 0) chi2[j] = tot;
+}
+
+// ---- adjoint passes of gradient jobs: blockIdx.y selects the job ------------
+template <typename T, typename Cfg>
+__global__ __launch_bounds__(Cfg::NT) void kb_adj_cols(const JobDesc *__restrict__ jobs,
+                                                       const int *__restrict__ list, char *ws) {
+    const JobDesc &j = jobs[list[blockIdx.y]];
+    adj_cols_body<T, Cfg>(geom_of(j), (c2<T> *)(ws + j.a_off), blockIdx.x);
+}
+
+template <typename T, typename Cfg>
+__global__ __launch_bounds__(Cfg::NT) void kb_adj_rows(const JobDesc *__restrict__ jobs,
+                                                       const int *__restrict__ list, char *ws) {
+    const JobDesc &j = jobs[list[blockIdx.y]];
+    adj_rows_body<T, Cfg>(geom_of(j), (const c2<T> *)(ws + j.a_off), (T *)j.grad, blockIdx.x);
+}
+
+template <typename T, typename Cfg>
+__global__ __launch_bounds__(Cfg::NT) void kb_adj_cols_sym(const JobDesc *__restrict__ jobs,
+                                                           const int *__restrict__ list,
+                                                           char *ws) {
+    const JobDesc &j = jobs[list[blockIdx.y]];
+    adj_cols_sym_body<T, Cfg>(geom_of(j), j.Qe, (T *)(ws + j.a_off), blockIdx.x);
+}
+
+template <typename T, typename Cfg>
+__global__ __launch_bounds__(Cfg::NT) void kb_adj_rows_sym(const JobDesc *__restrict__ jobs,
+                                                           const int *__restrict__ list,
+                                                           char *ws) {
+    extern __shared__ double hist[];
+    const JobDesc &j = jobs[list[blockIdx.y]];
+    const SweepArgs sw = sweep_from_geo(j.geo, j.Nr, j.dxy);
+    adj_rows_sym_body<T, Cfg>(geom_of(j), (const T *)(ws + j.a_off), sw,
+                              (double *)(ws + j.gi_off), hist, blockIdx.x);
+}
+
+// profile gradients: the double accumulator into the caller's array
+template <typename T>
+__global__ __launch_bounds__(256) void kb_grad_out(const JobDesc *__restrict__ jobs,
+                                                   const int *__restrict__ list, const char *ws) {
+    const JobDesc &j = jobs[list[blockIdx.y]];
+    const int i = blockIdx.x * 256 + threadIdx.x;
+    if (i < j.Nr) ((T *)j.grad)[i] = (T)((const double *)(ws + j.gi_off))[i];
 }
 
 }  // namespace gal

@@ -755,17 +755,20 @@ struct gal_dataset {
     int32_t *perm;  // perm[k] = registration index of stored point k
 };
 
-// a planned batch (see batch.h)
-struct gal_batch {
-    int device = 0;
+// A batch plan (see batch.h): per-job descriptors, sample groups, FFT groups
+// and the workspace layout.  Built on the host only; where the device table
+// lives depends on the caller (own allocation or the workspace).
+struct BatchPlan {
     int n = 0;
+    bool grads = false;
     std::vector<JobDesc> jobs;
-    std::vector<SGroup> groups;    // sorted by sample class
-    std::vector<int> job_group;    // job -> group
+    std::vector<SGroup> groups;     // sorted by sample class
+    std::vector<int> job_group;     // job -> group
     struct FGroup {
-        int prec, kind, N, list_off, count, maxQ, maxQe;
+        int prec, kind, N, list_off, count, maxQ, maxQe, maxNr;
     };
-    std::vector<FGroup> fgroups;
+    std::vector<FGroup> fgroups;    // FFT groups (all jobs)
+    std::vector<FGroup> agroups;    // adjoint groups (gradient jobs)
     std::vector<int> lists;
     struct SClass {
         int prec;
@@ -773,12 +776,15 @@ struct gal_batch {
         int group_off, count, blocks;
     };
     std::vector<SClass> sclasses;
+    size_t table_bytes = 0;         // jobs | groups | lists | job_group
+    size_t zero_begin = 0, zero_end = 0;  // scatter grids and bin accumulators
     size_t ws_need = 0;
-    void *dtab = nullptr;          // device copy of jobs | groups | lists | job_group
-    JobDesc *d_jobs = nullptr;
-    SGroup *d_groups = nullptr;
-    int *d_lists = nullptr;
-    int *d_job_group = nullptr;
+};
+
+struct gal_batch {
+    int device = 0;
+    BatchPlan plan;
+    void *dtab = nullptr;           // device copy of the plan's table
 };
 
 // The definitions below take their C linkage from the declarations in the
@@ -1347,38 +1353,45 @@ GAL_PROFILE_GRAD_DS(d, double)
 GAL_PROFILE_GRAD_DS(f, float)
 
 // ---- batches --------------------------------------------------------------
-int gal_batch_create(const gal_job *jobs, int n, gal_batch **out) {
-    if (!out || (n > 0 && !jobs)) return fail(GAL_ERR_NULL, "NULL argument");
-    *out = nullptr;
+// Plan a job list: checks, geometry, sample groups (same dataset, kind and
+// grid, <= KMAX jobs), FFT groups (same precision, kind and size), adjoint
+// groups (the gradient jobs), workspace layout starting at `base`:
+// [partials][spectra][scatter grids][bin accumulators].
+static int plan_batch(const gal_job *jobs, int n, void *const *grads, size_t base,
+                      BatchPlan &P) {
     if (n < 1) return fail(GAL_ERR_SIZE, "a batch needs at least one job");
-    int rc = ensure_init();
-    if (rc) return rc;
-    gal_batch *b = new gal_batch();
-    GAL_HIP(hipGetDevice(&b->device));
-    b->n = n;
-    b->jobs.resize(n);
-    b->job_group.assign(n, -1);
-    // per-job checks and geometry
+    if (!jobs) return fail(GAL_ERR_NULL, "NULL jobs");
+    int dev = 0;
+    GAL_HIP(hipGetDevice(&dev));
+    P = BatchPlan();
+    P.n = n;
+    P.jobs.resize(n);
+    P.job_group.assign(n, -1);
     for (int i = 0; i < n; ++i) {
         const gal_job &J = jobs[i];
-        auto bad = [&](int code, const char *what) {
-            delete b;
-            return fail(code, "job %d: %s", i, what);
-        };
-        if (!J.ds || !J.model || !J.geo) return bad(GAL_ERR_NULL, "NULL dataset, model or geo");
-        if (!J.ds->re) return bad(GAL_ERR_UNSUPPORTED, "dataset holds no observations");
-        if (J.kind != 0 && J.kind != 1) return bad(GAL_ERR_UNSUPPORTED, "kind must be 0 or 1");
-        if (!pow2_in_range(J.Nxy)) return bad(GAL_ERR_SIZE, "Nxy unsupported");
-        if (!(J.dxy > 0.0) || !std::isfinite(J.dxy)) return bad(GAL_ERR_SCALAR, "dxy must be > 0");
-        if (J.kind == 1 && J.Nr < 2) return bad(GAL_ERR_SIZE, "Nr < 2");
-        if (J.ds->device != b->device) return bad(GAL_ERR_UNSUPPORTED, "dataset on another device");
+        if (!J.ds || !J.model || !J.geo) return fail(GAL_ERR_NULL, "job %d: NULL dataset, model or geo", i);
+        if (!J.ds->re) return fail(GAL_ERR_UNSUPPORTED, "job %d: dataset holds no observations", i);
+        if (J.kind != 0 && J.kind != 1) return fail(GAL_ERR_UNSUPPORTED, "job %d: kind must be 0 or 1", i);
+        if (!pow2_in_range(J.Nxy)) return fail(GAL_ERR_SIZE, "job %d: Nxy unsupported", i);
+        if (!(J.dxy > 0.0) || !std::isfinite(J.dxy)) return fail(GAL_ERR_SCALAR, "job %d: dxy must be > 0", i);
+        if (J.kind == 1 && J.Nr < 2) return fail(GAL_ERR_SIZE, "job %d: Nr < 2", i);
+        if (J.ds->device != dev) return fail(GAL_ERR_UNSUPPORTED, "job %d: dataset on another device", i);
         const double du = 1.0 / ((double)J.Nxy * J.dxy);
         if (!(J.ds->rho_max < ((double)(J.Nxy / 2) - 1.0) * du))
-            return bad(GAL_ERR_UV_RANGE, "dataset rho_max reaches beyond the half spectrum");
+            return fail(GAL_ERR_UV_RANGE, "job %d: dataset rho_max reaches beyond the half spectrum", i);
+        void *gr = grads ? grads[i] : nullptr;
+        if (gr && J.kind == 1) {
+            if (J.Nr > GRAD_NR_MAX) return fail(GAL_ERR_SIZE, "job %d: gradient needs Nr <= %d", i, GRAD_NR_MAX);
+            const size_t lds = (size_t)cols_B(J.Nxy) * J.Nxy * 2 * (size_t)J.ds->precision +
+                               (size_t)J.Nr * sizeof(double);
+            if (lds > (size_t)160 * 1024) return fail(GAL_ERR_SIZE, "job %d: Nr too large for Nxy", i);
+        }
         const Geom g = geom_pruned(J.Nxy, J.dxy, J.ds->rho_max);
-        JobDesc &d = b->jobs[i];
+        JobDesc &d = P.jobs[i];
+        d = JobDesc{};
         d.src = J.model;
         d.geo = J.geo;
+        d.grad = gr;
         d.kind = J.kind;
         d.N = J.Nxy;
         d.Nr = J.kind == 1 ? J.Nr : 0;
@@ -1387,10 +1400,10 @@ int gal_batch_create(const gal_job *jobs, int n, gal_batch **out) {
         d.Qe = (g.Q + 1) & ~1;
         d.CS = J.kind == 1 ? J.Nxy / 2 + 2 : g.CS;
         d.dxy = J.dxy;
+        P.grads = P.grads || gr;
     }
-    // sample groups: same dataset, kind and grid, at most KMAX jobs each
     for (int i = 0; i < n; ++i) {
-        if (b->job_group[i] >= 0) continue;
+        if (P.job_group[i] >= 0) continue;
         const gal_job &Ji = jobs[i];
         SGroup G{};
         G.u = Ji.ds->u;
@@ -1402,118 +1415,129 @@ int gal_batch_create(const gal_job *jobs, int n, gal_batch **out) {
         G.nj = 0;
         for (int k = i; k < n && G.nj < KMAX; ++k) {
             const gal_job &Jk = jobs[k];
-            if (b->job_group[k] >= 0 || Jk.ds != Ji.ds || Jk.kind != Ji.kind ||
+            if (P.job_group[k] >= 0 || Jk.ds != Ji.ds || Jk.kind != Ji.kind ||
                 Jk.Nxy != Ji.Nxy || Jk.dxy != Ji.dxy)
                 continue;
-            b->job_group[k] = (int)b->groups.size();
+            P.job_group[k] = (int)P.groups.size();
             G.jobs[G.nj++] = k;
         }
         G.nblk = (int)sample_blocks(G.M);
-        b->groups.push_back(G);
+        P.groups.push_back(G);
     }
-    // order groups by sample class (precision, real spectrum) and number blocks
-    std::vector<int> order(b->groups.size());
-    for (size_t g = 0; g < order.size(); ++g) order[g] = (int)g;
-    auto cls = [&](int g) {
-        const JobDesc &d = b->jobs[b->groups[g].jobs[0]];
-        const int prec = jobs[b->groups[g].jobs[0]].ds->precision;
-        return (prec == 8 ? 0 : 2) + (d.kind == 1 ? 1 : 0);
+    auto cls = [&](const SGroup &G) {
+        return (jobs[G.jobs[0]].ds->precision == 8 ? 0 : 2) + (jobs[G.jobs[0]].kind == 1 ? 1 : 0);
     };
-    std::stable_sort(order.begin(), order.end(), [&](int a, int c) { return cls(a) < cls(c); });
+    std::vector<int> order(P.groups.size());
+    for (size_t g = 0; g < order.size(); ++g) order[g] = (int)g;
+    std::stable_sort(order.begin(), order.end(),
+                     [&](int a, int c) { return cls(P.groups[a]) < cls(P.groups[c]); });
     std::vector<SGroup> sorted;
     std::vector<int> remap(order.size());
     for (size_t k = 0; k < order.size(); ++k) {
         remap[order[k]] = (int)k;
-        sorted.push_back(b->groups[order[k]]);
+        sorted.push_back(P.groups[order[k]]);
     }
-    b->groups.swap(sorted);
-    for (int i = 0; i < n; ++i) b->job_group[i] = remap[b->job_group[i]];
-    for (size_t g = 0; g < b->groups.size(); ++g) {
-        const int c = cls((int)g);
-        if (b->sclasses.empty() || (b->sclasses.back().prec == (c < 2 ? 8 : 4) &&
-                                    b->sclasses.back().real == ((c & 1) == 1)) == false) {
-            b->sclasses.push_back({c < 2 ? 8 : 4, (c & 1) == 1, (int)g, 0, 0});
-        }
-        gal_batch::SClass &sc = b->sclasses.back();
-        b->groups[g].blk0 = sc.blocks;
-        sc.blocks += b->groups[g].nblk;
+    P.groups.swap(sorted);
+    for (int i = 0; i < n; ++i) P.job_group[i] = remap[P.job_group[i]];
+    for (size_t g = 0; g < P.groups.size(); ++g) {
+        const int c = cls(P.groups[g]);
+        const int prec = c < 2 ? 8 : 4;
+        const bool real = (c & 1) == 1;
+        if (P.sclasses.empty() || P.sclasses.back().prec != prec || P.sclasses.back().real != real)
+            P.sclasses.push_back({prec, real, (int)g, 0, 0});
+        BatchPlan::SClass &sc = P.sclasses.back();
+        P.groups[g].blk0 = sc.blocks;
+        sc.blocks += P.groups[g].nblk;
         sc.count += 1;
     }
-    // FFT groups: same precision, kind and size
-    for (int i = 0; i < n; ++i) {
-        const int prec = jobs[i].ds->precision;
-        bool found = false;
-        for (auto &f : b->fgroups)
-            if (f.prec == prec && f.kind == jobs[i].kind && f.N == jobs[i].Nxy) found = true;
-        if (found) continue;
-        gal_batch::FGroup f{prec, jobs[i].kind, jobs[i].Nxy, (int)b->lists.size(), 0, 0, 0};
-        for (int k = i; k < n; ++k)
-            if (jobs[k].ds->precision == prec && jobs[k].kind == f.kind && jobs[k].Nxy == f.N) {
-                b->lists.push_back(k);
+    auto make_groups = [&](bool grad_only, std::vector<BatchPlan::FGroup> &out) {
+        std::vector<char> used(n, 0);
+        for (int i = 0; i < n; ++i) {
+            if (used[i] || (grad_only && !P.jobs[i].grad)) continue;
+            const int prec = jobs[i].ds->precision;
+            BatchPlan::FGroup f{prec, jobs[i].kind, jobs[i].Nxy, (int)P.lists.size(), 0, 0, 0, 0};
+            for (int k = i; k < n; ++k) {
+                if (used[k] || (grad_only && !P.jobs[k].grad)) continue;
+                if (jobs[k].ds->precision != prec || jobs[k].kind != f.kind || jobs[k].Nxy != f.N)
+                    continue;
+                used[k] = 1;
+                P.lists.push_back(k);
                 f.count += 1;
-                f.maxQ = max_c(f.maxQ, b->jobs[k].Q);
-                f.maxQe = max_c(f.maxQe, b->jobs[k].Qe);
+                f.maxQ = max_c(f.maxQ, P.jobs[k].Q);
+                f.maxQe = max_c(f.maxQe, P.jobs[k].Qe);
+                f.maxNr = max_c(f.maxNr, P.jobs[k].Nr);
             }
-        b->fgroups.push_back(f);
-    }
-    // workspace: control | partials per job | spectrum slot per job
-    size_t off = 256;
+            out.push_back(f);
+        }
+    };
+    make_groups(false, P.fgroups);
+    make_groups(true, P.agroups);
+    // layout
+    P.table_bytes = align256(sizeof(JobDesc) * n) + align256(sizeof(SGroup) * P.groups.size()) +
+                    align256(sizeof(int) * P.lists.size()) + align256(sizeof(int) * n);
+    size_t off = base;
     for (int i = 0; i < n; ++i) {
-        b->jobs[i].part_off = off;
-        off += align256((size_t)b->groups[b->job_group[i]].nblk * sizeof(double));
+        P.jobs[i].part_off = off;
+        off += align256((size_t)P.groups[P.job_group[i]].nblk * sizeof(double));
     }
-    for (int i = 0; i < n; ++i) {
-        const JobDesc &d = b->jobs[i];
+    auto spec_bytes = [&](int i) {
+        const JobDesc &d = P.jobs[i];
         const size_t el = (size_t)jobs[i].ds->precision;
-        const size_t bytes = d.kind == 1 ? (size_t)d.Qe * d.CS * el : (size_t)d.Q * d.CS * 2 * el;
-        b->jobs[i].spec_off = off;
-        off += align256(bytes);
+        return d.kind == 1 ? (size_t)d.Qe * d.CS * el : (size_t)d.Q * d.CS * 2 * el;
+    };
+    for (int i = 0; i < n; ++i) {
+        P.jobs[i].spec_off = off;
+        off += align256(spec_bytes(i));
     }
-    b->ws_need = off;
-    // device tables
-    const size_t s1 = align256(sizeof(JobDesc) * n);
-    const size_t s2 = align256(sizeof(SGroup) * b->groups.size());
-    const size_t s3 = align256(sizeof(int) * b->lists.size());
-    const size_t s4 = align256(sizeof(int) * n);
-    if (hipMalloc(&b->dtab, s1 + s2 + s3 + s4) != hipSuccess) {
-        delete b;
-        return fail(GAL_ERR_WORKSPACE, "out of device memory for a batch table");
+    P.zero_begin = off;
+    for (int i = 0; i < n; ++i) {
+        if (!P.jobs[i].grad) continue;
+        P.jobs[i].a_off = off;
+        off += align256(spec_bytes(i));
+        if (P.jobs[i].kind == 1) {
+            P.jobs[i].gi_off = off;
+            off += align256((size_t)P.jobs[i].Nr * sizeof(double));
+        }
     }
-    char *p = (char *)b->dtab;
-    b->d_jobs = (JobDesc *)p;
-    b->d_groups = (SGroup *)(p + s1);
-    b->d_lists = (int *)(p + s1 + s2);
-    b->d_job_group = (int *)(p + s1 + s2 + s3);
-    bool ok = hipMemcpy(b->d_jobs, b->jobs.data(), sizeof(JobDesc) * n, hipMemcpyHostToDevice) ==
-                  hipSuccess &&
-              hipMemcpy(b->d_groups, b->groups.data(), sizeof(SGroup) * b->groups.size(),
-                        hipMemcpyHostToDevice) == hipSuccess &&
-              hipMemcpy(b->d_lists, b->lists.data(), sizeof(int) * b->lists.size(),
-                        hipMemcpyHostToDevice) == hipSuccess &&
-              hipMemcpy(b->d_job_group, b->job_group.data(), sizeof(int) * n,
-                        hipMemcpyHostToDevice) == hipSuccess;
-    if (!ok) {
-        (void)hipFree(b->dtab);
-        delete b;
-        return fail(GAL_ERR_HIP, "batch table upload failed");
-    }
-    *out = b;
+    P.zero_end = off;
+    P.ws_need = off;
     return GAL_OK;
 }
 
-size_t gal_batch_workspace_bytes(const gal_batch *b) { return b ? b->ws_need : 0; }
+struct BatchTables {
+    JobDesc *jobs;
+    SGroup *groups;
+    int *lists;
+    int *job_group;
+};
 
-int gal_batch_info(const gal_batch *b, int *n_jobs, int *n_fft_groups, int *n_sample_groups) {
-    if (!b) return fail(GAL_ERR_NULL, "NULL batch");
-    if (n_jobs) *n_jobs = b->n;
-    if (n_fft_groups) *n_fft_groups = (int)b->fgroups.size();
-    if (n_sample_groups) *n_sample_groups = (int)b->groups.size();
-    return GAL_OK;
+static BatchTables tables_at(const BatchPlan &P, void *base) {
+    char *p = (char *)base;
+    BatchTables t;
+    t.jobs = (JobDesc *)p;
+    p += align256(sizeof(JobDesc) * P.n);
+    t.groups = (SGroup *)p;
+    p += align256(sizeof(SGroup) * P.groups.size());
+    t.lists = (int *)p;
+    p += align256(sizeof(int) * P.lists.size());
+    t.job_group = (int *)p;
+    return t;
+}
+
+// host copy of the table, laid out as on the device
+static std::vector<char> table_image(const BatchPlan &P) {
+    std::vector<char> h(P.table_bytes, 0);
+    BatchTables t = tables_at(P, h.data());
+    std::memcpy(t.jobs, P.jobs.data(), sizeof(JobDesc) * P.n);
+    std::memcpy(t.groups, P.groups.data(), sizeof(SGroup) * P.groups.size());
+    if (!P.lists.empty()) std::memcpy(t.lists, P.lists.data(), sizeof(int) * P.lists.size());
+    std::memcpy(t.job_group, P.job_group.data(), sizeof(int) * P.n);
+    return h;
 }
 
 template <typename T>
-static int batch_fft(const gal_batch *b, const gal_batch::FGroup &f, char *ws, hipStream_t s) {
-    FftJobB j{b->d_jobs, b->d_lists + f.list_off, f.count, f.maxQ, f.maxQe, ws, s};
+static int batch_fft(const BatchPlan::FGroup &f, const BatchTables &t, char *ws, hipStream_t s) {
+    FftJobB j{t.jobs, t.lists + f.list_off, f.count, f.maxQ, f.maxQe, ws, s};
     const int k1 = f.kind == 1 ? K_ROWS_SYM : K_ROWS_IMG;
     const int k2 = f.kind == 1 ? K_COLS_SYM : K_COLS;
     FftFnB r = fft_fn_b<T>(f.N, k1, chosen_var<T>(f.N, k1));
@@ -1524,34 +1548,128 @@ static int batch_fft(const gal_batch *b, const gal_batch::FGroup &f, char *ws, h
     return c(j);
 }
 
+template <typename T, int N>
+static int batch_adj_n(const BatchPlan::FGroup &f, const BatchTables &t, char *ws, hipStream_t s) {
+    constexpr int B = cols_B(N);
+    using C = CfgE<T, N, B, 8>;
+    const int *list = t.lists + f.list_off;
+    int rc;
+    if (f.kind == 1) {
+        rc = launch("kb_adj_cols_sym", kb_adj_cols_sym<T, C>, dim3((f.maxQe / 2 + B - 1) / B, f.count),
+                    dim3(C::NT), s, t.jobs, list, ws);
+        if (rc) return rc;
+        rc = launch_sm("kb_adj_rows_sym", kb_adj_rows_sym<T, C>,
+                       dim3((N / 4 + 1 + B - 1) / B, f.count), dim3(C::NT),
+                       (unsigned)(f.maxNr * sizeof(double)), s, t.jobs, list, ws);
+        if (rc) return rc;
+        return launch("kb_grad_out", kb_grad_out<T>, dim3((f.maxNr + 255) / 256, f.count), dim3(256),
+                      s, t.jobs, list, ws);
+    }
+    rc = launch("kb_adj_cols", kb_adj_cols<T, C>, dim3((f.maxQ + B - 1) / B, f.count), dim3(C::NT),
+                s, t.jobs, list, ws);
+    if (rc) return rc;
+    return launch("kb_adj_rows", kb_adj_rows<T, C>, dim3((N / 2 + B - 1) / B, f.count), dim3(C::NT),
+                  s, t.jobs, list, ws);
+}
+
+template <typename T>
+static int batch_adj(const BatchPlan::FGroup &f, const BatchTables &t, char *ws, hipStream_t s) {
+    switch (f.N) {
+        case 16: return batch_adj_n<T, 16>(f, t, ws, s);
+        case 32: return batch_adj_n<T, 32>(f, t, ws, s);
+        case 64: return batch_adj_n<T, 64>(f, t, ws, s);
+        case 128: return batch_adj_n<T, 128>(f, t, ws, s);
+        case 256: return batch_adj_n<T, 256>(f, t, ws, s);
+        case 512: return batch_adj_n<T, 512>(f, t, ws, s);
+        case 1024: return batch_adj_n<T, 1024>(f, t, ws, s);
+        case 2048: return batch_adj_n<T, 2048>(f, t, ws, s);
+        case 4096: return batch_adj_n<T, 4096>(f, t, ws, s);
+        case 8192: return batch_adj_n<T, 8192>(f, t, ws, s);
+        default: return fail(GAL_ERR_SIZE, "Nxy=%d unsupported", f.N);
+    }
+}
+
+template <typename T, bool REAL>
+static int batch_sample(const BatchPlan::SClass &c, bool grads, const BatchTables &t, char *ws,
+                        hipStream_t s) {
+    const SGroup *g = t.groups + c.group_off;
+    const dim3 grid(c.blocks), blk(SAMPLE_NT);
+    const char *name = REAL ? "kb_sample_sym_chi2" : "kb_sample_chi2";
+    if (grads) return launch(name, kb_sample_chi2<T, REAL, true>, grid, blk, s, t.jobs, g, c.count, ws);
+    return launch(name, kb_sample_chi2<T, REAL, false>, grid, blk, s, t.jobs, g, c.count, ws);
+}
+
+static int exec_plan(const BatchPlan &P, const BatchTables &t, char *ws, double *chi2, hipStream_t s) {
+    int rc = GAL_OK;
+    if (P.zero_end > P.zero_begin) {
+        rc = launch("k_zero", k_zero<double>, dim3(256), dim3(256), s, ws + P.zero_begin,
+                    (int64_t)((P.zero_end - P.zero_begin) / sizeof(double)));
+        if (rc) return rc;
+    }
+    for (const auto &f : P.fgroups) {
+        rc = f.prec == 8 ? batch_fft<double>(f, t, ws, s) : batch_fft<float>(f, t, ws, s);
+        if (rc) return rc;
+    }
+    for (const auto &c : P.sclasses) {
+        if (c.prec == 8)
+            rc = c.real ? batch_sample<double, true>(c, P.grads, t, ws, s)
+                        : batch_sample<double, false>(c, P.grads, t, ws, s);
+        else
+            rc = c.real ? batch_sample<float, true>(c, P.grads, t, ws, s)
+                        : batch_sample<float, false>(c, P.grads, t, ws, s);
+        if (rc) return rc;
+    }
+    rc = launch("kb_reduce", kb_reduce, dim3(P.n), dim3(SAMPLE_NT), s, t.jobs, t.groups, t.job_group,
+                ws, chi2);
+    if (rc) return rc;
+    for (const auto &f : P.agroups) {
+        rc = f.prec == 8 ? batch_adj<double>(f, t, ws, s) : batch_adj<float>(f, t, ws, s);
+        if (rc) return rc;
+    }
+    return GAL_OK;
+}
+
+int gal_batch_create(const gal_job *jobs, int n, gal_batch **out) {
+    if (!out) return fail(GAL_ERR_NULL, "NULL argument");
+    *out = nullptr;
+    int rc = ensure_init();
+    if (rc) return rc;
+    gal_batch *b = new gal_batch();
+    rc = plan_batch(jobs, n, nullptr, 256, b->plan);
+    if (rc) {
+        delete b;
+        return rc;
+    }
+    GAL_HIP(hipGetDevice(&b->device));
+    if (hipMalloc(&b->dtab, b->plan.table_bytes) != hipSuccess) {
+        delete b;
+        return fail(GAL_ERR_WORKSPACE, "out of device memory for a batch table");
+    }
+    const std::vector<char> h = table_image(b->plan);
+    if (hipMemcpy(b->dtab, h.data(), h.size(), hipMemcpyHostToDevice) != hipSuccess) {
+        (void)hipFree(b->dtab);
+        delete b;
+        return fail(GAL_ERR_HIP, "batch table upload failed");
+    }
+    *out = b;
+    return GAL_OK;
+}
+
+size_t gal_batch_workspace_bytes(const gal_batch *b) { return b ? b->plan.ws_need : 0; }
+
+int gal_batch_info(const gal_batch *b, int *n_jobs, int *n_fft_groups, int *n_sample_groups) {
+    if (!b) return fail(GAL_ERR_NULL, "NULL batch");
+    if (n_jobs) *n_jobs = b->plan.n;
+    if (n_fft_groups) *n_fft_groups = (int)b->plan.fgroups.size();
+    if (n_sample_groups) *n_sample_groups = (int)b->plan.groups.size();
+    return GAL_OK;
+}
+
 int gal_batch_chi2(const gal_batch *b, double *chi2, void *ws, size_t ws_bytes_, void *stream) {
     if (!b || !chi2 || !ws) return fail(GAL_ERR_NULL, "NULL argument");
-    if (ws_bytes_ < b->ws_need)
-        return fail(GAL_ERR_WORKSPACE, "workspace of %zu bytes, need %zu", ws_bytes_, b->ws_need);
-    hipStream_t s = (hipStream_t)stream;
-    char *w = (char *)ws;
-    int rc = GAL_OK;
-    for (const auto &f : b->fgroups) {
-        rc = f.prec == 8 ? batch_fft<double>(b, f, w, s) : batch_fft<float>(b, f, w, s);
-        if (rc) return rc;
-    }
-    for (const auto &c : b->sclasses) {
-        const SGroup *g = b->d_groups + c.group_off;
-        const dim3 grid(c.blocks), blk(SAMPLE_NT);
-        if (c.prec == 8)
-            rc = c.real ? launch("kb_sample_sym_chi2", kb_sample_chi2<double, true>, grid, blk, s,
-                                 b->d_jobs, g, c.count, w)
-                        : launch("kb_sample_chi2", kb_sample_chi2<double, false>, grid, blk, s,
-                                 b->d_jobs, g, c.count, w);
-        else
-            rc = c.real ? launch("kb_sample_sym_chi2", kb_sample_chi2<float, true>, grid, blk, s,
-                                 b->d_jobs, g, c.count, w)
-                        : launch("kb_sample_chi2", kb_sample_chi2<float, false>, grid, blk, s,
-                                 b->d_jobs, g, c.count, w);
-        if (rc) return rc;
-    }
-    return launch("kb_reduce", kb_reduce, dim3(b->n), dim3(SAMPLE_NT), s, b->d_jobs, b->d_groups,
-                  b->d_job_group, w, chi2);
+    if (ws_bytes_ < b->plan.ws_need)
+        return fail(GAL_ERR_WORKSPACE, "workspace of %zu bytes, need %zu", ws_bytes_, b->plan.ws_need);
+    return exec_plan(b->plan, tables_at(b->plan, b->dtab), (char *)ws, chi2, (hipStream_t)stream);
 }
 
 int gal_batch_destroy(gal_batch *b) {
@@ -1564,6 +1682,42 @@ int gal_batch_destroy(gal_batch *b) {
     delete b;
     if (e != hipSuccess) return fail(GAL_ERR_HIP, "hipFree: %s", hipGetErrorString(e));
     return GAL_OK;
+}
+
+// one-shot execution: the table travels in the workspace (after its control block)
+size_t gal_batch_exec_workspace_bytes(const gal_job *jobs, int n, void *const *grads) {
+    BatchPlan P;
+    if (plan_batch(jobs, n, grads, 256, P) != GAL_OK) return 0;
+    return align256(256 + P.table_bytes) + (P.ws_need - 256);
+}
+
+int gal_batch_exec(const gal_job *jobs, int n, double *chi2, void *const *grads, void *ws,
+                   size_t ws_bytes_, void *stream) {
+    if (!chi2 || !ws) return fail(GAL_ERR_NULL, "NULL argument");
+    int rc = ensure_init();
+    if (rc) return rc;
+    BatchPlan P;
+    rc = plan_batch(jobs, n, grads, 256, P);
+    if (rc) return rc;
+    const size_t tab = align256(256 + P.table_bytes) - 256;  // table after the control block
+    const size_t need = P.ws_need + tab;
+    if (ws_bytes_ < need) return fail(GAL_ERR_WORKSPACE, "workspace of %zu bytes, need %zu", ws_bytes_, need);
+    // shift the data layout past the table
+    for (auto &j : P.jobs) {
+        j.part_off += tab;
+        j.spec_off += tab;
+        if (j.grad) {
+            j.a_off += tab;
+            if (j.kind == 1) j.gi_off += tab;
+        }
+    }
+    P.zero_begin += tab;
+    P.zero_end += tab;
+    hipStream_t s = (hipStream_t)stream;
+    char *w = (char *)ws;
+    const std::vector<char> h = table_image(P);
+    GAL_HIP(hipMemcpyAsync(w + 256, h.data(), h.size(), hipMemcpyHostToDevice, s));
+    return exec_plan(P, tables_at(P, w + 256), w, chi2, s);
 }
 
 // ---- autotuning ----------------------------------------------------------

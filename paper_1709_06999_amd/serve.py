@@ -11,11 +11,13 @@ the GPU.
    admitted only while the footprints in flight stay within the HBM budget;
    otherwise it waits until earlier work completes.  A request that cannot
    fit even on an idle device is rejected (MemoryError).
- - Batching.  Queued chi^2-only requests on the same dataset, image grid and
-   profile length form one micro-batch, evaluated by one planned batch
-   (models and geometry written into the plan's device slots, so the uv data
-   is read once for the whole micro-batch).  Gradient requests run the
-   adjoint path, one call each, in the micro-batch's stream.
+ - Batching.  An executor that evaluates mixed job lists (``mixed_batches``
+   true, as ``GpuExecutor``) receives the queue's oldest requests in arrival
+   order, whatever their datasets, grids, profile lengths and gradient
+   flags: one micro-batch is one batch_exec call (FFTs of equal shape share
+   launches, requests on one dataset share its pass over the uv data, the
+   gradient requests add the adjoint passes).  Other executors receive
+   requests of one key (dataset, grid, profile length, gradient flag).
  - Deadlines and cancellation.  A request whose deadline passes while it is
    queued fails with TimeoutError; a cancelled future is dropped.
  - Latency is completion minus arrival on the host clock (time.perf_counter).
@@ -27,6 +29,7 @@ HIP one.
 from __future__ import annotations
 
 import collections
+import itertools
 import threading
 import time
 from concurrent.futures import Future
@@ -77,6 +80,7 @@ class Server:
         self.max_batch = int(max_batch)
         self.max_inflight = int(max_inflight)
         self.budget = hbm_budget if hbm_budget is not None else executor.default_budget()
+        self.mixed = bool(getattr(executor, "mixed_batches", False))
         self.idle_wait = idle_wait
         self._in = collections.deque()
         self._lock = threading.Lock()
@@ -181,8 +185,11 @@ class Server:
             # admit new micro-batches while slots and memory allow
             while self._pending and self._free_slots:
                 head = self._pending[0]
-                key = head.key()
-                group = [r for r in self._pending if r.key() == key][: self.max_batch]
+                if self.mixed:
+                    group = list(itertools.islice(self._pending, self.max_batch))
+                else:
+                    key = head.key()
+                    group = [r for r in self._pending if r.key() == key][: self.max_batch]
                 fp_one = self.ex.footprint([head])
                 if fp_one > self.budget:
                     self._pending.popleft()
@@ -217,26 +224,57 @@ class Server:
                 self._wake.clear()
 
 
+class _Slot:
+    """Staging buffers of one in-flight slot: pinned host and device copies of
+    the packed models, geometry rows, chi^2 and gradient outputs, and the
+    slot's workspace.  A slot is reused only after its previous micro-batch
+    was collected, so the buffers are free whenever a launch fills them."""
+
+    def __init__(self, torch, device, dtype, Workspace):
+        self.torch, self.device, self.dtype = torch, device, dtype
+        self.ws = Workspace(device, torch.float64)
+        self.cap = (0, 0, 0)
+
+    def grow(self, K, n_model, n_grad):
+        torch = self.torch
+        if K <= self.cap[0] and n_model <= self.cap[1] and n_grad <= self.cap[2]:
+            return
+        K = max(K, self.cap[0])
+        n_model = max(n_model, self.cap[1], 1)
+        n_grad = max(n_grad, self.cap[2], 1)
+        pin = dict(pin_memory=True)
+        self.h_model = torch.empty(n_model, dtype=self.dtype, **pin)
+        self.d_model = torch.empty(n_model, dtype=self.dtype, device=self.device)
+        self.h_geo = torch.empty((K, 6), dtype=torch.float64, **pin)
+        self.d_geo = torch.empty((K, 6), dtype=torch.float64, device=self.device)
+        self.h_chi2 = torch.empty(K, dtype=torch.float64, **pin)
+        self.d_chi2 = torch.empty(K, dtype=torch.float64, device=self.device)
+        self.h_grad = torch.empty(n_grad, dtype=self.dtype, **pin)
+        self.d_grad = torch.empty(n_grad, dtype=self.dtype, device=self.device)
+        self.cap = (K, n_model, n_grad)
+
+
 class GpuExecutor:
-    """HIP executor: datasets resident in HBM, one stream per in-flight slot,
-    planned batches for chi^2-only micro-batches, adjoint calls for gradients."""
+    """HIP executor: datasets resident in HBM, one stream and one set of
+    staging buffers per in-flight slot, one batch_exec call per micro-batch
+    (any mix of requests, gradients included)."""
+
+    mixed_batches = True
 
     def __init__(self, device=None, dtype=None, max_batch: int = 16, max_inflight: int = 4):
         import torch
 
-        from . import Dataset, profile_batch, Workspace, _lib, _sfx
+        from . import JOB_PROFILE, Dataset, Workspace, batch_exec
 
         self.torch = torch
-        self._Dataset, self._profile_batch, self._Workspace = Dataset, profile_batch, Workspace
-        self._lib, self._sfx = _lib, _sfx
+        self._Dataset, self._batch_exec, self._JOB_PROFILE = Dataset, batch_exec, JOB_PROFILE
         self.device = torch.device("cuda", torch.cuda.current_device()) if device is None \
             else torch.device(device)
         self.dtype = torch.float64 if dtype is None else dtype
         self.max_batch = max_batch
         self.streams = [torch.cuda.Stream(device=self.device) for _ in range(max_inflight)]
+        self.slots = [_Slot(torch, self.device, self.dtype, Workspace) for _ in range(max_inflight)]
         self.datasets = {}
-        self._plans = {}            # (key, slot) -> (batch, I slots, geo slots)
-        self._ws = {}               # slot -> [Workspace] for gradient calls
 
     def default_budget(self) -> int:
         free, total = self.torch.cuda.mem_get_info(self.device)
@@ -252,87 +290,65 @@ class GpuExecutor:
         return self.datasets[name]
 
     def footprint(self, reqs) -> int:
-        r = reqs[0]
+        """Upper bound of the device bytes a micro-batch uses: per request its
+        pruned spectrum (at most (Nxy/2 + 2)^2 reals), chi^2 partials, model,
+        geometry and table entry; a gradient request adds its adjoint grid,
+        bin accumulator and gradient output."""
         el = 8 if self.dtype == self.torch.float64 else 4
-        ds = self.datasets[r.dataset]
-        if r.grad:
-            ws = getattr(self._lib(), "gal_grad_workspace_bytes" + self._sfx(self.dtype))(
-                int(r.Nxy), int(ds.M), int(np.size(r.I)))
-            return len(reqs) * (int(ws) + 2 * el * int(np.size(r.I)) + 64)
-        Nxy = int(r.Nxy)
-        spec = (Nxy // 2 + 2) ** 2 * el
-        part = 8 * ((ds.M + 1023) // 1024)
-        return len(reqs) * (spec + part + el * int(np.size(r.I)) + 64) + 4096
-
-    def _plan(self, key, slot, K):
-        pk = (key, slot, K)
-        if pk not in self._plans:
-            torch = self.torch
-            name, Nxy, dxy, Nr, _ = key
-            I = torch.zeros((K, Nr), dtype=self.dtype, device=self.device)
-            geo = torch.zeros((K, 6), dtype=torch.float64, device=self.device)
-            geo[:, 1] = 1.0
-            b = self._profile_batch(self.datasets[name], I, geo, Nxy, dxy)
-            self._plans[pk] = (b, I, geo)
-        return self._plans[pk]
+        tot = 4096
+        for r in reqs:
+            N, Nr = int(r.Nxy), int(np.size(r.I))
+            M = int(self.datasets[r.dataset].M)
+            spec = (N // 2 + 2) ** 2 * el + 256
+            b = spec + 8 * ((M + 1023) // 1024) + 256 + el * Nr + 48 + 8 + 512
+            if r.grad:
+                b += spec + 8 * Nr + 256 + el * Nr
+            tot += b
+        return tot
 
     def launch(self, reqs, slot):
         torch = self.torch
-        st = self.streams[slot]
-        key = reqs[0].key()
-        name, Nxy, dxy, Nr, want_grad = key
-        ds = self.datasets[name]
-        with torch.cuda.stream(st):
-            if not want_grad:
-                K = 1
-                while K < len(reqs):
-                    K *= 2
-                b, I, geo = self._plan(key, slot, K)
-                Ih = torch.empty((K, Nr), dtype=self.dtype, pin_memory=True)
-                gh = torch.empty((K, 6), dtype=torch.float64, pin_memory=True)
-                for k in range(K):
-                    r = reqs[min(k, len(reqs) - 1)]   # unused slots repeat the last request
-                    Ih[k] = torch.as_tensor(np.asarray(r.I) if not torch.is_tensor(r.I)
-                                            else r.I.detach().cpu(), dtype=self.dtype)
-                    gh[k] = torch.tensor([r.Rmin, r.dR, r.inc, r.PA, r.dRA, r.dDec],
-                                         dtype=torch.float64)
-                I.copy_(Ih, non_blocking=True)
-                geo.copy_(gh, non_blocking=True)
-                out = b.chi2()
-                host = torch.empty(K, dtype=torch.float64, pin_memory=True)
-                host.copy_(out, non_blocking=True)
-                keep = (Ih, gh, host)
-                outs = [("chi2", host, k) for k in range(len(reqs))]
+        st, S = self.streams[slot], self.slots[slot]
+        K = len(reqs)
+        nr = [int(np.size(r.I)) for r in reqs]
+        mo = np.concatenate([[0], np.cumsum(nr)]).astype(np.int64)
+        n_grad = sum(n for n, r in zip(nr, reqs) if r.grad)
+        S.grow(K, int(mo[-1]), n_grad)
+        hm, hg = S.h_model.numpy(), S.h_geo.numpy()
+        for k, r in enumerate(reqs):
+            I = r.I.detach().cpu().numpy() if torch.is_tensor(r.I) else np.asarray(r.I)
+            hm[mo[k]:mo[k + 1]] = I
+            hg[k] = (r.Rmin, r.dR, r.inc, r.PA, r.dRA, r.dDec)
+        jobs, grads, goff = [], [], []
+        g0 = 0
+        for k, r in enumerate(reqs):
+            jobs.append({"ds": self.datasets[r.dataset], "kind": self._JOB_PROFILE,
+                         "Nxy": int(r.Nxy), "dxy": float(r.dxy),
+                         "model": S.d_model[mo[k]:mo[k + 1]], "geo": S.d_geo[k]})
+            if r.grad:
+                grads.append(S.d_grad[g0:g0 + nr[k]])
+                goff.append(g0)
+                g0 += nr[k]
             else:
-                pool = self._ws.setdefault(slot, [])
-                while len(pool) < len(reqs):
-                    pool.append(self._Workspace(self.device, self.dtype))
-                outs, keep = [], []
-                for k, r in enumerate(reqs):
-                    I = torch.as_tensor(np.asarray(r.I) if not torch.is_tensor(r.I) else r.I,
-                                        dtype=self.dtype).to(self.device, non_blocking=True)
-                    c2, g = ds.chi2Profile_grad(I, r.Rmin, r.dR, Nxy, dxy, r.inc, r.PA, r.dRA,
-                                                r.dDec, ws=pool[k])
-                    hc = torch.empty((), dtype=torch.float64, pin_memory=True)
-                    hg = torch.empty(g.shape, dtype=g.dtype, pin_memory=True)
-                    hc.copy_(c2, non_blocking=True)
-                    hg.copy_(g, non_blocking=True)
-                    keep.append((I, c2, g))
-                    outs.append(("grad", hc, hg))
+                grads.append(None)
+                goff.append(-1)
+        with torch.cuda.stream(st):
+            S.d_model[:mo[-1]].copy_(S.h_model[:mo[-1]], non_blocking=True)
+            S.d_geo[:K].copy_(S.h_geo[:K], non_blocking=True)
+            self._batch_exec(jobs, grads if n_grad else None, out=S.d_chi2[:K], ws=S.ws)
+            S.h_chi2[:K].copy_(S.d_chi2[:K], non_blocking=True)
+            if n_grad:
+                S.h_grad[:n_grad].copy_(S.d_grad[:n_grad], non_blocking=True)
             ev = torch.cuda.Event()
             ev.record(st)
-        return (ev, outs, keep)
+        return (ev, S, nr, goff)
 
     def done(self, handle) -> bool:
         return handle[0].query()
 
     def collect(self, handle):
-        ev, outs, _ = handle
+        ev, S, nr, goff = handle
         ev.synchronize()
-        res = []
-        for o in outs:
-            if o[0] == "chi2":
-                res.append((float(o[1][o[2]]), None))
-            else:
-                res.append((float(o[1]), o[2].numpy().copy()))
-        return res
+        c, g = S.h_chi2.numpy(), S.h_grad.numpy()
+        return [(float(c[k]), None if goff[k] < 0 else g[goff[k]:goff[k] + nr[k]].copy())
+                for k in range(len(nr))]

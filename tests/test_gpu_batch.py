@@ -109,3 +109,61 @@ def test_mixed_batch_kinds_sizes_datasets_precisions():
         tol = 1e-12 if spec[3] == np.float64 else 1e-6
         assert abs(c2b[k] - c2s) <= tol * c2s, (k, spec, c2b[k], c2s)
     b.close()
+
+
+def _rel(a, b):
+    return float(np.linalg.norm(a - b) / max(np.linalg.norm(b), 1e-300))
+
+
+def test_batch_exec_mixed_with_gradients():
+    # one call: several datasets, kinds, sizes and precisions, two walkers per
+    # dataset (one sample group), gradients on some jobs only; each result
+    # against its single call (chi^2, gradient) and one job against the oracle
+    dev = device()
+    gal = _gal()
+    import torch
+
+    specs = [(128, 6001, "image", np.float64), (256, 9001, "profile", np.float64),
+             (64, 3001, "image", np.float32), (512, 15001, "profile", np.float32)]
+    jobs, grads, refs, keep = [], [], [], []
+    for i, (N, M, kind, d) in enumerate(specs):
+        case = wl.random_case(N, M, seed=1970 + i, kind=kind, fill=0.8)
+        Vo = _obs(case, d)
+        re, im, w = (rounded(1.03 * Vo.real + case.noise_re, d),
+                     rounded(0.97 * Vo.imag + case.noise_im, d), rounded(case.w, d))
+        ds = gal.Dataset(*(t(a, d, dev) for a in (case.u, case.v, re, im, w)))
+        for walker in range(2):
+            scale = 1.0 + 0.1 * walker
+            src = (case.image if kind == "image" else case.I) * scale
+            model = t(src, d, dev)
+            geo = torch.as_tensor(_geo(case), dtype=torch.float64, device=dev)
+            geo[3] += 0.2 * walker
+            g = torch.empty_like(model) if (i + walker) % 2 == 0 else None
+            jobs.append({"ds": ds, "kind": gal.JOB_IMAGE if kind == "image" else gal.JOB_PROFILE,
+                         "Nxy": N, "dxy": case.dxy, "model": model, "geo": geo})
+            grads.append(g)
+            gv = geo.cpu().numpy()
+            if kind == "image":
+                c2s, gs = ds.chi2Image_grad(model, case.dxy, gv[3], gv[4], gv[5], gv[2])
+            else:
+                c2s, gs = ds.chi2Profile_grad(model, gv[0], gv[1], N, case.dxy, gv[2], gv[3],
+                                              gv[4], gv[5])
+            refs.append((float(c2s), gs.cpu().numpy().astype(np.float64), d, case, re, im, w,
+                         src, gv))
+            keep.append((ds, model, geo))
+    for call in range(2):
+        sub = slice(0, len(jobs)) if call == 0 else slice(2, 6)  # second call: smaller
+        c2 = gal.batch_exec(jobs[sub], grads[sub]).cpu().numpy()
+        for k, j in enumerate(range(len(jobs))[sub]):
+            c2s, gs, d, case, *_ = refs[j]
+            tol = 1e-12 if d == np.float64 else 1e-6
+            assert abs(c2[k] - c2s) <= tol * c2s, (call, j, c2[k], c2s)
+            if grads[j] is not None:
+                err = _rel(grads[j].cpu().numpy().astype(np.float64), gs)
+                assert err <= (1e-10 if d == np.float64 else 1e-4), (call, j, err)
+    # the FP64 profile job with a gradient (second walker) against the oracle
+    assert grads[3] is not None and specs[1][2:] == ("profile", np.float64)
+    _, _, _, case, re, im, w, src, gv = refs[3]
+    _, go = oracle.grad_profile(src, gv[0], gv[1], case.N, case.dxy, case.u, case.v, re, im, w,
+                                gv[2], gv[3], gv[4], gv[5])
+    assert _rel(grads[3].cpu().numpy(), go) <= 1e-8

@@ -103,3 +103,21 @@ def test_grad_and_plain_requests_are_not_mixed():
     byid = {id(r): r for r in reqs}
     for b in ex.launched:
         assert len({byid[i].grad for i in b}) == 1
+
+
+class MixedStub(StubExecutor):
+    mixed_batches = True
+
+
+def test_mixed_executor_takes_requests_in_arrival_order():
+    ex = MixedStub(delay=0.01)
+    srv = Server(ex, max_batch=4, max_inflight=1).start()
+    reqs = [_req(ds="ab"[i % 2], val=float(i), grad=(i % 3 == 0)) for i in range(12)]
+    futs = [srv.submit(r) for r in reqs]
+    res = [f.result(timeout=5) for f in futs]
+    srv.stop()
+    assert [r[0] for r in res] == [8.0 * i for i in range(12)]
+    order = [i for b in ex.launched for i in b]
+    assert order == [id(r) for r in reqs]                      # FIFO across keys
+    assert any(len({reqs[[id(r) for r in reqs].index(i)].key() for i in b}) > 1
+               for b in ex.launched)
