@@ -123,15 +123,16 @@ def serve_bench(gal, torch, np, dev, rates, n_req, warm, grad_frac, n_datasets, 
         futs = []
         for i, prm in enumerate(params):
             t_next += gaps[i]
-            while time.perf_counter() < t_next:
-                pass
+            while True:   # pace by sleeping: a spinning client would hold the GIL
+                dt = t_next - time.perf_counter()
+                if dt <= 0:
+                    break
+                time.sleep(dt if dt > 2e-4 else 0)
             futs.append(srv.submit(Request(grad=bool(rng.random() < grad_frac), **prm)))
             if i == warm - 1:
                 for f in futs:
                     f.result(timeout=120)
-                srv.latencies.clear()
-                srv.completed = 0
-                srv._t_first = None
+                srv.reset_stats()
         for f in futs:
             f.result(timeout=300)
         srv.stop()
@@ -140,6 +141,7 @@ def serve_bench(gal, torch, np, dev, rates, n_req, warm, grad_frac, n_datasets, 
                           "evals_per_s": round(st["evals_per_s"], 1) if st["evals_per_s"] else None,
                           "p50_ms": round(st["p50_ms"], 3), "p99_ms": round(st["p99_ms"], 3),
                           "requests": st["completed"], "micro_batches": st["batches"],
+                          "host_launch_ms_per_batch": round(st["host_launch_ms_per_batch"], 3),
                           "peak_hbm_MB": round(st["peak_hbm_bytes"] / 1e6, 1)}
     return {"workload": f"{n_datasets} resident datasets (M log-uniform in [1e5, {max_M:.0e}]), "
                         "requests: chi2Profile with Nxy in {512, 1024, 2048}, Nr in [512, 4096], "

@@ -54,7 +54,7 @@ __global__ __launch_bounds__(SAMPLE_NT) void k_sample_scatter(
         if (k >= a.M) continue;
         const double uu = u[k], vv = v[k];
         double sn, cs;
-        sincospi(2.0 * (uu * a.dRA + vv * a.dDec), &sn, &cs);
+        sincospi_tab(2.0 * (uu * a.dRA + vv * a.dDec), sn, cs);
         double Vre, Vim;
         if constexpr (REAL) {
             const StencilR<T> st = locate_r<T>(S, g, a, uu, vv);

@@ -17,6 +17,7 @@
 namespace gal {
 
 constexpr int KMAX = 16;  // jobs sharing one pass over a dataset
+constexpr int WAVES = SAMPLE_NT / 64;  // chi^2 partials per sampling block and job
 
 struct JobDesc {
     const void *src;     // image [N*N] or profile [Nr], dataset precision
@@ -29,7 +30,22 @@ struct JobDesc {
     int kind;            // 0 image, 1 profile
     int N, Nr, Q, P, CS, Qe;
     double dxy;
+    // sampling constants of the job's geometry, written at every execution by
+    // the job's first row-pass block (geo may change between executions)
+    double cpa, spa, cinc, dRA, dDec;
 };
+
+// thread 0 of a job's first row-pass block: cos PA, sin PA, cos inc, offsets
+__device__ __forceinline__ void job_constants(JobDesc &j) {
+    if (blockIdx.x != 0 || threadIdx.x != 0) return;
+    double sn, cs;
+    sincos(j.geo[3], &sn, &cs);
+    j.cpa = cs;
+    j.spa = sn;
+    j.cinc = j.kind == 1 ? 1.0 : cos(j.geo[2]);
+    j.dRA = j.geo[4];
+    j.dDec = j.geo[5];
+}
 
 struct SGroup {          // jobs sharing one pass over a dataset
     const void *u, *v, *re, *im, *w;
@@ -55,10 +71,11 @@ __device__ __forceinline__ SampleArgs sample_from_job(const JobDesc &j, int64_t 
     SampleArgs a;
     a.M = M;
     a.inv_du = (double)j.N * j.dxy;
-    sincos(j.geo[3], &a.spa, &a.cpa);
-    a.cinc = j.kind == 1 ? 1.0 : cos(j.geo[2]);
-    a.dRA = j.geo[4];
-    a.dDec = j.geo[5];
+    a.cpa = j.cpa;
+    a.spa = j.spa;
+    a.cinc = j.cinc;
+    a.dRA = j.dRA;
+    a.dDec = j.dDec;
     a.jmax = min(j.Q - 2, j.N / 2 - 1);
     a.imin = -min(j.P, j.N / 2);
     a.imax = min(j.P - 1, j.N / 2 - 2);
@@ -69,8 +86,9 @@ __device__ __forceinline__ Geom geom_of(const JobDesc &j) { return Geom{j.N, j.Q
 
 // ---- FFT stage: blockIdx.y selects the job in `list` ----------------------
 template <typename T, typename Cfg>
-__global__ __launch_bounds__(Cfg::NT) void kb_rows_img(const JobDesc *__restrict__ jobs,
+__global__ __launch_bounds__(Cfg::NT) void kb_rows_img(JobDesc *__restrict__ jobs,
                                                        const int *__restrict__ list, char *ws) {
+    job_constants(jobs[list[blockIdx.y]]);
     const JobDesc &j = jobs[list[blockIdx.y]];
     rows_body<T, Cfg, false>((const T *)j.src, SweepArgs{}, geom_of(j),
                              (c2<T> *)(ws + j.spec_off), xcd_remap(blockIdx.x, gridDim.x));
@@ -84,8 +102,9 @@ __global__ __launch_bounds__(Cfg::NT) void kb_cols(const JobDesc *__restrict__ j
 }
 
 template <typename T, typename Cfg>
-__global__ __launch_bounds__(Cfg::NT) void kb_rows_sym(const JobDesc *__restrict__ jobs,
+__global__ __launch_bounds__(Cfg::NT) void kb_rows_sym(JobDesc *__restrict__ jobs,
                                                        const int *__restrict__ list, char *ws) {
+    job_constants(jobs[list[blockIdx.y]]);
     const JobDesc &j = jobs[list[blockIdx.y]];
     const SweepArgs sw = sweep_from_geo(j.geo, j.Nr, j.dxy);
     rows_sym_body<T, Cfg>((const T *)j.src, sw, geom_of(j), j.Qe, (T *)(ws + j.spec_off),
@@ -100,29 +119,6 @@ __global__ __launch_bounds__(Cfg::NT) void kb_cols_sym(const JobDesc *__restrict
 }
 
 // ---- sampling stage ------------------------------------------------------
-template <typename T>
-__device__ __forceinline__ double sample_real_at(const T *__restrict__ S, const Geom &g,
-                                                 const SampleArgs &a, double u, double v,
-                                                 bool &ok, double &Vre, double &Vim) {
-    const StencilR<T> st = locate_r<T>(S, g, a, u, v);
-    ok = st.ok;
-    if (!ok) {
-        Vre = __builtin_nan("");
-        Vim = __builtin_nan("");
-        return 0.0;
-    }
-    const T x0 = st.c0[0], x1 = st.c0[1], y0 = st.c0[g.CS], y1 = st.c0[g.CS + 1];
-    const double a00 = st.swap ? x1 : x0, a10 = st.swap ? x0 : x1;
-    const double a01 = st.swap ? y1 : y0, a11 = st.swap ? y0 : y1;
-    const double s = st.s, t = st.t;
-    const double b = (1.0 - t) * ((1.0 - s) * a00 + s * a01) + t * ((1.0 - s) * a10 + s * a11);
-    double sn, cs;
-    sincospi(2.0 * (u * a.dRA + v * a.dDec), &sn, &cs);
-    Vre = a.cinc * b * cs;
-    Vim = a.cinc * b * sn;
-    return 0.0;
-}
-
 // Residual of one point scattered onto the four nodes of its stencil (the
 // adjoint of the sampling; see adjoint.h for the derivation).
 template <typename T>
@@ -159,7 +155,6 @@ __global__ __launch_bounds__(SAMPLE_NT) void kb_sample_chi2(const JobDesc *__res
                                                             const SGroup *__restrict__ groups,
                                                             int ngroups, char *ws) {
     constexpr int PPT = SAMPLE_PPT;
-    __shared__ double red[SAMPLE_NT / 64];
     int lo = 0, hi = ngroups - 1;
     while (lo < hi) {
         const int mid = (lo + hi + 1) >> 1;
@@ -169,8 +164,8 @@ __global__ __launch_bounds__(SAMPLE_NT) void kb_sample_chi2(const JobDesc *__res
     const SGroup &G = groups[lo];
     const int chunk = (int)blockIdx.x - G.blk0;
     const int64_t base = (int64_t)chunk * (SAMPLE_NT * PPT) + threadIdx.x;
-    const T *u = (const T *)G.u, *v = (const T *)G.v;
-    const T *re = (const T *)G.re, *im = (const T *)G.im, *w = (const T *)G.w;
+    const gptr<T> u = as_global<T>(G.u), v = as_global<T>(G.v);
+    const gptr<T> re = as_global<T>(G.re), im = as_global<T>(G.im), w = as_global<T>(G.w);
     double uu[PPT], vv[PPT], rr[PPT], ii[PPT], ww[PPT];
 #pragma unroll
     for (int p = 0; p < PPT; ++p) {
@@ -191,17 +186,27 @@ __global__ __launch_bounds__(SAMPLE_NT) void kb_sample_chi2(const JobDesc *__res
         double acc = 0.0;
 #pragma unroll
         for (int p = 0; p < PPT; ++p) {
+            const bool in = base + p * SAMPLE_NT < G.M;
+            // exp(i theta), theta = 2 pi (u dRA + v dDec)
+            double sn, cs;
+            sincospi_tab(2.0 * (uu[p] * a.dRA + vv[p] * a.dDec), sn, cs);
             double Vre, Vim;
             bool ok;
-            const bool in = base + p * SAMPLE_NT < G.M;
+            // an off-grid stencil points at valid nodes; its value is discarded
             if constexpr (REAL) {
                 const T *S = (const T *)(ws + J.spec_off);
-                sample_real_at<T>(S, g, a, uu[p], vv[p], ok, Vre, Vim);
+                const StencilR<T> st = locate_r<T>(S, g, a, uu[p], vv[p]);
+                ok = st.ok;
+                const T x0 = st.c0[0], x1 = st.c0[1], y0 = st.c0[g.CS], y1 = st.c0[g.CS + 1];
+                const double a00 = st.swap ? x1 : x0, a10 = st.swap ? x0 : x1;
+                const double a01 = st.swap ? y1 : y0, a11 = st.swap ? y0 : y1;
+                const double s = st.s, t = st.t;
+                const double b = a.cinc * ((1.0 - t) * ((1.0 - s) * a00 + s * a01) +
+                                           t * ((1.0 - s) * a10 + s * a11));
+                Vre = ok ? b * cs : __builtin_nan("");
+                Vim = ok ? b * sn : __builtin_nan("");
                 if (GRAD && J.grad && in && ok) {
-                    // Re(conj(R) e^{i theta}) with e^{i theta} = V / (cinc b)
-                    const StencilR<T> st = locate_r<T>(S, g, a, uu[p], vv[p]);
-                    double sn, cs;
-                    sincospi(2.0 * (uu[p] * a.dRA + vv[p] * a.dDec), &sn, &cs);
+                    // Re(conj(R) e^{i theta}) on the real spectrum
                     const double R0 = rr[p] - Vre, R1 = ii[p] - Vim;
                     scatter_real<T>((T *)(ws + J.a_off), S, st, g.CS,
                                     ww[p] * a.cinc * (R0 * cs + R1 * sn));
@@ -210,11 +215,21 @@ __global__ __launch_bounds__(SAMPLE_NT) void kb_sample_chi2(const JobDesc *__res
                 const c2<T> *S = (const c2<T> *)(ws + J.spec_off);
                 const Stencil<T> st = locate<T>(S, g, a, uu[p], vv[p]);
                 ok = st.ok;
-                finish<T>(st, st.c0[0], st.c0[1], st.c0[g.CS], st.c0[g.CS + 1], a, uu[p], vv[p],
-                          Vre, Vim);
+                const c2<T> n00 = st.c0[0], n10 = st.c0[1], n01 = st.c0[g.CS], n11 = st.c0[g.CS + 1];
+                const double s = st.s, t = st.t;
+                const double w00 = (1.0 - t) * (1.0 - s), w01 = (1.0 - t) * s;
+                const double w10 = t * (1.0 - s), w11 = t * s;
+                double br = w00 * (double)n00.x + w01 * (double)n01.x + w10 * (double)n10.x +
+                            w11 * (double)n11.x;
+                double bi = w00 * (double)n00.y + w01 * (double)n01.y + w10 * (double)n10.y +
+                            w11 * (double)n11.y;
+                if (st.mirror) bi = -bi;
+                br *= a.cinc;
+                bi *= a.cinc;
+                Vre = ok ? br * cs - bi * sn : __builtin_nan("");
+                Vim = ok ? br * sn + bi * cs : __builtin_nan("");
                 if (GRAD && J.grad && in && ok) {
-                    double sn, cs;
-                    sincospi(2.0 * (uu[p] * a.dRA + vv[p] * a.dDec), &sn, &cs);
+                    // a = conj(R) e^{i theta} (direct) or R e^{-i theta} (mirrored)
                     const double R0 = rr[p] - Vre, R1 = ii[p] - Vim;
                     const double ar = R0 * cs + R1 * sn;
                     const double ai = st.mirror ? (R1 * cs - R0 * sn) : (R0 * sn - R1 * cs);
@@ -227,8 +242,10 @@ __global__ __launch_bounds__(SAMPLE_NT) void kb_sample_chi2(const JobDesc *__res
                 acc += ww[p] * (dr * dr + di * di);
             }
         }
-        const double bs = block_sum(acc, red);
-        if (threadIdx.x == 0) ((double *)(ws + J.part_off))[chunk] = bs;
+        // one partial per wave (no barrier between jobs); kb_reduce adds them
+        const double wsum = wave_sum(acc);
+        if ((threadIdx.x & 63) == 0)
+            ((double *)(ws + J.part_off))[chunk * WAVES + (threadIdx.x >> 6)] = wsum;
     }
     if (bad) ctl->flag = 1;
 }
@@ -241,7 +258,7 @@ __global__ __launch_bounds__(SAMPLE_NT) void kb_reduce(const JobDesc *__restrict
     __shared__ double red[SAMPLE_NT / 64];
     const int j = blockIdx.x;
     const JobDesc &J = jobs[j];
-    const int n = groups[job_group[j]].nblk;
+    const int n = groups[job_group[j]].nblk * WAVES;
     const double *part = (const double *)(ws + J.part_off);
     double s = 0.0;
     for (int k = threadIdx.x; k < n; k += SAMPLE_NT) s += part[k];

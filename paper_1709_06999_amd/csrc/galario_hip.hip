@@ -318,7 +318,7 @@ static int run_fft(int kind, const FftJob<T> &j) {
 // batched FFT passes: one launch per (precision, kind, image size) group,
 // blockIdx.y = job of the group
 struct FftJobB {
-    const JobDesc *jobs;
+    JobDesc *jobs;
     const int *list;
     int count;
     int maxQ, maxQe;
@@ -1478,7 +1478,7 @@ static int plan_batch(const gal_job *jobs, int n, void *const *grads, size_t bas
     size_t off = base;
     for (int i = 0; i < n; ++i) {
         P.jobs[i].part_off = off;
-        off += align256((size_t)P.groups[P.job_group[i]].nblk * sizeof(double));
+        off += align256((size_t)P.groups[P.job_group[i]].nblk * WAVES * sizeof(double));
     }
     auto spec_bytes = [&](int i) {
         const JobDesc &d = P.jobs[i];

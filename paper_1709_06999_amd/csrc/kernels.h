@@ -28,6 +28,37 @@ __device__ __forceinline__ const c2<double> *twiddles<double>() { return g_tw_d;
 template <>
 __device__ __forceinline__ const c2<float> *twiddles<float>() { return g_tw_f; }
 
+// Pointers read from device tables are generic, and loads through them
+// become flat instructions; arrays known to be in device global memory are
+// re-typed so that they load with global instructions.
+template <typename T>
+using gptr = const T __attribute__((address_space(1))) *;
+template <typename T>
+__device__ __forceinline__ gptr<T> as_global(const void *p) {
+    return (gptr<T>)p;
+}
+
+// sin(pi x) and cos(pi x) for the phase factor of a uv point, by table and
+// series: x = n/128 + r with n = rint(128 x) and |r| <= 1/256 (r exact);
+// (cos, -sin)(pi n / 128) is entry n mod 256 of the length-256 twiddle row
+// (exp(-2 pi i m / 256), stored at [256, 512)); sin and cos of y = pi r by
+// their Taylor series through y^5 and y^6 (|y| <= pi/256: truncation below
+// 1e-17); then the angle-addition formulas.  About 20 FP64 operations and one
+// cached 16-byte load; abs. error a few 1e-16.
+__device__ __forceinline__ void sincospi_tab(double x, double &sn, double &cs) {
+    const double n = rint(x * 128.0);
+    const double r = fma(n, -1.0 / 128.0, x);
+    const double m = fma(-256.0, floor(n * (1.0 / 256.0)), n);  // n mod 256
+    const int idx = (int)fmin(fmax(m, 0.0), 255.0);               // NaN -> 0
+    const c2<double> t = g_tw_d[256 + idx];
+    const double y = r * 3.141592653589793;
+    const double y2 = y * y;
+    const double sb = fma(y * y2, fma(y2, 1.0 / 120.0, -1.0 / 6.0), y);
+    const double cb = fma(y2, fma(y2, fma(y2, -1.0 / 720.0, 1.0 / 24.0), -0.5), 1.0);
+    sn = fma(-t.y, cb, t.x * sb);
+    cs = fma(t.x, cb, t.y * sb);
+}
+
 // Workgroups are dispatched round-robin over the 8 XCDs; give every XCD a
 // contiguous range of logical blocks so that neighbouring tiles share an L2.
 __device__ __forceinline__ int xcd_remap(int bid, int nblk) {
@@ -364,7 +395,7 @@ __device__ __forceinline__ void finish(const Stencil<T> &st, c2<T> a00, c2<T> a1
     bi *= a.cinc;
     // exp(i theta), theta = 2 pi (u dRA + v dDec) = pi * x
     double sn, cs;
-    sincospi(2.0 * (u * a.dRA + v * a.dDec), &sn, &cs);
+    sincospi_tab(2.0 * (u * a.dRA + v * a.dDec), sn, cs);
     Vre = br * cs - bi * sn;
     Vim = br * sn + bi * cs;
 }
@@ -492,7 +523,7 @@ __global__ __launch_bounds__(SAMPLE_NT) void k_sample_sym(
                 const double b = (1.0 - t) * ((1.0 - s) * a00 + s * a01) +
                                  t * ((1.0 - s) * a10 + s * a11);
                 double sn, cs;
-                sincospi(2.0 * (uu[p] * a.dRA + vv[p] * a.dDec), &sn, &cs);
+                sincospi_tab(2.0 * (uu[p] * a.dRA + vv[p] * a.dDec), sn, cs);
                 Vre = a.cinc * b * cs;
                 Vim = a.cinc * b * sn;
             }

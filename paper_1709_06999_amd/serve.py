@@ -97,6 +97,7 @@ class Server:
         self.expired = 0
         self.batches = 0
         self.peak_used = 0
+        self.launch_s = 0.0          # host time spent in executor.launch
         self._t_first = None
         self._t_last = None
 
@@ -129,6 +130,15 @@ class Server:
         if self._thr is not None:
             self._thr.join(timeout)
 
+    def reset_stats(self):
+        """Start the counters afresh (e.g. after a warm-up phase)."""
+        self.latencies = []
+        self.completed = self.rejected = self.expired = self.batches = 0
+        self.launch_s = 0.0
+        self.peak_used = self._used
+        self._t_first = None
+        self._t_last = None
+
     def stats(self) -> dict:
         lat = np.array(self.latencies) * 1e3
         span = (self._t_last - self._t_first) if self._t_first is not None and self._t_last else 0.0
@@ -139,6 +149,7 @@ class Server:
             "p99_ms": float(np.percentile(lat, 99)) if lat.size else None,
             "evals_per_s": self.completed / span if span > 0 else None,
             "peak_hbm_bytes": self.peak_used, "hbm_budget_bytes": self.budget,
+            "host_launch_ms_per_batch": 1e3 * self.launch_s / max(self.batches, 1),
         }
 
     # -- scheduler ---------------------------------------------------------
@@ -205,6 +216,7 @@ class Server:
                 ids = set(id(r) for r in group)
                 self._pending = collections.deque(r for r in self._pending if id(r) not in ids)
                 slot = self._free_slots.pop()
+                t0 = time.perf_counter()
                 try:
                     handle = self.ex.launch(group, slot)
                 except Exception as e:  # launch errors go to the callers
@@ -212,6 +224,7 @@ class Server:
                         _settle(r.future, exc=e)
                     self._free_slots.append(slot)
                     continue
+                self.launch_s += time.perf_counter() - t0
                 if self._t_first is None:
                     self._t_first = time.perf_counter()
                 self._inflight.append((handle, group, fp, slot))
