@@ -32,7 +32,7 @@ from ._native import GalarioError, check
 __all__ = [
     "sweep", "sampleImage", "sampleProfile", "chi2Image", "chi2Profile", "spectrum",
     "sample_spectrum", "Dataset", "Workspace", "read_status", "timing", "GalarioError",
-    "version", "init", "autotune", "tune_get", "tune_set", "Batch", "profile_batch",
+    "version", "init", "autotune", "autotune_batch", "tune_get", "tune_set", "Batch", "profile_batch",
     "JOB_IMAGE", "JOB_PROFILE", "batch_exec", "chi2Image_grad", "chi2Profile_grad", "chi2_profile", "chi2_image",
 ]
 
@@ -586,6 +586,41 @@ def autotune(Nxy: int, dtype=torch.float64, frac: float = 1.0, device=None, time
             json.dump(cache, f, indent=1, sort_keys=True)
         os.replace(tmp, path)
     return res
+
+
+def autotune_batch(batch: "Batch", Nxy: int, dtype=torch.float64, reps: int = 10,
+                   times=None) -> list:
+    """Tune the FFT variants for a planned batch as it runs: time
+    ``batch.chi2()`` under each variant of each pass the batch uses (one pass
+    at a time, the others at their current choice) and keep the fastest.
+    Call it before capturing the batch into a graph (a graph keeps the
+    kernels it recorded).  ``times``, if a dict, receives ms per execution."""
+    kinds = sorted({2 if j["kind"] == JOB_PROFILE else 0 for j in batch.jobs
+                    if int(j["Nxy"]) == int(Nxy) and j["ds"].dtype == dtype})
+    best = tune_get(Nxy, dtype)
+    names = ["rows_image", "cols", "rows_sym", "cols_sym"]
+    dev = batch.device
+    for k0 in kinds:
+        for kind in (k0, k0 + 1):
+            ms = []
+            for var in range(3):
+                trial = list(best)
+                trial[kind] = var
+                tune_set(Nxy, trial, dtype)
+                batch.chi2()
+                e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+                with torch.cuda.device(dev):
+                    e0.record()
+                    for _ in range(reps):
+                        batch.chi2()
+                    e1.record()
+                e1.synchronize()
+                ms.append(e0.elapsed_time(e1) / reps)
+            best[kind] = int(min(range(3), key=lambda v: ms[v]))
+            if isinstance(times, dict):
+                times[names[kind]] = [round(x, 5) for x in ms]
+    tune_set(Nxy, best, dtype)
+    return best
 
 
 def tune_get(Nxy: int, dtype=torch.float64) -> list:

@@ -36,26 +36,173 @@ __global__ __launch_bounds__(256) void k_zero(T *__restrict__ p, int64_t n) {
         p[i] = T(0);
 }
 
+// ---- block scatter through an LDS tile --------------------------------------
+// Each point adds hv * wa * ws to the four nodes of its stencil, node (q, i)
+// at flat index q * CS + i (times NV components: 1 real, 2 complex), with
+// wa = 1 - a at i and a at i + 1, ws = 1 - s at q and s at q + 1.  The points
+// of one sampling block are consecutive in Morton order, a compact patch of
+// the uv plane, so their nodes span a small box: they are added into an LDS
+// tile over that box (one LDS atomic per node value) and the tile is added to
+// the grid with one global atomic per touched value.  Dense uv cores, where
+// thousands of points share a node, then cost few global atomics.  A box
+// larger than the tile falls back to direct global atomics.
+constexpr int SCAT_TILE = 2048;  // doubles of LDS per block
+
+template <int NV>
+struct PointAdd {
+    int q, i;         // q < 0: nothing to add
+    double hv[NV];
+    double a, s;
+};
+
+__device__ __forceinline__ int wave_min(int x) {
+#pragma unroll
+    for (int o = 32; o >= 1; o >>= 1) x = min(x, __shfl_xor(x, o, 64));
+    return x;
+}
+__device__ __forceinline__ int wave_max(int x) {
+#pragma unroll
+    for (int o = 32; o >= 1; o >>= 1) x = max(x, __shfl_xor(x, o, 64));
+    return x;
+}
+
+// Called by every thread of the block (it synchronises); tile: SCAT_TILE
+// doubles of LDS, box: 4 * (blockDim.x / 64) ints of LDS.
+template <typename T, int NV, int NP>
+__device__ __forceinline__ void block_scatter(T *__restrict__ A, int CS, const PointAdd<NV> (&pa)[NP],
+                                              double *tile, int *box) {
+    constexpr int BIG = 0x3fffffff;
+    int qlo = BIG, qhi = -BIG, ilo = BIG, ihi = -BIG;
+#pragma unroll
+    for (int p = 0; p < NP; ++p) {
+        if (pa[p].q < 0) continue;
+        qlo = min(qlo, pa[p].q);
+        qhi = max(qhi, pa[p].q);
+        ilo = min(ilo, pa[p].i);
+        ihi = max(ihi, pa[p].i);
+    }
+    qlo = wave_min(qlo);
+    qhi = wave_max(qhi);
+    ilo = wave_min(ilo);
+    ihi = wave_max(ihi);
+    const int nw = (int)(blockDim.x >> 6), wid = (int)(threadIdx.x >> 6);
+    __syncthreads();  // the previous call's readers of box and tile are done
+    if ((threadIdx.x & 63) == 0) {
+        box[4 * wid] = qlo;
+        box[4 * wid + 1] = qhi;
+        box[4 * wid + 2] = ilo;
+        box[4 * wid + 3] = ihi;
+    }
+    __syncthreads();
+    for (int k = 0; k < nw; ++k) {
+        qlo = min(qlo, box[4 * k]);
+        qhi = max(qhi, box[4 * k + 1]);
+        ilo = min(ilo, box[4 * k + 2]);
+        ihi = max(ihi, box[4 * k + 3]);
+    }
+    if (qlo > qhi) return;  // no point of the block adds anything (uniform)
+    const int TQ = qhi - qlo + 2, TI = ihi - ilo + 2;
+    if (TQ * TI * NV <= SCAT_TILE) {
+        for (int k = threadIdx.x; k < TQ * TI * NV; k += blockDim.x) tile[k] = 0.0;
+        __syncthreads();
+#pragma unroll
+        for (int p = 0; p < NP; ++p) {
+            if (pa[p].q < 0) continue;
+            const int b = ((pa[p].q - qlo) * TI + (pa[p].i - ilo)) * NV;
+            const double wa[2] = {1.0 - pa[p].a, pa[p].a}, ws[2] = {1.0 - pa[p].s, pa[p].s};
+#pragma unroll
+            for (int dq = 0; dq < 2; ++dq)
+#pragma unroll
+                for (int di = 0; di < 2; ++di)
+#pragma unroll
+                    for (int c = 0; c < NV; ++c)
+                        atomicAdd(&tile[b + (dq * TI + di) * NV + c], pa[p].hv[c] * wa[di] * ws[dq]);
+        }
+        __syncthreads();
+        // flat tile index -> (row, column) of the box: exact in float for
+        // indices below 2^11 (the quotient stays >= 0.5/TI from an integer)
+        const float inv = 1.0f / (float)TI;
+        for (int k = threadIdx.x; k < TQ * TI; k += blockDim.x) {
+            const int dq = (int)(((float)k + 0.5f) * inv), di = k - dq * TI;
+            const size_t n = (size_t)(qlo + dq) * CS + (ilo + di);
+#pragma unroll
+            for (int c = 0; c < NV; ++c) {
+                const double v = tile[k * NV + c];
+                if (v != 0.0) atomicAdd(&A[n * NV + c], (T)v);
+            }
+        }
+    } else {
+#pragma unroll
+        for (int p = 0; p < NP; ++p) {
+            if (pa[p].q < 0) continue;
+            const size_t n = (size_t)pa[p].q * CS + pa[p].i;
+            const double wa[2] = {1.0 - pa[p].a, pa[p].a}, ws[2] = {1.0 - pa[p].s, pa[p].s};
+#pragma unroll
+            for (int dq = 0; dq < 2; ++dq)
+#pragma unroll
+                for (int di = 0; di < 2; ++di)
+#pragma unroll
+                    for (int c = 0; c < NV; ++c)
+                        atomicAdd(&A[(n + (size_t)dq * CS + di) * NV + c],
+                                  (T)(pa[p].hv[c] * wa[di] * ws[dq]));
+        }
+    }
+}
+
+// The residual R_k = Vobs_k - V_k of one sampled point as node additions.
+// Real spectrum (swept profile): hv = w cinc Re(conj(R) e^{i theta}); the
+// stencil's rows lo and lo + 1 carry p~0 + 1 and p~0 when swapped.
+template <typename T>
+__device__ __forceinline__ PointAdd<1> point_add_real(const StencilR<T> &st, double h) {
+    PointAdd<1> r;
+    r.q = st.q;
+    r.i = st.i;
+    r.hv[0] = h;
+    r.a = st.swap ? 1.0 - st.t : st.t;
+    r.s = st.s;
+    return r;
+}
+
+// Complex half spectrum (image): hv = w cinc a_k, a_k = conj(R) e^{i theta}
+// (direct) or R e^{-i theta} (mirrored).
+template <typename T>
+__device__ __forceinline__ PointAdd<2> point_add_cplx(const Stencil<T> &st, double h, double R0,
+                                                      double R1, double sn, double cs) {
+    PointAdd<2> r;
+    r.q = st.q;
+    r.i = st.i;
+    r.hv[0] = h * (R0 * cs + R1 * sn);
+    r.hv[1] = h * (st.mirror ? (R1 * cs - R0 * sn) : (R0 * sn - R1 * cs));
+    r.a = st.t;
+    r.s = st.s;
+    return r;
+}
+
 // ---- sampling + scatter ----------------------------------------------------
 // Forward sample of every point (chi^2 partials as in k_sample*), then the
-// residual's contribution to the adjoint grid A (same layout as the spectrum).
+// residuals added to the adjoint grid A (same layout as the spectrum).
 template <typename T, bool REAL>
 __global__ __launch_bounds__(SAMPLE_NT) void k_sample_scatter(
     const T *__restrict__ S, T *__restrict__ A, Geom g, SampleArgs a, const T *__restrict__ u,
     const T *__restrict__ v, const T *__restrict__ re, const T *__restrict__ im,
     const T *__restrict__ w, double *__restrict__ partials, Control *ctl) {
+    constexpr int NV = REAL ? 1 : 2;
     __shared__ double red[SAMPLE_NT / 64];
+    __shared__ double tile[SCAT_TILE];
+    __shared__ int box[4 * (SAMPLE_NT / 64)];
     const int blk = xcd_remap(blockIdx.x, gridDim.x);
     const int64_t base = (int64_t)blk * (SAMPLE_NT * SAMPLE_PPT) + threadIdx.x;
     double acc = 0.0;
     bool bad = false;
+    PointAdd<NV> pa[SAMPLE_PPT];
+#pragma unroll
     for (int p = 0; p < SAMPLE_PPT; ++p) {
+        pa[p].q = -1;
         const int64_t k = base + p * SAMPLE_NT;
         if (k >= a.M) continue;
         const double uu = u[k], vv = v[k];
         double sn, cs;
         sincospi_tab(2.0 * (uu * a.dRA + vv * a.dDec), sn, cs);
-        double Vre, Vim;
         if constexpr (REAL) {
             const StencilR<T> st = locate_r<T>(S, g, a, uu, vv);
             if (!st.ok) {
@@ -69,19 +216,11 @@ __global__ __launch_bounds__(SAMPLE_NT) void k_sample_scatter(
             const double s = st.s, t = st.t;
             const double b = (1.0 - t) * ((1.0 - s) * a00 + s * a01) +
                              t * ((1.0 - s) * a10 + s * a11);
-            Vre = a.cinc * b * cs;
-            Vim = a.cinc * b * sn;
+            const double Vre = a.cinc * b * cs, Vim = a.cinc * b * sn;
             const double rr = (double)re[k] - Vre, ri = (double)im[k] - Vim;
             acc += (double)w[k] * (rr * rr + ri * ri);
-            // Re(conj(R) e^{i theta}) = rr cs + ri sn; node weights; rows lo, lo+1
-            const double h = (double)w[k] * a.cinc * (rr * cs + ri * sn);
-            const double w_p0 = (1.0 - t), w_p1 = t;                   // rows p~0, p~0+1
-            const double wl = st.swap ? w_p1 : w_p0, wh = st.swap ? w_p0 : w_p1;  // lo, lo+1
-            T *c0 = A + (st.c0 - S);
-            atomicAdd(c0, (T)(h * wl * (1.0 - s)));
-            atomicAdd(c0 + 1, (T)(h * wh * (1.0 - s)));
-            atomicAdd(c0 + g.CS, (T)(h * wl * s));
-            atomicAdd(c0 + g.CS + 1, (T)(h * wh * s));
+            // Re(conj(R) e^{i theta}) = rr cs + ri sn
+            pa[p] = point_add_real<T>(st, (double)w[k] * a.cinc * (rr * cs + ri * sn));
         } else {
             const c2<T> *Sc = (const c2<T> *)S;
             const Stencil<T> st = locate<T>(Sc, g, a, uu, vv);
@@ -99,25 +238,14 @@ __global__ __launch_bounds__(SAMPLE_NT) void k_sample_scatter(
             if (st.mirror) bi = -bi;
             br *= a.cinc;
             bi *= a.cinc;
-            Vre = br * cs - bi * sn;
-            Vim = br * sn + bi * cs;
+            const double Vre = br * cs - bi * sn, Vim = br * sn + bi * cs;
             const double rr = (double)re[k] - Vre, ri = (double)im[k] - Vim;
             acc += (double)w[k] * (rr * rr + ri * ri);
-            // a = conj(R) e^{i theta} (direct) or R e^{-i theta} (mirrored)
-            const double ar = rr * cs + ri * sn;
-            const double ai = st.mirror ? (ri * cs - rr * sn) : (rr * sn - ri * cs);
-            const double h = (double)w[k] * a.cinc;
-            T *c0 = (T *)(A + 2 * (st.c0 - Sc));
-            const double wts[4] = {w00, w10, w01, w11};
-            const int offs[4] = {0, 1, g.CS, g.CS + 1};
-#pragma unroll
-            for (int n = 0; n < 4; ++n) {
-                atomicAdd(c0 + 2 * offs[n], (T)(h * wts[n] * ar));
-                atomicAdd(c0 + 2 * offs[n] + 1, (T)(h * wts[n] * ai));
-            }
+            pa[p] = point_add_cplx<T>(st, (double)w[k] * a.cinc, rr, ri, sn, cs);
         }
     }
     if (bad) ctl->flag = 1;
+    block_scatter<T, NV, SAMPLE_PPT>(A, g.CS, pa, tile, box);
     const double bs = block_sum(acc, red);
     if (threadIdx.x == 0) partials[blk] = bs;
 }

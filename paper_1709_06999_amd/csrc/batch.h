@@ -30,21 +30,30 @@ struct JobDesc {
     int kind;            // 0 image, 1 profile
     int N, Nr, Q, P, CS, Qe;
     double dxy;
-    // sampling constants of the job's geometry, written at every execution by
-    // the job's first row-pass block (geo may change between executions)
-    double cpa, spa, cinc, dRA, dDec;
+    // constants of the job's geometry, written by kb_prepare at the head of
+    // every execution (geo may change between executions)
+    double cpa, spa, cinc, dRA, dDec;  // sampling
+    double Rmin, inv_dR, inv_cos;      // sweep (profiles)
 };
 
-// thread 0 of a job's first row-pass block: cos PA, sin PA, cos inc, offsets
-__device__ __forceinline__ void job_constants(JobDesc &j) {
-    if (blockIdx.x != 0 || threadIdx.x != 0) return;
+// one thread per job: the trigonometry and divisions every later block of
+// the job would otherwise repeat
+__global__ __launch_bounds__(64) void kb_prepare(JobDesc *__restrict__ jobs, int n) {
+    const int i = blockIdx.x * 64 + threadIdx.x;
+    if (i >= n) return;
+    JobDesc &j = jobs[i];
+    const double *geo = j.geo;
     double sn, cs;
-    sincos(j.geo[3], &sn, &cs);
+    sincos(geo[3], &sn, &cs);
+    const double ci = cos(geo[2]);
     j.cpa = cs;
     j.spa = sn;
-    j.cinc = j.kind == 1 ? 1.0 : cos(j.geo[2]);
-    j.dRA = j.geo[4];
-    j.dDec = j.geo[5];
+    j.cinc = j.kind == 1 ? 1.0 : ci;
+    j.dRA = geo[4];
+    j.dDec = geo[5];
+    j.Rmin = geo[0];
+    j.inv_dR = 1.0 / geo[1];
+    j.inv_cos = 1.0 / ci;
 }
 
 struct SGroup {          // jobs sharing one pass over a dataset
@@ -55,15 +64,15 @@ struct SGroup {          // jobs sharing one pass over a dataset
     int jobs[KMAX];
 };
 
-__device__ __forceinline__ SweepArgs sweep_from_geo(const double *geo, int Nr, double dxy) {
+__device__ __forceinline__ SweepArgs sweep_of(const JobDesc &j) {
     SweepArgs a;
-    a.Nr = Nr;
-    a.Rmin = geo[0];
-    a.inv_dR = 1.0 / geo[1];
-    a.dxy = dxy;
-    a.inv_cos = 1.0 / cos(geo[2]);
-    a.pix_area = dxy * dxy;
-    a.tmax = (double)(Nr - 1);
+    a.Nr = j.Nr;
+    a.Rmin = j.Rmin;
+    a.inv_dR = j.inv_dR;
+    a.dxy = j.dxy;
+    a.inv_cos = j.inv_cos;
+    a.pix_area = j.dxy * j.dxy;
+    a.tmax = (double)(j.Nr - 1);
     return a;
 }
 
@@ -86,9 +95,8 @@ __device__ __forceinline__ Geom geom_of(const JobDesc &j) { return Geom{j.N, j.Q
 
 // ---- FFT stage: blockIdx.y selects the job in `list` ----------------------
 template <typename T, typename Cfg>
-__global__ __launch_bounds__(Cfg::NT) void kb_rows_img(JobDesc *__restrict__ jobs,
+__global__ __launch_bounds__(Cfg::NT) void kb_rows_img(const JobDesc *__restrict__ jobs,
                                                        const int *__restrict__ list, char *ws) {
-    job_constants(jobs[list[blockIdx.y]]);
     const JobDesc &j = jobs[list[blockIdx.y]];
     rows_body<T, Cfg, false>((const T *)j.src, SweepArgs{}, geom_of(j),
                              (c2<T> *)(ws + j.spec_off), xcd_remap(blockIdx.x, gridDim.x));
@@ -102,13 +110,11 @@ __global__ __launch_bounds__(Cfg::NT) void kb_cols(const JobDesc *__restrict__ j
 }
 
 template <typename T, typename Cfg>
-__global__ __launch_bounds__(Cfg::NT) void kb_rows_sym(JobDesc *__restrict__ jobs,
+__global__ __launch_bounds__(Cfg::NT) void kb_rows_sym(const JobDesc *__restrict__ jobs,
                                                        const int *__restrict__ list, char *ws) {
-    job_constants(jobs[list[blockIdx.y]]);
     const JobDesc &j = jobs[list[blockIdx.y]];
-    const SweepArgs sw = sweep_from_geo(j.geo, j.Nr, j.dxy);
-    rows_sym_body<T, Cfg>((const T *)j.src, sw, geom_of(j), j.Qe, (T *)(ws + j.spec_off),
-                          xcd_remap(blockIdx.x, gridDim.x));
+    rows_sym_body<T, Cfg, gptr<T>>(as_global<T>(j.src), sweep_of(j), geom_of(j), j.Qe,
+                                   (T *)(ws + j.spec_off), xcd_remap(blockIdx.x, gridDim.x));
 }
 
 template <typename T, typename Cfg>
@@ -119,35 +125,8 @@ __global__ __launch_bounds__(Cfg::NT) void kb_cols_sym(const JobDesc *__restrict
 }
 
 // ---- sampling stage ------------------------------------------------------
-// Residual of one point scattered onto the four nodes of its stencil (the
-// adjoint of the sampling; see adjoint.h for the derivation).
-template <typename T>
-__device__ __forceinline__ void scatter_real(T *A, const T *S, const StencilR<T> &st, int CS,
-                                             double h) {
-    const double s = st.s, t = st.t;
-    const double wl = st.swap ? t : (1.0 - t), wh = st.swap ? (1.0 - t) : t;
-    T *c0 = A + (st.c0 - S);
-    atomicAdd(c0, (T)(h * wl * (1.0 - s)));
-    atomicAdd(c0 + 1, (T)(h * wh * (1.0 - s)));
-    atomicAdd(c0 + CS, (T)(h * wl * s));
-    atomicAdd(c0 + CS + 1, (T)(h * wh * s));
-}
-
-template <typename T>
-__device__ __forceinline__ void scatter_cplx(T *A, const c2<T> *S, const Stencil<T> &st, int CS,
-                                             double h, double ar, double ai) {
-    const double s = st.s, t = st.t;
-    const double wts[4] = {(1.0 - t) * (1.0 - s), t * (1.0 - s), (1.0 - t) * s, t * s};
-    const int offs[4] = {0, 1, CS, CS + 1};
-    T *c0 = A + 2 * (st.c0 - S);
-#pragma unroll
-    for (int n = 0; n < 4; ++n) {
-        atomicAdd(c0 + 2 * offs[n], (T)(h * wts[n] * ar));
-        atomicAdd(c0 + 2 * offs[n] + 1, (T)(h * wts[n] * ai));
-    }
-}
-
-// Block -> group by binary search over the groups' first blocks; each thread
+// Block -> group by binary search over the groups' first blocks (after the
+// XCD remap); each thread
 // keeps SAMPLE_PPT points in registers and evaluates every job of the group.
 // GRAD: jobs with a gradient output also scatter their residuals.
 template <typename T, bool REAL, bool GRAD>
@@ -155,14 +134,20 @@ __global__ __launch_bounds__(SAMPLE_NT) void kb_sample_chi2(const JobDesc *__res
                                                             const SGroup *__restrict__ groups,
                                                             int ngroups, char *ws) {
     constexpr int PPT = SAMPLE_PPT;
+    constexpr int NV = REAL ? 1 : 2;
+    __shared__ double tile[GRAD ? SCAT_TILE : 1];
+    __shared__ int box[GRAD ? 4 * WAVES : 1];
+    // every XCD takes a contiguous run of chunks: a compact patch of the
+    // (Morton-ordered) uv plane, whose spectrum nodes then stay in its L2
+    const int bid = xcd_remap(blockIdx.x, gridDim.x);
     int lo = 0, hi = ngroups - 1;
     while (lo < hi) {
         const int mid = (lo + hi + 1) >> 1;
-        if (groups[mid].blk0 <= (int)blockIdx.x) lo = mid;
+        if (groups[mid].blk0 <= bid) lo = mid;
         else hi = mid - 1;
     }
     const SGroup &G = groups[lo];
-    const int chunk = (int)blockIdx.x - G.blk0;
+    const int chunk = bid - G.blk0;
     const int64_t base = (int64_t)chunk * (SAMPLE_NT * PPT) + threadIdx.x;
     const gptr<T> u = as_global<T>(G.u), v = as_global<T>(G.v);
     const gptr<T> re = as_global<T>(G.re), im = as_global<T>(G.im), w = as_global<T>(G.w);
@@ -184,9 +169,11 @@ __global__ __launch_bounds__(SAMPLE_NT) void kb_sample_chi2(const JobDesc *__res
         const SampleArgs a = sample_from_job(J, G.M);
         const Geom g = geom_of(J);
         double acc = 0.0;
+        PointAdd<NV> pa[PPT];
 #pragma unroll
         for (int p = 0; p < PPT; ++p) {
             const bool in = base + p * SAMPLE_NT < G.M;
+            pa[p].q = -1;
             // exp(i theta), theta = 2 pi (u dRA + v dDec)
             double sn, cs;
             sincospi_tab(2.0 * (uu[p] * a.dRA + vv[p] * a.dDec), sn, cs);
@@ -208,8 +195,7 @@ __global__ __launch_bounds__(SAMPLE_NT) void kb_sample_chi2(const JobDesc *__res
                 if (GRAD && J.grad && in && ok) {
                     // Re(conj(R) e^{i theta}) on the real spectrum
                     const double R0 = rr[p] - Vre, R1 = ii[p] - Vim;
-                    scatter_real<T>((T *)(ws + J.a_off), S, st, g.CS,
-                                    ww[p] * a.cinc * (R0 * cs + R1 * sn));
+                    pa[p] = point_add_real<T>(st, ww[p] * a.cinc * (R0 * cs + R1 * sn));
                 }
             } else {
                 const c2<T> *S = (const c2<T> *)(ws + J.spec_off);
@@ -228,13 +214,8 @@ __global__ __launch_bounds__(SAMPLE_NT) void kb_sample_chi2(const JobDesc *__res
                 bi *= a.cinc;
                 Vre = ok ? br * cs - bi * sn : __builtin_nan("");
                 Vim = ok ? br * sn + bi * cs : __builtin_nan("");
-                if (GRAD && J.grad && in && ok) {
-                    // a = conj(R) e^{i theta} (direct) or R e^{-i theta} (mirrored)
-                    const double R0 = rr[p] - Vre, R1 = ii[p] - Vim;
-                    const double ar = R0 * cs + R1 * sn;
-                    const double ai = st.mirror ? (R1 * cs - R0 * sn) : (R0 * sn - R1 * cs);
-                    scatter_cplx<T>((T *)(ws + J.a_off), S, st, g.CS, ww[p] * a.cinc, ar, ai);
-                }
+                if (GRAD && J.grad && in && ok)
+                    pa[p] = point_add_cplx<T>(st, ww[p] * a.cinc, rr[p] - Vre, ii[p] - Vim, sn, cs);
             }
             bad |= in && !ok;
             if (in) {
@@ -242,7 +223,8 @@ __global__ __launch_bounds__(SAMPLE_NT) void kb_sample_chi2(const JobDesc *__res
                 acc += ww[p] * (dr * dr + di * di);
             }
         }
-        // one partial per wave (no barrier between jobs); kb_reduce adds them
+        if (GRAD && J.grad) block_scatter<T, NV, PPT>((T *)(ws + J.a_off), g.CS, pa, tile, box);
+        // one partial per wave (no barrier between chi^2-only jobs); kb_reduce adds them
         const double wsum = wave_sum(acc);
         if ((threadIdx.x & 63) == 0)
             ((double *)(ws + J.part_off))[chunk * WAVES + (threadIdx.x >> 6)] = wsum;
@@ -295,8 +277,7 @@ __global__ __launch_bounds__(Cfg::NT) void kb_adj_rows_sym(const JobDesc *__rest
                                                            char *ws) {
     extern __shared__ double hist[];
     const JobDesc &j = jobs[list[blockIdx.y]];
-    const SweepArgs sw = sweep_from_geo(j.geo, j.Nr, j.dxy);
-    adj_rows_sym_body<T, Cfg>(geom_of(j), (const T *)(ws + j.a_off), sw,
+    adj_rows_sym_body<T, Cfg>(geom_of(j), (const T *)(ws + j.a_off), sweep_of(j),
                               (double *)(ws + j.gi_off), hist, blockIdx.x);
 }
 

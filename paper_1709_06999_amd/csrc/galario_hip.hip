@@ -318,7 +318,7 @@ static int run_fft(int kind, const FftJob<T> &j) {
 // batched FFT passes: one launch per (precision, kind, image size) group,
 // blockIdx.y = job of the group
 struct FftJobB {
-    JobDesc *jobs;
+    const JobDesc *jobs;
     const int *list;
     int count;
     int maxQ, maxQe;
@@ -1600,7 +1600,8 @@ static int batch_sample(const BatchPlan::SClass &c, bool grads, const BatchTable
 }
 
 static int exec_plan(const BatchPlan &P, const BatchTables &t, char *ws, double *chi2, hipStream_t s) {
-    int rc = GAL_OK;
+    int rc = launch("kb_prepare", kb_prepare, dim3((P.n + 63) / 64), dim3(64), s, t.jobs, P.n);
+    if (rc) return rc;
     if (P.zero_end > P.zero_begin) {
         rc = launch("k_zero", k_zero<double>, dim3(256), dim3(256), s, ws + P.zero_begin,
                     (int64_t)((P.zero_end - P.zero_begin) / sizeof(double)));

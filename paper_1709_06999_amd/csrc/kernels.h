@@ -83,9 +83,9 @@ struct SweepArgs {
     double Rmin, inv_dR, dxy, inv_cos, pix_area, tmax;
 };
 
-template <typename T>
-__device__ __forceinline__ double sweep_pixel(const T *__restrict__ I, int N, int r, int c,
-                                              const SweepArgs &a) {
+// PI: pointer to the profile (generic, or global for pointers read from tables)
+template <typename PI>
+__device__ __forceinline__ double sweep_pixel(PI I, int N, int r, int c, const SweepArgs &a) {
     if (r == N / 2 && c == N / 2) {
         const double I0 = I[0], I1 = I[1];
         return (I0 - a.Rmin * (I1 - I0) * a.inv_dR) * a.pix_area;
@@ -222,9 +222,9 @@ __global__ __launch_bounds__(Cfg::NT) void k_cols(Geom g, c2<T> *__restrict__ XT
 // Row pass: pair m holds rows 2m and 2m+1; output XR[q * CS + r] (real,
 // shift sign (-1)^q) for r in [0, N/2], q in [0, Qe) (Qe = Q rounded up to
 // even so that the column pass can pair columns).
-template <typename T, typename Cfg>
-__device__ __forceinline__ void rows_sym_body(const T *__restrict__ I, const SweepArgs &sw,
-                                              const Geom &g, int Qe, T *__restrict__ XR, int blk) {
+template <typename T, typename Cfg, typename PI = const T *__restrict__>
+__device__ __forceinline__ void rows_sym_body(PI I, const SweepArgs &sw, const Geom &g, int Qe,
+                                              T *__restrict__ XR, int blk) {
     constexpr int L = Cfg::L, B = Cfg::B, NT = Cfg::NT, E = Cfg::E;
     constexpr int N = L;
     constexpr int R0 = pass_radix(L, 1, Cfg::RMAX);
@@ -350,6 +350,7 @@ struct Stencil {
     const c2<T> *c0;   // node (q, i); (q, i+1) follows, (q+1, .) is CS further
     double s, t;
     bool mirror, ok;
+    int q, i;          // c0 = S + q * CS + i
 };
 
 template <typename T>
@@ -373,6 +374,8 @@ __device__ __forceinline__ Stencil<T> locate(const c2<T> *__restrict__ S, const 
     const int q = st.ok ? (int)j0f : 0;
     const int i = st.ok ? (int)i0f + g.P : g.P;
     st.c0 = S + (size_t)q * g.CS + i;
+    st.q = q;
+    st.i = i;
     return st;
 }
 
@@ -449,6 +452,7 @@ struct StencilR {
     const T *c0;       // SR + q * CS + lo; row lo and lo + 1
     double s, t;
     bool swap, ok;     // swap: node p~0 is at lo + 1 (p~0 < 0)
+    int q, i;          // c0 = SR + q * CS + i (i = lo)
 };
 
 template <typename T>
@@ -473,6 +477,8 @@ __device__ __forceinline__ StencilR<T> locate_r(const T *__restrict__ S, const G
     st.swap = p0 < 0;
     const int lo = st.swap ? -p0 - 1 : p0;
     st.c0 = S + (size_t)q * g.CS + lo;
+    st.q = q;
+    st.i = lo;
     return st;
 }
 
