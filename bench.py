@@ -212,6 +212,8 @@ def main():
                          "2: E=4) instead of autotuning, e.g. for counter runs that must see "
                          "the same kernels")
     ap.add_argument("--no-serve", action="store_true", help="skip the served-load section")
+    ap.add_argument("--serve-only", action="store_true",
+                    help="run only the served-load section and print its JSON (profiling aid)")
     ap.add_argument("--serve-rates", default="500,2000,5000",
                     help="Poisson arrival rates (requests/s) of the served-load section")
     ap.add_argument("--serve-requests", type=int, default=1000, help="timed requests per rate")
@@ -233,6 +235,11 @@ def main():
     dev = torch.device("cuda", 0)
     torch.cuda.set_device(dev)
     gal.init(0)
+    if args.serve_only:
+        served = serve_bench(gal, torch, np, dev, [int(r) for r in args.serve_rates.split(",")],
+                             args.serve_requests, 200, 0.5, 8, 2_000_000)
+        print(json.dumps({"served": served}), flush=True)
+        return
     case = wl.profile_2048()
     N, M, Nr = case.N, case.M, case.I.size
     f64 = lambda a: torch.as_tensor(np.ascontiguousarray(a, dtype=np.float64), device=dev)
