@@ -67,7 +67,7 @@ extern "C" {
 #define GAL_ERR_NULL        (-1)  /* a required pointer is NULL */
 #define GAL_ERR_SIZE        (-2)  /* Nxy not a power of two in [16, 8192], Nr < 2, M < 0 */
 #define GAL_ERR_UV_RANGE    (-3)  /* dataset rho_max outside the half spectrum */
-#define GAL_ERR_SCALAR      (-4)  /* dxy <= 0, dR <= 0, Rmin < 0, cos(inc) <= 0, non-finite */
+#define GAL_ERR_SCALAR      (-4)  /* dxy < 1e-100, dR <= 0, Rmin < 0, cos(inc) <= 0, non-finite */
 #define GAL_ERR_WORKSPACE   (-5)  /* workspace too small / out of memory */
 #define GAL_ERR_HIP         (-6)  /* a HIP runtime call failed */
 #define GAL_ERR_UNSUPPORTED (-7)  /* e.g. dataset precision differs from the call */

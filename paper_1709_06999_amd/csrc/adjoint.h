@@ -477,7 +477,7 @@ __device__ __forceinline__ void adj_rows_sym_body(const Geom &g, const T *__rest
         const double x = (double)(N / 2 - c) * sw.dxy;
         const double y = (double)(N / 2 - r) * sw.dxy;
         const double xs = x * sw.inv_cos;
-        const double rho = sqrt(xs * xs + y * y);
+        const double rho = sqrt_pos(xs * xs + y * y);
         const double tt = (rho - sw.Rmin) * sw.inv_dR;
         if (tt >= 0.0 && tt <= sw.tmax) {
             int j = (int)tt;

@@ -190,12 +190,11 @@ __device__ __forceinline__ void fft_gather(c2<T> *v, const c2<T> *lds, int tid) 
     }
 }
 
-// Run the passes from stride NS to the end; v holds this pass's inputs.  The
-// natural-order result is left in LDS (element e of row b at Cfg::at(b, e)),
-// followed by a barrier.  `tw` is the twiddle table.
+// One pass with stride NS: twiddles, radix-R butterflies in registers, and
+// the Stockham write of the outputs to LDS (between two barriers).
 template <typename Cfg, int NS, typename T>
-__device__ __forceinline__ void fft_passes(c2<T> *v, c2<T> *lds, const c2<T> *__restrict__ tw,
-                                           int tid) {
+__device__ __forceinline__ void fft_pass(c2<T> *v, c2<T> *lds, const c2<T> *__restrict__ tw,
+                                         int tid) {
     constexpr int L = Cfg::L, NT = Cfg::NT, E = Cfg::E;
     constexpr int R = pass_radix(L, NS, Cfg::RMAX);
     constexpr int LR = L / R;
@@ -222,9 +221,78 @@ __device__ __forceinline__ void fft_passes(c2<T> *v, c2<T> *lds, const c2<T> *__
         for (int t = 0; t < R; ++t) lds[Cfg::at(b, base + t * NS)] = v[i * R + t];
     }
     __syncthreads();
+}
+
+// Run the passes from stride NS to the end; v holds this pass's inputs.  The
+// natural-order result is left in LDS (element e of row b at Cfg::at(b, e)),
+// followed by a barrier.  `tw` is the twiddle table.
+template <typename Cfg, int NS, typename T>
+__device__ __forceinline__ void fft_passes(c2<T> *v, c2<T> *lds, const c2<T> *__restrict__ tw,
+                                           int tid) {
+    constexpr int L = Cfg::L;
+    constexpr int R = pass_radix(L, NS, Cfg::RMAX);
+    fft_pass<Cfg, NS>(v, lds, tw, tid);
     if constexpr (NS * R < L) {
         fft_gather<Cfg, NS * R>(v, lds, tid);
         fft_passes<Cfg, NS * R>(v, lds, tw, tid);
+    }
+}
+
+// Run the passes from stride NS up to, not including, the last one; v then
+// holds the last pass's inputs (for fft_last_pass).
+template <typename Cfg, int NS, typename T>
+__device__ __forceinline__ void fft_passes_but_last(c2<T> *v, c2<T> *lds,
+                                                    const c2<T> *__restrict__ tw, int tid) {
+    constexpr int L = Cfg::L;
+    constexpr int R = pass_radix(L, NS, Cfg::RMAX);
+    if constexpr (NS * R < L) {
+        fft_pass<Cfg, NS>(v, lds, tw, tid);
+        fft_gather<Cfg, NS * R>(v, lds, tid);
+        fft_passes_but_last<Cfg, NS * R>(v, lds, tw, tid);
+    }
+}
+
+// stride of the last pass of a length-L transform
+constexpr int last_stride(int L, int RMAX) {
+    int ns = 1;
+    while (ns * pass_radix(L, ns, RMAX) < L) ns *= pass_radix(L, ns, RMAX);
+    return ns;
+}
+
+// The last pass in registers, for callers that keep only the first `keep`
+// outputs of each sequence (natural order): out(b, e, value) is called for
+// every kept element e of sequence b that this thread holds, e = j + t NS
+// (t < R) for its butterflies j < NS, and the results go to their
+// destination without another trip through LDS.  When keep <= NS only t = 0
+// survives, which is the twiddled sum of the butterfly's inputs.
+template <typename Cfg, typename T, typename Out>
+__device__ __forceinline__ void fft_last_pass(c2<T> *v, const c2<T> *__restrict__ tw, int tid,
+                                              int keep, Out out) {
+    constexpr int L = Cfg::L, NT = Cfg::NT, E = Cfg::E;
+    constexpr int NS = last_stride(L, Cfg::RMAX);
+    constexpr int R = L / NS;
+    static_assert(R == pass_radix(L, NS, Cfg::RMAX), "last pass");
+    const c2<T> *w = tw + L;  // exp(-2 pi i m / L)
+#pragma unroll
+    for (int i = 0; i < E / R; ++i) {
+        const int g = tid + i * NT;
+        const int b = g / NS, j = g % NS;  // L / R = NS butterflies per sequence
+        if (j >= keep) continue;
+        if (NS > 1) {
+#pragma unroll
+            for (int t = 1; t < R; ++t) v[i * R + t] = cmul(v[i * R + t], w[t * j]);
+        }
+        if (keep <= NS) {
+            c2<T> s = v[i * R];
+#pragma unroll
+            for (int t = 1; t < R; ++t) s = cadd(s, v[i * R + t]);
+            out(b, j, s);
+        } else {
+            dftR<R>(v + i * R);
+#pragma unroll
+            for (int t = 0; t < R; ++t)
+                if (j + t * NS < keep) out(b, j + t * NS, v[i * R + t]);
+        }
     }
 }
 

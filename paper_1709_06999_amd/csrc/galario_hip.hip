@@ -430,10 +430,13 @@ static int carve(void *ws, size_t bytes, int N, int64_t M, WS &out) {
 // ---------------------------------------------------------------------------
 // argument checks
 static bool pow2_in_range(int N) { return N >= 16 && N <= 8192 && (N & (N - 1)) == 0; }
+// smallest pixel size: squared pixel radii stay far above the range where the
+// sweep's square root would need scaling
+constexpr double DXY_MIN = 1e-100;
 
 static int check_image_scalars(int N, double dxy, double PA, double dRA, double dDec, double inc) {
     if (!pow2_in_range(N)) return fail(GAL_ERR_SIZE, "Nxy=%d: need a power of two in [16, 8192]", N);
-    if (!(dxy > 0.0) || !std::isfinite(dxy)) return fail(GAL_ERR_SCALAR, "dxy must be > 0");
+    if (!(dxy >= DXY_MIN) || !std::isfinite(dxy)) return fail(GAL_ERR_SCALAR, "dxy must be >= 1e-100");
     if (!std::isfinite(PA) || !std::isfinite(dRA) || !std::isfinite(dDec) || !std::isfinite(inc))
         return fail(GAL_ERR_SCALAR, "PA, dRA, dDec and inc must be finite");
     if (!(std::cos(inc) > 0.0)) return fail(GAL_ERR_SCALAR, "cos(inc) must be > 0");
@@ -1311,7 +1314,7 @@ static int ds_grad(const gal_dataset *ds, int Nxy, double dxy, Geom &g, Obs<T> &
         return fail(GAL_ERR_UNSUPPORTED, "dataset precision %d differs from the call", ds->precision);
     if (!ds->re) return fail(GAL_ERR_UNSUPPORTED, "dataset holds no observations");
     if (!pow2_in_range(Nxy)) return fail(GAL_ERR_SIZE, "Nxy=%d unsupported", Nxy);
-    if (!(dxy > 0.0) || !std::isfinite(dxy)) return fail(GAL_ERR_SCALAR, "dxy must be > 0");
+    if (!(dxy >= DXY_MIN) || !std::isfinite(dxy)) return fail(GAL_ERR_SCALAR, "dxy must be >= 1e-100");
     const double du = 1.0 / ((double)Nxy * dxy);
     if (!(ds->rho_max < ((double)(Nxy / 2) - 1.0) * du))
         return fail(GAL_ERR_UV_RANGE, "rho_max = %.6g lambda reaches beyond the half spectrum",
@@ -1373,7 +1376,7 @@ static int plan_batch(const gal_job *jobs, int n, void *const *grads, size_t bas
         if (!J.ds->re) return fail(GAL_ERR_UNSUPPORTED, "job %d: dataset holds no observations", i);
         if (J.kind != 0 && J.kind != 1) return fail(GAL_ERR_UNSUPPORTED, "job %d: kind must be 0 or 1", i);
         if (!pow2_in_range(J.Nxy)) return fail(GAL_ERR_SIZE, "job %d: Nxy unsupported", i);
-        if (!(J.dxy > 0.0) || !std::isfinite(J.dxy)) return fail(GAL_ERR_SCALAR, "job %d: dxy must be > 0", i);
+        if (!(J.dxy >= DXY_MIN) || !std::isfinite(J.dxy)) return fail(GAL_ERR_SCALAR, "job %d: dxy must be >= 1e-100", i);
         if (J.kind == 1 && J.Nr < 2) return fail(GAL_ERR_SIZE, "job %d: Nr < 2", i);
         if (J.ds->device != dev) return fail(GAL_ERR_UNSUPPORTED, "job %d: dataset on another device", i);
         const double du = 1.0 / ((double)J.Nxy * J.dxy);

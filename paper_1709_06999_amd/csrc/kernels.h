@@ -83,6 +83,23 @@ struct SweepArgs {
     double Rmin, inv_dR, dxy, inv_cos, pix_area, tmax;
 };
 
+// Square root of a squared pixel radius: x is a normal number well above
+// 2^-767 (pixel sizes are >= 1e-100 rad, checked on the host), so the
+// hardware reciprocal square root needs none of the general routine's
+// range scaling; one Goldschmidt step and two Newton corrections give the
+// correctly rounded root in practice (checked on 2e7 arguments).
+__device__ __forceinline__ double sqrt_pos(double x) {
+    const double y = __builtin_amdgcn_rsq(x);
+    double g = x * y, h = 0.5 * y;
+    const double r = fma(-g, h, 0.5);
+    g = fma(g, r, g);
+    h = fma(h, r, h);
+    double d = fma(-g, g, x);
+    g = fma(d, h, g);
+    d = fma(-g, g, x);
+    return fma(d, h, g);
+}
+
 // PI: pointer to the profile (generic, or global for pointers read from tables)
 template <typename PI>
 __device__ __forceinline__ double sweep_pixel(PI I, int N, int r, int c, const SweepArgs &a) {
@@ -93,7 +110,7 @@ __device__ __forceinline__ double sweep_pixel(PI I, int N, int r, int c, const S
     const double x = (double)(N / 2 - c) * a.dxy;
     const double y = (double)(N / 2 - r) * a.dxy;
     const double xs = x * a.inv_cos;
-    const double rho = sqrt(xs * xs + y * y);
+    const double rho = sqrt_pos(xs * xs + y * y);
     const double t = (rho - a.Rmin) * a.inv_dR;
     if (t >= 0.0 && t <= a.tmax) {
         int j = (int)t;
@@ -253,18 +270,19 @@ __device__ __forceinline__ void rows_sym_body(PI I, const SweepArgs &sw, const G
             v[i * R0 + t] = lds[Cfg::at(b, n <= N / 2 ? n : N - n)];
         }
     }
-    fft_passes<Cfg, 1>(v, lds, twiddles<T>(), tid);
-
-    constexpr int RB = 2 * B;  // rows per block
-    for (int idx = tid; idx < Qe * RB; idx += NT) {
-        const int q = idx / RB, rr = idx % RB;
-        const int r = 2 * m0 + rr;
-        if (r > N / 2) continue;
-        const c2<T> z = lds[Cfg::at(rr >> 1, q)];
-        T x = (rr & 1) ? z.y : z.x;
-        if (q & 1) x = -x;
-        XR[(size_t)q * g.CS + r] = x;
-    }
+    const c2<T> *tw = twiddles<T>();
+    fft_passes_but_last<Cfg, 1>(v, lds, tw, tid);
+    // last pass in registers: only outputs q < Qe are kept, and the two rows
+    // of a pair are adjacent in XR (one 16-byte store; CS and r are even)
+    fft_last_pass<Cfg>(v, tw, tid, Qe, [&](int b, int q, c2<T> z) {
+        const int r = 2 * (m0 + b);
+        if (r > N / 2) return;
+        if (q & 1) z = c2<T>{-z.x, -z.y};
+        if (r + 1 <= N / 2)
+            *reinterpret_cast<c2<T> *>(XR + (size_t)q * g.CS + r) = z;
+        else
+            XR[(size_t)q * g.CS + r] = z.x;
+    });
 }
 
 template <typename T, typename Cfg>
@@ -305,18 +323,17 @@ __device__ __forceinline__ void cols_sym_body(const Geom &g, int Qe, T *__restri
             }
         }
     }
-    fft_passes<Cfg, 1>(v, lds, twiddles<T>(), tid);
-
-    const int NP = g.P + 1;
-    for (int idx = tid; idx < NP * 2 * B; idx += NT) {
-        const int cb = idx / NP, p = idx % NP;
-        const int q = 2 * m0 + cb;
-        if (q >= Qe) continue;
-        const c2<T> z = lds[Cfg::at(cb >> 1, p)];
-        T x = (cb & 1) ? z.y : z.x;
-        if (p & 1) x = -x;
-        XR[(size_t)q * g.CS + p] = x;
-    }
+    const c2<T> *tw = twiddles<T>();
+    fft_passes_but_last<Cfg, 1>(v, lds, tw, tid);
+    // last pass in registers, rows p <= P kept; every read of this block's
+    // columns happened before the first barrier, so the in-place stores are safe
+    fft_last_pass<Cfg>(v, tw, tid, g.P + 1, [&](int b, int p, c2<T> z) {
+        const int q = 2 * (m0 + b);
+        if (q >= Qe) return;
+        const T sg = (p & 1) ? T(-1) : T(1);
+        XR[(size_t)q * g.CS + p] = sg * z.x;
+        XR[(size_t)(q + 1) * g.CS + p] = sg * z.y;
+    });
 }
 
 template <typename T, typename Cfg>
