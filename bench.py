@@ -71,6 +71,18 @@ def algorithmic_bytes(N, Nr, M, Q, P, kind="profile", p=8):
             "k_sample_chi2": 5 * p * M + spec, "k_reduce": red}
 
 
+def path_bytes(N, Nr, M, p=8):
+    """Bytes of one chi2Profile evaluation as the roofline of the whole path
+    counts them: the profile, the full half spectrum written and read once
+    as the row -> column intermediate and once as the spectrum, and five
+    observation columns; with the gradient also the residuals, a second pass
+    over the observations, the scatter grid and the transposed transforms
+    (4 half-spectrum passes) and the profile gradient."""
+    H = N * (N // 2 + 1)
+    chi2 = p * Nr + 2 * (2 * p * H) + 5 * p * M
+    return {"chi2": chi2, "chi2_grad": chi2 + 2 * p * M + 5 * p * M + 4 * (2 * p * H) + p * Nr}
+
+
 def fft_flops(N, Q, K=1):
     """Algorithmic flops of the two FFT passes of the profile path for K jobs,
     counted as 5 L log2 L per complex FFT of length L: the row pass transforms
@@ -202,6 +214,7 @@ def main():
     ap.add_argument("--batch", type=int, default=16, help="models per batched step")
     ap.add_argument("--plain-steps", type=int, default=2000)
     ap.add_argument("--latency-samples", type=int, default=300)
+    ap.add_argument("--grad-steps", type=int, default=300, help="timed plain gradient calls")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-graph", action="store_true", help="launch batches without a HIP graph")
     ap.add_argument("--calib-copy", action="store_true",
@@ -286,6 +299,11 @@ def main():
         lat.append((time.perf_counter() - a) * 1e3)
     lat = np.sort(np.array(lat))
 
+    # ---- plain gradient: chi^2 and d chi^2 / d I per call ------------------
+    grad_call = lambda: ds.chi2Profile_grad(I, case.Rmin, case.dR, N, case.dxy, **geo)
+    ms_grad = _timed(grad_call, args.grad_steps, args.warmup, torch)
+    kern_grad = _kernel_times(gal, grad_call, max(args.grad_steps // 3, 20), torch)
+
     # ---- batched: K walkers (different profiles and geometry) per step ----
     K = args.batch
     rng = np.random.default_rng(1102)
@@ -320,6 +338,12 @@ def main():
     replay_ok = bool(torch.equal(eager, batch.out))
     kern = _kernel_times(gal, batch.chi2, max(args.steps // 4, 20), torch)
     evals_per_s = K * 1e3 / ms_batch
+
+    # ---- batched with gradients: the same K walkers, one batch_exec call ---
+    gbuf = [torch.empty_like(Ib[k]) for k in range(K)]
+    gjobs = batch.jobs
+    gstep = lambda: gal.batch_exec(gjobs, gbuf)
+    ms_bgrad = _timed(gstep, max(args.steps // 4, 20), args.warmup, torch)
 
     # ---- roofline of the dominant kernel of the batched step ---------------
     ab = algorithmic_bytes(N, Nr, M, Q, P, "profile")
@@ -365,6 +389,17 @@ def main():
     roofline["step_alg_bytes"] = sum(ab_batch.values())
     roofline["step_hbm_frac"] = round(sum(ab_batch.values()) / (ms_batch * 1e-3) / 1e9 /
                                       HBM_PEAK_GBS, 4)
+
+    pb = path_bytes(N, Nr, M)
+    path_roofline = {
+        "definition": "evals/s x bytes per evaluation (full half spectrum, no pruning or "
+                      "batching credit) / 8 TB/s",
+        "bytes_per_eval": pb,
+        "plain": round(1e3 / ms_plain * pb["chi2"] / 1e9 / HBM_PEAK_GBS, 4),
+        "batched": round(evals_per_s * pb["chi2"] / 1e9 / HBM_PEAK_GBS, 4),
+        "plain_grad": round(1e3 / ms_grad * pb["chi2_grad"] / 1e9 / HBM_PEAK_GBS, 4),
+        "batched_grad": round(K * 1e3 / ms_bgrad * pb["chi2_grad"] / 1e9 / HBM_PEAK_GBS, 4),
+    }
 
     served = None
     if not args.no_serve:
@@ -418,6 +453,12 @@ def main():
                                  "p99": round(float(np.percentile(lat, 99)), 4)},
                   "kernels": rnd(kern_plain)},
         "batched_vs_plain": round(evals_per_s / (1e3 / ms_plain), 3),
+        "grad": {"plain": {"value": round(1e3 / ms_grad, 1), "unit": "chi2+grad evals/s",
+                           "ms_per_eval": round(ms_grad, 5), "kernels": rnd(kern_grad)},
+                 "batched": {"value": round(K * 1e3 / ms_bgrad, 1), "unit": "chi2+grad evals/s",
+                             "ms_per_step": round(ms_bgrad, 5), "batch": K,
+                             "form": "one gal_batch_exec call per step (planned at the call)"}},
+        "path_roofline": path_roofline,
         "served": served,
         "kernels": rnd(kern),
         "roofline": roofline,

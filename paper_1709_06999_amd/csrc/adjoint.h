@@ -40,13 +40,18 @@ __global__ __launch_bounds__(256) void k_zero(T *__restrict__ p, int64_t n) {
 // Each point adds hv * wa * ws to the four nodes of its stencil, node (q, i)
 // at flat index q * CS + i (times NV components: 1 real, 2 complex), with
 // wa = 1 - a at i and a at i + 1, ws = 1 - s at q and s at q + 1.  The points
-// of one sampling block are consecutive in Morton order, a compact patch of
-// the uv plane, so their nodes span a small box: they are added into an LDS
-// tile over that box (one LDS atomic per node value) and the tile is added to
-// the grid with one global atomic per touched value.  Dense uv cores, where
-// thousands of points share a node, then cost few global atomics.  A box
-// larger than the tile falls back to direct global atomics.
-constexpr int SCAT_TILE = 2048;  // doubles of LDS per block
+// of one sampling block are consecutive in the locality order of datasets,
+// a compact patch of the uv plane, so their nodes span a small box.  The box
+// is covered by windows of whole q-rows that fit an LDS tile; per window the
+// points add into the tile (one LDS atomic per node value) and the tile is
+// added to the grid row by row with one global atomic per touched value.
+// That turns scattered global atomics into coalesced ones, and in dense uv
+// cores, where thousands of points share a node, into a few.  A box larger
+// than SCAT_WINDOWS tiles (sparse points spread thin, where clearing and
+// scanning the box would cost more than the atomics it saves) falls back to
+// direct global atomics.
+constexpr int SCAT_TILE = 4096;  // doubles of LDS per block
+constexpr int SCAT_WINDOWS = 4;
 
 template <int NV>
 struct PointAdd {
@@ -102,36 +107,8 @@ __device__ __forceinline__ void block_scatter(T *__restrict__ A, int CS, const P
     }
     if (qlo > qhi) return;  // no point of the block adds anything (uniform)
     const int TQ = qhi - qlo + 2, TI = ihi - ilo + 2;
-    if (TQ * TI * NV <= SCAT_TILE) {
-        for (int k = threadIdx.x; k < TQ * TI * NV; k += blockDim.x) tile[k] = 0.0;
-        __syncthreads();
-#pragma unroll
-        for (int p = 0; p < NP; ++p) {
-            if (pa[p].q < 0) continue;
-            const int b = ((pa[p].q - qlo) * TI + (pa[p].i - ilo)) * NV;
-            const double wa[2] = {1.0 - pa[p].a, pa[p].a}, ws[2] = {1.0 - pa[p].s, pa[p].s};
-#pragma unroll
-            for (int dq = 0; dq < 2; ++dq)
-#pragma unroll
-                for (int di = 0; di < 2; ++di)
-#pragma unroll
-                    for (int c = 0; c < NV; ++c)
-                        atomicAdd(&tile[b + (dq * TI + di) * NV + c], pa[p].hv[c] * wa[di] * ws[dq]);
-        }
-        __syncthreads();
-        // flat tile index -> (row, column) of the box: exact in float for
-        // indices below 2^11 (the quotient stays >= 0.5/TI from an integer)
-        const float inv = 1.0f / (float)TI;
-        for (int k = threadIdx.x; k < TQ * TI; k += blockDim.x) {
-            const int dq = (int)(((float)k + 0.5f) * inv), di = k - dq * TI;
-            const size_t n = (size_t)(qlo + dq) * CS + (ilo + di);
-#pragma unroll
-            for (int c = 0; c < NV; ++c) {
-                const double v = tile[k * NV + c];
-                if (v != 0.0) atomicAdd(&A[n * NV + c], (T)v);
-            }
-        }
-    } else {
+    const int SQ = SCAT_TILE / (TI * NV);  // q-rows per window
+    if (SQ < 1 || TQ * TI * NV > SCAT_WINDOWS * SCAT_TILE) {
 #pragma unroll
         for (int p = 0; p < NP; ++p) {
             if (pa[p].q < 0) continue;
@@ -146,6 +123,81 @@ __device__ __forceinline__ void block_scatter(T *__restrict__ A, int CS, const P
                         atomicAdd(&A[(n + (size_t)dq * CS + di) * NV + c],
                                   (T)(pa[p].hv[c] * wa[di] * ws[dq]));
         }
+        return;
+    }
+    // node values of point 0 with the later points of the same stencil folded
+    // in (dense uv cores: fewer conflicting adds); `own` marks the others
+    double acc[4][NV];
+    bool own[NP];
+#pragma unroll
+    for (int n = 0; n < 4; ++n)
+#pragma unroll
+        for (int c = 0; c < NV; ++c) acc[n][c] = 0.0;
+#pragma unroll
+    for (int p = 0; p < NP; ++p) {
+        own[p] = false;
+        if (pa[p].q < 0) continue;
+        if (p > 0 && (pa[p].q != pa[0].q || pa[p].i != pa[0].i)) {
+            own[p] = true;
+            continue;
+        }
+        const double wa[2] = {1.0 - pa[p].a, pa[p].a}, ws[2] = {1.0 - pa[p].s, pa[p].s};
+#pragma unroll
+        for (int dq = 0; dq < 2; ++dq)
+#pragma unroll
+            for (int di = 0; di < 2; ++di)
+#pragma unroll
+                for (int c = 0; c < NV; ++c) acc[2 * dq + di][c] += pa[p].hv[c] * wa[di] * ws[dq];
+    }
+    // flat index -> (row, column) of a window: exact in float for indices
+    // below 2^12 (the quotient stays >= 0.5/TI from an integer, far above the
+    // float rounding of k/TI)
+    const float inv = 1.0f / (float)TI;
+    for (int w0 = qlo; w0 < qlo + TQ; w0 += SQ) {
+        const int w1 = min(w0 + SQ, qlo + TQ);  // q-rows [w0, w1) of this window
+        const int nk = (w1 - w0) * TI;
+        for (int k = threadIdx.x; k < nk * NV; k += blockDim.x) tile[k] = 0.0;
+        __syncthreads();
+        if (pa[0].q >= 0) {
+#pragma unroll
+            for (int dq = 0; dq < 2; ++dq) {
+                const int qn = pa[0].q + dq;
+                if (qn < w0 || qn >= w1) continue;
+#pragma unroll
+                for (int di = 0; di < 2; ++di)
+#pragma unroll
+                    for (int c = 0; c < NV; ++c)
+                        atomicAdd(&tile[((qn - w0) * TI + pa[0].i + di - ilo) * NV + c],
+                                  acc[2 * dq + di][c]);
+            }
+        }
+#pragma unroll
+        for (int p = 1; p < NP; ++p) {
+            if (!own[p]) continue;
+            const double wa[2] = {1.0 - pa[p].a, pa[p].a}, ws[2] = {1.0 - pa[p].s, pa[p].s};
+#pragma unroll
+            for (int dq = 0; dq < 2; ++dq) {
+                const int qn = pa[p].q + dq;
+                if (qn < w0 || qn >= w1) continue;
+#pragma unroll
+                for (int di = 0; di < 2; ++di)
+#pragma unroll
+                    for (int c = 0; c < NV; ++c)
+                        atomicAdd(&tile[((qn - w0) * TI + pa[p].i + di - ilo) * NV + c],
+                                  pa[p].hv[c] * wa[di] * ws[dq]);
+            }
+        }
+        __syncthreads();
+        for (int k = threadIdx.x; k < nk; k += blockDim.x) {
+            const int dq = (int)(((float)k + 0.5f) * inv), di = k - dq * TI;
+            const size_t n = (size_t)(w0 + dq) * CS + (ilo + di);
+#pragma unroll
+            for (int c = 0; c < NV; ++c) {
+                const double v = tile[k * NV + c];
+                if (v != 0.0) atomicAdd(&A[n * NV + c], (T)v);
+            }
+        }
+        __syncthreads();  // the flush has read the tile before it is cleared
     }
 }
 
@@ -191,14 +243,16 @@ __global__ __launch_bounds__(SAMPLE_NT) void k_sample_scatter(
     __shared__ double tile[SCAT_TILE];
     __shared__ int box[4 * (SAMPLE_NT / 64)];
     const int blk = xcd_remap(blockIdx.x, gridDim.x);
-    const int64_t base = (int64_t)blk * (SAMPLE_NT * SAMPLE_PPT) + threadIdx.x;
+    // each thread takes SAMPLE_PPT consecutive points: neighbours in the
+    // locality order of datasets, which in dense regions share a stencil
+    const int64_t base = (int64_t)blk * (SAMPLE_NT * SAMPLE_PPT) + threadIdx.x * SAMPLE_PPT;
     double acc = 0.0;
     bool bad = false;
     PointAdd<NV> pa[SAMPLE_PPT];
 #pragma unroll
     for (int p = 0; p < SAMPLE_PPT; ++p) {
         pa[p].q = -1;
-        const int64_t k = base + p * SAMPLE_NT;
+        const int64_t k = base + p;
         if (k >= a.M) continue;
         const double uu = u[k], vv = v[k];
         double sn, cs;

@@ -1022,21 +1022,32 @@ int gal_sample_spectrum_f(const float *spec, int Nxy, double dxy, const float *u
 // [-rho_max, rho_max]^2: neighbouring keys are neighbouring points, and a
 // rotation by PA keeps neighbours together, so a wavefront of consecutive
 // points gathers from a few cache lines of the spectrum.
-static uint32_t spread16(uint32_t x) {
-    x &= 0xFFFFu;
-    x = (x | (x << 8)) & 0x00FF00FFu;
-    x = (x | (x << 4)) & 0x0F0F0F0Fu;
-    x = (x | (x << 2)) & 0x33333333u;
-    x = (x | (x << 1)) & 0x55555555u;
-    return x;
-}
-
-static uint32_t morton_key(double u, double v, double rho_max) {
+// Locality order of a dataset: position along a Hilbert curve over a
+// 65536^2 grid spanning [-rho_max, rho_max]^2.  Consecutive runs of points are
+// connected patches of the uv plane (a Z-order curve jumps between distant
+// quadrants), so a sampling block's stencil nodes span a compact box.
+static uint64_t hilbert_key(double u, double v, double rho_max) {
     const double sc = rho_max > 0.0 ? 32767.5 / rho_max : 0.0;
-    double x = (u * sc) + 32767.5, y = (v * sc) + 32767.5;
-    x = x < 0.0 ? 0.0 : (x > 65535.0 ? 65535.0 : x);
-    y = y < 0.0 ? 0.0 : (y > 65535.0 ? 65535.0 : y);
-    return spread16((uint32_t)x) | (spread16((uint32_t)y) << 1);
+    double xf = (u * sc) + 32767.5, yf = (v * sc) + 32767.5;
+    xf = xf < 0.0 ? 0.0 : (xf > 65535.0 ? 65535.0 : xf);
+    yf = yf < 0.0 ? 0.0 : (yf > 65535.0 ? 65535.0 : yf);
+    uint32_t x = (uint32_t)xf, y = (uint32_t)yf;
+    constexpr uint32_t n = 65536;
+    uint64_t d = 0;
+    for (uint32_t s = n / 2; s > 0; s /= 2) {
+        const uint32_t rx = (x & s) ? 1u : 0u, ry = (y & s) ? 1u : 0u;
+        d += (uint64_t)s * s * ((3u * rx) ^ ry);
+        if (ry == 0) {  // rotate the quadrant so that the sub-curve starts at its corner
+            if (rx == 1) {
+                x = n - 1 - x;
+                y = n - 1 - y;
+            }
+            const uint32_t t = x;
+            x = y;
+            y = t;
+        }
+    }
+    return d;
 }
 
 template <typename T>
@@ -1069,11 +1080,11 @@ static int dataset_create(const T *u, const T *v, const T *re, const T *im, cons
     }
     const double rho_max = std::sqrt(r2max);
     // locality order
-    std::vector<std::pair<uint32_t, int32_t>> key((size_t)M);
+    std::vector<std::pair<uint64_t, int32_t>> key((size_t)M);
     for (int64_t k = 0; k < M; ++k)
-        key[k] = {morton_key((double)h[0][k], (double)h[1][k], rho_max), (int32_t)k};
+        key[k] = {hilbert_key((double)h[0][k], (double)h[1][k], rho_max), (int32_t)k};
     std::stable_sort(key.begin(), key.end(),
-                     [](const std::pair<uint32_t, int32_t> &a, const std::pair<uint32_t, int32_t> &b) {
+                     [](const std::pair<uint64_t, int32_t> &a, const std::pair<uint64_t, int32_t> &b) {
                          return a.first < b.first;
                      });
     std::vector<int32_t> perm((size_t)M);

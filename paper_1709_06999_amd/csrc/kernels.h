@@ -509,13 +509,20 @@ __global__ __launch_bounds__(SAMPLE_NT) void k_sample_sym(
     __shared__ double red[SAMPLE_NT / 64];
     const int blk = xcd_remap(blockIdx.x, gridDim.x);
     const int64_t base = (int64_t)blk * (SAMPLE_NT * PPT) + threadIdx.x;
-    double uu[PPT], vv[PPT];
+    // every column load is issued before the arithmetic (the observations
+    // are independent of the stencil, so they stream in during the gathers)
+    double uu[PPT], vv[PPT], rr[PPT], ii[PPT], ww[PPT];
 #pragma unroll
     for (int p = 0; p < PPT; ++p) {
         const int64_t k = base + p * SAMPLE_NT;
         const bool in = k < a.M;
         uu[p] = in ? (double)u[k] : 0.0;
         vv[p] = in ? (double)v[k] : 0.0;
+        if constexpr (CHI2) {
+            rr[p] = in ? (double)re[k] : 0.0;
+            ii[p] = in ? (double)im[k] : 0.0;
+            ww[p] = in ? (double)w[k] : 0.0;
+        }
     }
     StencilR<T> st[PPT];
     c2<T> lo0[PPT], lo1[PPT];
@@ -551,9 +558,9 @@ __global__ __launch_bounds__(SAMPLE_NT) void k_sample_sym(
                 Vim = a.cinc * b * sn;
             }
             if constexpr (CHI2) {
-                const double dr = Vre - (double)re[k];
-                const double di = Vim - (double)im[k];
-                acc += (double)w[k] * (dr * dr + di * di);
+                const double dr = Vre - rr[p];
+                const double di = Vim - ii[p];
+                acc += ww[p] * (dr * dr + di * di);
             } else {
                 vis[perm ? (int64_t)perm[k] : k] = c2<T>{(T)Vre, (T)Vim};
             }
@@ -575,13 +582,20 @@ __global__ __launch_bounds__(SAMPLE_NT) void k_sample(
     __shared__ double red[SAMPLE_NT / 64];
     const int blk = xcd_remap(blockIdx.x, gridDim.x);
     const int64_t base = (int64_t)blk * (SAMPLE_NT * PPT) + threadIdx.x;
-    double uu[PPT], vv[PPT];
+    // every column load is issued before the arithmetic (the observations
+    // are independent of the stencil, so they stream in during the gathers)
+    double uu[PPT], vv[PPT], rr[PPT], ii[PPT], ww[PPT];
 #pragma unroll
     for (int p = 0; p < PPT; ++p) {
         const int64_t k = base + p * SAMPLE_NT;
         const bool in = k < a.M;
         uu[p] = in ? (double)u[k] : 0.0;
         vv[p] = in ? (double)v[k] : 0.0;
+        if constexpr (CHI2) {
+            rr[p] = in ? (double)re[k] : 0.0;
+            ii[p] = in ? (double)im[k] : 0.0;
+            ww[p] = in ? (double)w[k] : 0.0;
+        }
     }
     Stencil<T> st[PPT];
     c2<T> n00[PPT], n10[PPT], n01[PPT], n11[PPT];
@@ -603,9 +617,9 @@ __global__ __launch_bounds__(SAMPLE_NT) void k_sample(
             finish<T>(st[p], n00[p], n10[p], n01[p], n11[p], a, uu[p], vv[p], Vre, Vim);
             bad |= !st[p].ok;
             if constexpr (CHI2) {
-                const double dr = Vre - (double)re[k];
-                const double di = Vim - (double)im[k];
-                acc += (double)w[k] * (dr * dr + di * di);
+                const double dr = Vre - rr[p];
+                const double di = Vim - ii[p];
+                acc += ww[p] * (dr * dr + di * di);
             } else {
                 vis[perm ? (int64_t)perm[k] : k] = c2<T>{(T)Vre, (T)Vim};
             }
