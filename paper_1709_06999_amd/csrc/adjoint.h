@@ -469,7 +469,11 @@ __global__ __launch_bounds__(Cfg::NT) void k_adj_cols_sym(Geom g, int Qe, T *__r
 // (halved off q = 0, N/2), packed; g[r][c] = -2 x transform, c in [0, N/2].
 // Each pixel then adds m(r) m(c) g dxy^2 (1 - f) to bin j and ... f to bin j+1
 // (centre pixel: (1 + Rmin/dR) to bin 0 and -Rmin/dR to bin 1) in an LDS
-// histogram, flushed to gI with one atomic per touched bin.
+// histogram, flushed with one atomic per touched bin into copy blk mod
+// GI_COPIES of the bin accumulator: the outer bins are reached by almost
+// every row pair, and same-address atomics serialise, so the copies split
+// those chains; k_sum_bins adds the copies afterwards.
+constexpr int GI_COPIES = 16;
 template <typename T, typename Cfg>
 __device__ __forceinline__ void adj_rows_sym_body(const Geom &g, const T *__restrict__ H,
                                                   const SweepArgs &sw, double *__restrict__ gI,
@@ -543,8 +547,12 @@ __device__ __forceinline__ void adj_rows_sym_body(const Geom &g, const T *__rest
             jhi = j + 1 > jhi ? j + 1 : jhi;
         }
     }
-    atomicMin(&jlo_s, jlo);
-    atomicMax(&jhi_s, jhi);
+    jlo = wave_min(jlo);  // one LDS atomic per wave instead of one per thread
+    jhi = wave_max(jhi);
+    if ((tid & 63) == 0) {
+        atomicMin(&jlo_s, jlo);
+        atomicMax(&jhi_s, jhi);
+    }
     __syncthreads();
     for (int k = jlo_s + tid; k <= jhi_s; k += NT) {
         const double h = hist[k];
@@ -556,15 +564,24 @@ template <typename T, typename Cfg>
 __global__ __launch_bounds__(Cfg::NT) void k_adj_rows_sym(Geom g, const T *__restrict__ H,
                                                           SweepArgs sw, double *__restrict__ gI) {
     extern __shared__ double hist[];
-    adj_rows_sym_body<T, Cfg>(g, H, sw, gI, hist, blockIdx.x);
+    adj_rows_sym_body<T, Cfg>(g, H, sw, gI + (size_t)(blockIdx.x % GI_COPIES) * sw.Nr, hist,
+                              blockIdx.x);
 }
 
-// profile gradient in the array type (FP32 callers get a float copy)
+// profile gradient: the sum of the accumulator copies, in the array type
 template <typename T>
-__global__ __launch_bounds__(256) void k_cast_out(const double *__restrict__ a, T *__restrict__ b,
-                                                  int n) {
+__device__ __forceinline__ void sum_bins(const double *__restrict__ copies, int n, T *out, int i) {
+    double s = 0.0;
+#pragma unroll
+    for (int c = 0; c < GI_COPIES; ++c) s += copies[(size_t)c * n + i];
+    out[i] = (T)s;
+}
+
+template <typename T>
+__global__ __launch_bounds__(256) void k_sum_bins(const double *__restrict__ copies, int n,
+                                                  T *__restrict__ out) {
     const int i = blockIdx.x * 256 + threadIdx.x;
-    if (i < n) b[i] = (T)a[i];
+    if (i < n) sum_bins<T>(copies, n, out, i);
 }
 
 }  // namespace gal

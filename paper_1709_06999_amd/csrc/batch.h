@@ -278,16 +278,17 @@ __global__ __launch_bounds__(Cfg::NT) void kb_adj_rows_sym(const JobDesc *__rest
     extern __shared__ double hist[];
     const JobDesc &j = jobs[list[blockIdx.y]];
     adj_rows_sym_body<T, Cfg>(geom_of(j), (const T *)(ws + j.a_off), sweep_of(j),
-                              (double *)(ws + j.gi_off), hist, blockIdx.x);
+                              (double *)(ws + j.gi_off) + (size_t)(blockIdx.x % GI_COPIES) * j.Nr,
+                              hist, blockIdx.x);
 }
 
-// profile gradients: the double accumulator into the caller's array
+// profile gradients: the sum of the accumulator copies into the caller's array
 template <typename T>
 __global__ __launch_bounds__(256) void kb_grad_out(const JobDesc *__restrict__ jobs,
                                                    const int *__restrict__ list, const char *ws) {
     const JobDesc &j = jobs[list[blockIdx.y]];
     const int i = blockIdx.x * 256 + threadIdx.x;
-    if (i < j.Nr) ((T *)j.grad)[i] = (T)((const double *)(ws + j.gi_off))[i];
+    if (i < j.Nr) sum_bins<T>((const double *)(ws + j.gi_off), j.Nr, (T *)j.grad, i);
 }
 
 }  // namespace gal

@@ -566,14 +566,19 @@ constexpr int GRAD_NR_MAX = 8192;  // profile bins held in LDS by the transposed
 template <typename T>
 static size_t grad_ws_bytes(int N, int64_t M, int Nr) {
     const size_t xt = align256((size_t)(N / 2 + 1) * (size_t)(N + 2) * sizeof(c2<T>));
-    return ws_bytes<T>(N, M) + xt + align256((size_t)(Nr > 0 ? Nr : 1) * sizeof(double));
+    return ws_bytes<T>(N, M) + xt +
+           align256((size_t)GI_COPIES * (size_t)(Nr > 0 ? Nr : 1) * sizeof(double));
 }
+
+// values per thread in the adjoint FFT passes (more threads per block: a
+// single job's few hundred row pairs leave the CUs short of waves)
+constexpr int ADJ_E = 4;
 
 template <typename T, int N>
 static int launch_adjoint(bool profile, const Geom &gs, int Qe, const SweepArgs &sw, void *A,
                           T *grad, double *gI, hipStream_t s) {
     constexpr int B = cols_B(N);
-    using C = CfgE<T, N, B, 8>;
+    using C = CfgE<T, N, B, ADJ_E>;
     if (profile) {
         int rc = launch("k_adj_cols_sym", k_adj_cols_sym<T, C>, dim3((Qe / 2 + B - 1) / B),
                         dim3(C::NT), s, gs, Qe, A);
@@ -651,16 +656,15 @@ static int grad_path(const T *src, bool profile, const SweepArgs &sw, const Geom
     if (rc) return rc;
     rc = launch("k_reduce", k_reduce, dim3(1), dim3(SAMPLE_NT), s, w.partials, (int)grid.x, chi2);
     if (rc) return rc;
-    double *gacc = profile ? (sizeof(T) == 8 ? (double *)grad : gI) : nullptr;
     if (profile) {
-        rc = launch("k_zero", k_zero<double>, dim3(16), dim3(256), s, gacc, (int64_t)Nr);
+        rc = launch("k_zero", k_zero<double>, dim3(64), dim3(256), s, gI,
+                    (int64_t)GI_COPIES * Nr);
         if (rc) return rc;
     }
-    rc = dispatch_adjoint<T>(profile, gs, Qe, sw, A, grad, gacc, s);
+    rc = dispatch_adjoint<T>(profile, gs, Qe, sw, A, grad, profile ? gI : nullptr, s);
     if (rc) return rc;
-    if (profile && sizeof(T) != 8)
-        rc = launch("k_cast_out", k_cast_out<T>, dim3((Nr + 255) / 256), dim3(256), s, gI, grad,
-                    Nr);
+    if (profile)
+        rc = launch("k_sum_bins", k_sum_bins<T>, dim3((Nr + 255) / 256), dim3(256), s, gI, Nr, grad);
     return rc;
 }
 
@@ -1510,7 +1514,7 @@ static int plan_batch(const gal_job *jobs, int n, void *const *grads, size_t bas
         off += align256(spec_bytes(i));
         if (P.jobs[i].kind == 1) {
             P.jobs[i].gi_off = off;
-            off += align256((size_t)P.jobs[i].Nr * sizeof(double));
+            off += align256((size_t)GI_COPIES * P.jobs[i].Nr * sizeof(double));
         }
     }
     P.zero_end = off;
@@ -1565,7 +1569,7 @@ static int batch_fft(const BatchPlan::FGroup &f, const BatchTables &t, char *ws,
 template <typename T, int N>
 static int batch_adj_n(const BatchPlan::FGroup &f, const BatchTables &t, char *ws, hipStream_t s) {
     constexpr int B = cols_B(N);
-    using C = CfgE<T, N, B, 8>;
+    using C = CfgE<T, N, B, ADJ_E>;
     const int *list = t.lists + f.list_off;
     int rc;
     if (f.kind == 1) {
