@@ -36,6 +36,16 @@ __global__ __launch_bounds__(256) void k_zero(T *__restrict__ p, int64_t n) {
         p[i] = T(0);
 }
 
+// two ranges cleared by one launch
+template <typename T>
+__global__ __launch_bounds__(256) void k_zero2(T *__restrict__ p, int64_t n, double *__restrict__ q,
+                                               int64_t m) {
+    for (int64_t i = (int64_t)blockIdx.x * 256 + threadIdx.x; i < n + m; i += (int64_t)gridDim.x * 256) {
+        if (i < n) p[i] = T(0);
+        else q[i - n] = 0.0;
+    }
+}
+
 // ---- block scatter through an LDS tile --------------------------------------
 // Each point adds hv * wa * ws to the four nodes of its stencil, node (q, i)
 // at flat index q * CS + i (times NV components: 1 real, 2 complex), with

@@ -643,7 +643,9 @@ static int grad_path(const T *src, bool profile, const SweepArgs &sw, const Geom
     if (rc) return rc;
     const int Qe = (g.Q + 1) & ~1;
     const int64_t a_elems = profile ? (int64_t)Qe * gs.CS : (int64_t)2 * gs.Q * gs.CS;
-    rc = launch("k_zero", k_zero<T>, dim3(256), dim3(256), s, A, a_elems);
+    // the scatter grid and, for profiles, the bin accumulator copies
+    rc = launch("k_zero", k_zero2<T>, dim3(256), dim3(256), s, (T *)A, a_elems, gI,
+                profile ? (int64_t)GI_COPIES * Nr : (int64_t)0);
     if (rc) return rc;
     const SampleArgs sa = make_sample(g, o.M, dxy, PA, dRA, dDec, inc);
     const dim3 grid((unsigned)sample_blocks(o.M)), blk(SAMPLE_NT);
@@ -656,11 +658,6 @@ static int grad_path(const T *src, bool profile, const SweepArgs &sw, const Geom
     if (rc) return rc;
     rc = launch("k_reduce", k_reduce, dim3(1), dim3(SAMPLE_NT), s, w.partials, (int)grid.x, chi2);
     if (rc) return rc;
-    if (profile) {
-        rc = launch("k_zero", k_zero<double>, dim3(64), dim3(256), s, gI,
-                    (int64_t)GI_COPIES * Nr);
-        if (rc) return rc;
-    }
     rc = dispatch_adjoint<T>(profile, gs, Qe, sw, A, grad, profile ? gI : nullptr, s);
     if (rc) return rc;
     if (profile)
