@@ -232,19 +232,17 @@ __global__ __launch_bounds__(SAMPLE_NT) void kb_sample_chi2(const JobDesc *__res
     if (bad) ctl->flag = 1;
 }
 
-// chi2[j] = sum of job j's partials in index order (one block per job)
-__global__ __launch_bounds__(SAMPLE_NT) void kb_reduce(const JobDesc *__restrict__ jobs,
+// chi2[j] = sum of job j's partials in a fixed order (one block per job,
+// as k_reduce).  Bitwise repeatable.
+__global__ __launch_bounds__(REDUCE_NT) void kb_reduce(const JobDesc *__restrict__ jobs,
                                                        const SGroup *__restrict__ groups,
                                                        const int *__restrict__ job_group,
                                                        const char *ws, double *__restrict__ chi2) {
-    __shared__ double red[SAMPLE_NT / 64];
+    __shared__ double red[REDUCE_NT / 64];
     const int j = blockIdx.x;
     const JobDesc &J = jobs[j];
     const int n = groups[job_group[j]].nblk * WAVES;
-    const double *part = (const double *)(ws + J.part_off);
-    double s = 0.0;
-    for (int k = threadIdx.x; k < n; k += SAMPLE_NT) s += part[k];
-    const double tot = block_sum(s, red);
+    const double tot = block_sum(strided_sum((const double *)(ws + J.part_off), n), red);
     if (threadIdx.x == 0) chi2[j] = tot;
 }
 

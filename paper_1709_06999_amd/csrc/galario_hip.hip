@@ -539,7 +539,7 @@ static int sample(bool real_spec, const void *S, const Geom &gs, const SampleArg
                     o.im, o.w, nullptr, nullptr, w.partials, w.ctl);
     }
     if (rc) return rc;
-    return launch("k_reduce", k_reduce, dim3(1), dim3(SAMPLE_NT), s, w.partials, (int)grid.x, chi2);
+    return launch("k_reduce", k_reduce, dim3(1), dim3(REDUCE_NT), s, w.partials, (int)grid.x, chi2);
 }
 
 template <typename T>
@@ -656,7 +656,7 @@ static int grad_path(const T *src, bool profile, const SweepArgs &sw, const Geom
         rc = launch("k_sample_scatter", k_sample_scatter<T, false>, grid, blk, s, w.xt, A, gs, sa,
                     o.u, o.v, o.re, o.im, o.w, w.partials, w.ctl);
     if (rc) return rc;
-    rc = launch("k_reduce", k_reduce, dim3(1), dim3(SAMPLE_NT), s, w.partials, (int)grid.x, chi2);
+    rc = launch("k_reduce", k_reduce, dim3(1), dim3(REDUCE_NT), s, w.partials, (int)grid.x, chi2);
     if (rc) return rc;
     rc = dispatch_adjoint<T>(profile, gs, Qe, sw, A, grad, profile ? gI : nullptr, s);
     if (rc) return rc;
@@ -1635,7 +1635,7 @@ static int exec_plan(const BatchPlan &P, const BatchTables &t, char *ws, double 
                         : batch_sample<float, false>(c, P.grads, t, ws, s);
         if (rc) return rc;
     }
-    rc = launch("kb_reduce", kb_reduce, dim3(P.n), dim3(SAMPLE_NT), s, t.jobs, t.groups, t.job_group,
+    rc = launch("kb_reduce", kb_reduce, dim3(P.n), dim3(REDUCE_NT), s, t.jobs, t.groups, t.job_group,
                 ws, chi2);
     if (rc) return rc;
     for (const auto &f : P.agroups) {

@@ -452,12 +452,32 @@ __device__ __forceinline__ void chi2_block_end(double acc, double *red, int blk,
 }
 
 // Final chi^2: one block sums the per-block partials in a fixed order.
-__global__ __launch_bounds__(SAMPLE_NT) void k_reduce(const double *__restrict__ partials, int n,
-                                                      double *__restrict__ out) {
-    __shared__ double red[SAMPLE_NT / 64];
+// Second stage of the chi^2 sum: one block of REDUCE_NT threads; thread t
+// adds partials t, t + REDUCE_NT, ... in that order with all loads issued
+// before the adds (a dependent chain of L2 round trips otherwise sets the
+// kernel's time), then the block sum.  Bitwise repeatable.
+constexpr int REDUCE_NT = 1024;
+constexpr int REDUCE_UNROLL = 8;
+
+__device__ __forceinline__ double strided_sum(const double *__restrict__ part, int n) {
     double s = 0.0;
-    for (int k = threadIdx.x; k < n; k += SAMPLE_NT) s += partials[k];
-    const double tot = block_sum(s, red);
+    for (int k0 = threadIdx.x; k0 < n; k0 += REDUCE_NT * REDUCE_UNROLL) {
+        double x[REDUCE_UNROLL];
+#pragma unroll
+        for (int u = 0; u < REDUCE_UNROLL; ++u) {
+            const int k = k0 + u * REDUCE_NT;
+            x[u] = k < n ? part[k] : 0.0;
+        }
+#pragma unroll
+        for (int u = 0; u < REDUCE_UNROLL; ++u) s += x[u];
+    }
+    return s;
+}
+
+__global__ __launch_bounds__(REDUCE_NT) void k_reduce(const double *__restrict__ partials, int n,
+                                                      double *__restrict__ out) {
+    __shared__ double red[REDUCE_NT / 64];
+    const double tot = block_sum(strided_sum(partials, n), red);
     if (threadIdx.x == 0) *out = tot;
 }
 
