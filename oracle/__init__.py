@@ -80,6 +80,12 @@ def _load():
     lib.orc_grad_profile.argtypes = [_D, _I64, ctypes.c_double, ctypes.c_double,
                                      _I64, ctypes.c_double, ctypes.c_double, _D]
     lib.orc_grad_profile.restype = ctypes.c_int
+    lib.orc_sweep_dinc.argtypes = lib.orc_sweep.argtypes
+    lib.orc_sweep_dinc.restype = ctypes.c_int
+    lib.orc_geograd.argtypes = [_D, _D, _I64, ctypes.c_double, _D, _D, _D, _D, _D, _I64,
+                                ctypes.c_double, ctypes.c_double, ctypes.c_double,
+                                ctypes.c_double, _D]
+    lib.orc_geograd.restype = _I64
     _lib = lib
     return lib
 
@@ -198,3 +204,40 @@ def grad_profile(I, Rmin, dR, Nxy, dxy, u, v, re, im, w, inc=0.0, PA=0.0, dRA=0.
     if rc != 0:
         raise ValueError(f"orc_grad_profile: error {rc}")
     return c2, gI
+
+
+def sweep_dinc(I, Rmin, dR, N, dxy, inc=0.0) -> np.ndarray:
+    """d image / d inc of the swept profile (orc_sweep_dinc)."""
+    I = _f64(I)
+    out = np.empty((N, N), dtype=np.float64)
+    rc = _load().orc_sweep_dinc(_p(I), I.size, float(Rmin), float(dR), int(N), float(dxy),
+                                float(inc), _p(out))
+    if rc != 0:
+        raise ValueError(f"orc_sweep_dinc: error {rc}")
+    return out
+
+
+def _geograd(G, Gt, N, dxy, u, v, re, im, w, PA, dRA, dDec, inc):
+    u, v, re, im, w = map(_f64, (u, v, re, im, w))
+    Gi = np.ascontiguousarray(np.stack([G.real, G.imag], axis=-1))
+    Gti = None if Gt is None else np.ascontiguousarray(np.stack([Gt.real, Gt.imag], axis=-1))
+    out = np.empty(5, dtype=np.float64)
+    _load().orc_geograd(_p(Gi), None if Gti is None else _p(Gti), int(N), float(dxy), _p(u),
+                        _p(v), _p(re), _p(im), _p(w), u.size, float(PA), float(dRA),
+                        float(dDec), float(inc), _p(out))
+    return float(out[0]), out[1:].copy()
+
+
+def geograd_image(image, dxy, u, v, re, im, w, PA=0.0, dRA=0.0, dDec=0.0, inc=0.0):
+    """(chi2, [d/dPA, d/d dRA, d/d dDec, d/d inc]) of chi2Image (orc_geograd)."""
+    image = _f64(image)
+    return _geograd(grid(image), None, image.shape[0], dxy, u, v, re, im, w, PA, dRA, dDec, inc)
+
+
+def geograd_profile(I, Rmin, dR, Nxy, dxy, u, v, re, im, w, inc=0.0, PA=0.0, dRA=0.0,
+                    dDec=0.0):
+    """(chi2, [d/dPA, d/d dRA, d/d dDec, d/d inc]) of chi2Profile: the inclination
+    derivative samples the transform of sweep_dinc's image."""
+    G = grid(sweep(I, Rmin, dR, Nxy, dxy, inc))
+    Gt = grid(sweep_dinc(I, Rmin, dR, Nxy, dxy, inc))
+    return _geograd(G, Gt, Nxy, dxy, u, v, re, im, w, PA, dRA, dDec, inc)

@@ -459,3 +459,133 @@ int orc_grad_profile(const double *gimg, int64_t Nr, double Rmin, double dR,
     gI[1] += gc * pix_area * (-Rmin / dR);
     return 0;
 }
+
+/* ------------------------------------------------------------------------ */
+/* Derivative of the swept image with respect to the inclination (the tilt
+ * of orc_sweep): with rho = sqrt((x / cos inc)^2 + y^2) and the profile
+ * linear on [r_j, r_{j+1}], d img / d inc = dxy^2 (I_{j+1} - I_j) / dR *
+ * d rho / d inc, d rho / d inc = (x / cos inc)^2 tan(inc) / rho, on the same
+ * segment j that orc_sweep uses; 0 outside the profile's range and at the
+ * centre pixel (whose extrapolated value does not depend on inc).  Not in the
+ * paper: the inclination gradient of a swept profile is the transform of
+ * this image. */
+int orc_sweep_dinc(const double *I, int64_t Nr, double Rmin, double dR, int64_t N,
+                   double dxy, double inc, double *dimg)
+{
+    if (Nr < 2 || N < 2 || (N % 2) != 0) return -2;
+    if (!(dR > 0.0) || !(dxy > 0.0) || !(cos(inc) > 0.0) || !(Rmin >= 0.0)) return -4;
+    const double cos_inc = cos(inc), tan_inc = tan(inc);
+    const double pix_area = dxy * dxy;
+    const double t_max = (double)(Nr - 1);
+#pragma omp parallel for schedule(static)
+    for (int64_t r = 0; r < N; ++r) {
+        const double y = (double)(N / 2 - r) * dxy;
+        for (int64_t c = 0; c < N; ++c) {
+            const double x = (double)(N / 2 - c) * dxy;
+            const double xs = x / cos_inc;
+            const double rho = sqrt(xs * xs + y * y);
+            const double t = (rho - Rmin) / dR;
+            double val = 0.0;
+            if (rho > 0.0 && t >= 0.0 && t <= t_max) {
+                int64_t j = (int64_t)floor(t);
+                if (j > Nr - 2) j = Nr - 2;
+                val = (I[j + 1] - I[j]) / dR * (xs * xs * tan_inc / rho);
+            }
+            dimg[r * N + c] = val * pix_area;
+        }
+    }
+    dimg[(N / 2) * N + (N / 2)] = 0.0;
+    return 0;
+}
+
+/* chi^2 and its derivatives with respect to the geometry (not in the paper):
+ * out5 = {chi2, d/dPA, d/d dRA, d/d dDec, d/d inc}.  With R = Vobs - V,
+ * d chi2 / d a = -2 sum_k w_k Re(conj(R_k) dV_k / d a), and, following the
+ * steps of orc_locate / orc_finish:
+ *   - dV/d dRA = 2 pi i u V, dV/d dDec = 2 pi i v V (the phase);
+ *   - PA moves the sampling point: u' = u cos PA - v sin PA and
+ *     v' = u sin PA + v cos PA give du'/dPA = -v', dv'/dPA = u'; the point's
+ *     grid coordinates are fu = m u' cinc / du and fv = m v' / du (m = -1 for
+ *     mirrored points), and the bilinear value B(s, t) has
+ *     dB/ds = (1-t)(b01 - b00) + t(b11 - b10), dB/dt = (1-s)(b10 - b00) + s(b11 - b01);
+ *   - inc (image form, A-15): V^ = cinc conj_m(B(fu, fv)) with
+ *     dfu/dinc = -m u' sin(inc) / du;
+ *   - inc (swept profile, Gt != NULL, sampled with cinc = 1): the image
+ *     itself depends on inc, and dV/dinc samples the spectrum Gt of
+ *     orc_sweep_dinc's image at the same stencil.
+ * Invalid points make chi2 NaN.  Sums in long double, in index order. */
+int64_t orc_geograd(const double *G, const double *Gt, int64_t N, double dxy, const double *u,
+                    const double *v, const double *re, const double *im, const double *w,
+                    int64_t M, double PA, double dRA, double dDec, double inc, double *out5)
+{
+    const double du = 1.0 / ((double)N * dxy);
+    const double cpa = cos(PA), spa = sin(PA);
+    const double cinc = Gt ? 1.0 : cos(inc), sinc = Gt ? 0.0 : sin(inc);
+    long double acc[5] = {0.0L, 0.0L, 0.0L, 0.0L, 0.0L};
+    int64_t bad = 0;
+    for (int64_t k = 0; k < M; ++k) {
+        orc_stencil st;
+        if (!orc_locate(u[k], v[k], N, du, cpa, spa, cinc, &st)) {
+            bad += 1;
+            continue;
+        }
+        double b[8];
+        orc_shifted(G, N, st.i0, st.j0, &b[0], &b[1]);
+        orc_shifted(G, N, st.i0, st.j0 + 1, &b[2], &b[3]);
+        orc_shifted(G, N, st.i0 + 1, st.j0, &b[4], &b[5]);
+        orc_shifted(G, N, st.i0 + 1, st.j0 + 1, &b[6], &b[7]);
+        const double s = st.s, t = st.t;
+        const double msign = st.conj ? -1.0 : 1.0;
+        /* B and its partial derivatives (complex), before the mirror's conjugation */
+        double Br = (1 - t) * ((1 - s) * b[0] + s * b[2]) + t * ((1 - s) * b[4] + s * b[6]);
+        double Bi = (1 - t) * ((1 - s) * b[1] + s * b[3]) + t * ((1 - s) * b[5] + s * b[7]);
+        double Bsr = (1 - t) * (b[2] - b[0]) + t * (b[6] - b[4]);
+        double Bsi = (1 - t) * (b[3] - b[1]) + t * (b[7] - b[5]);
+        double Btr = (1 - s) * (b[4] - b[0]) + s * (b[6] - b[2]);
+        double Bti = (1 - s) * (b[5] - b[1]) + s * (b[7] - b[3]);
+        if (st.conj) {
+            Bi = -Bi;
+            Bsi = -Bsi;
+            Bti = -Bti;
+        }
+        const double up = u[k] * cpa - v[k] * spa, vp = u[k] * spa + v[k] * cpa;
+        const double dfu_dpa = msign * cinc * (-vp) / du, dfv_dpa = msign * up / du;
+        /* V^ and its derivatives (before the phase) */
+        const double Vr = cinc * Br, Vi = cinc * Bi;
+        const double Pr = cinc * (Bsr * dfu_dpa + Btr * dfv_dpa);
+        const double Pi = cinc * (Bsi * dfu_dpa + Bti * dfv_dpa);
+        double Ir, Ii;
+        if (Gt) {
+            double c[8];
+            orc_shifted(Gt, N, st.i0, st.j0, &c[0], &c[1]);
+            orc_shifted(Gt, N, st.i0, st.j0 + 1, &c[2], &c[3]);
+            orc_shifted(Gt, N, st.i0 + 1, st.j0, &c[4], &c[5]);
+            orc_shifted(Gt, N, st.i0 + 1, st.j0 + 1, &c[6], &c[7]);
+            Ir = (1 - t) * ((1 - s) * c[0] + s * c[2]) + t * ((1 - s) * c[4] + s * c[6]);
+            Ii = (1 - t) * ((1 - s) * c[1] + s * c[3]) + t * ((1 - s) * c[5] + s * c[7]);
+            if (st.conj) Ii = -Ii;
+        } else {
+            const double dfu_dinc = -msign * up * sinc / du;
+            Ir = -sinc * Br + cinc * Bsr * dfu_dinc;
+            Ii = -sinc * Bi + cinc * Bsi * dfu_dinc;
+        }
+        /* the phase exp(i theta) */
+        const double theta = TWO_PI * (u[k] * dRA + v[k] * dDec);
+        const double cs = cos(theta), sn = sin(theta);
+        const double VVr = Vr * cs - Vi * sn, VVi = Vr * sn + Vi * cs;
+        const double Rr = re[k] - VVr, Ri = im[k] - VVi;
+        /* Re(conj(R) z e^{i theta}) for each derivative z of V^ */
+        const double Pr2 = Pr * cs - Pi * sn, Pi2 = Pr * sn + Pi * cs;
+        const double Ir2 = Ir * cs - Ii * sn, Ii2 = Ir * sn + Ii * cs;
+        /* dV/d dRA = i 2 pi u V: Re(conj(R) i X) = -Im(conj(R) X) = -(Rr Xi - Ri Xr) */
+        const double imRV = Rr * VVi - Ri * VVr;
+        acc[0] += (long double)(w[k] * (Rr * Rr + Ri * Ri));
+        acc[1] += (long double)(-2.0 * w[k] * (Rr * Pr2 + Ri * Pi2));
+        acc[2] += (long double)(-2.0 * w[k] * (-TWO_PI * u[k] * imRV));
+        acc[3] += (long double)(-2.0 * w[k] * (-TWO_PI * v[k] * imRV));
+        acc[4] += (long double)(-2.0 * w[k] * (Rr * Ir2 + Ri * Ii2));
+    }
+    for (int k = 0; k < 5; ++k) out5[k] = (double)acc[k];
+    if (bad) out5[0] = NAN;
+    return bad;
+}

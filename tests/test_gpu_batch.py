@@ -167,3 +167,47 @@ def test_batch_exec_mixed_with_gradients():
     _, go = oracle.grad_profile(src, gv[0], gv[1], case.N, case.dxy, case.u, case.v, re, im, w,
                                 gv[2], gv[3], gv[4], gv[5])
     assert _rel(grads[3].cpu().numpy(), go) <= 1e-8
+
+
+def test_batch_exec_edge_cases():
+    # an empty dataset (chi^2 = 0, zero gradient), the smallest grid (16^2)
+    # and FP32 profile gradients, in one call, each against its single call
+    dev = device()
+    gal = _gal()
+    import torch
+
+    jobs, grads, want = [], [], []
+    z = torch.zeros(0, dtype=torch.float64, device=dev)
+    empty = gal.Dataset(z, z, z, z, z)
+    prof = torch.linspace(1.0, 0.1, 20, dtype=torch.float64, device=dev)
+    geo0 = torch.tensor([0.0, 1e-7, 0.3, 0.5, 0.0, 0.0], dtype=torch.float64, device=dev)
+    jobs.append({"ds": empty, "kind": gal.JOB_PROFILE, "Nxy": 64, "dxy": 1e-7, "model": prof,
+                 "geo": geo0})
+    grads.append(torch.full_like(prof, 7.0))
+    want.append((0.0, np.zeros(prof.numel())))
+    for i, (N, kind, d) in enumerate([(16, "image", np.float64), (16, "profile", np.float64),
+                                      (128, "profile", np.float32)]):
+        case = wl.random_case(N, 700 + 300 * i, seed=2200 + i, kind=kind, fill=0.8)
+        Vo = _obs(case, d)
+        re, im, w = (rounded(1.05 * Vo.real + case.noise_re, d), rounded(Vo.imag + case.noise_im, d),
+                     rounded(case.w, d))
+        ds = gal.Dataset(*(t(a, d, dev) for a in (case.u, case.v, re, im, w)))
+        model = t(case.image if kind == "image" else case.I, d, dev)
+        geo = torch.as_tensor(_geo(case), dtype=torch.float64, device=dev)
+        jobs.append({"ds": ds, "kind": gal.JOB_IMAGE if kind == "image" else gal.JOB_PROFILE,
+                     "Nxy": N, "dxy": case.dxy, "model": model, "geo": geo})
+        grads.append(torch.empty_like(model))
+        if kind == "image":
+            c2s, gs = ds.chi2Image_grad(model, case.dxy, case.PA, case.dRA, case.dDec, case.inc)
+        else:
+            c2s, gs = ds.chi2Profile_grad(model, case.Rmin, case.dR, N, case.dxy, case.inc,
+                                          case.PA, case.dRA, case.dDec)
+        want.append((float(c2s), gs.cpu().numpy().astype(np.float64)))
+    c2 = gal.batch_exec(jobs, grads).cpu().numpy()
+    for k, ((c2s, gs), g) in enumerate(zip(want, grads)):
+        fp32 = g.dtype == torch.float32
+        if c2s == 0.0:
+            assert c2[k] == 0.0 and not torch.any(g).item()
+            continue
+        assert abs(c2[k] - c2s) <= (1e-6 if fp32 else 1e-12) * c2s, (k, c2[k], c2s)
+        assert _rel(g.cpu().numpy().astype(np.float64), gs) <= (1e-4 if fp32 else 1e-10), k

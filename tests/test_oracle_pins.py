@@ -416,3 +416,66 @@ def test_grad_adjoint_dot_product():
     fp = oracle.chi2Image(case.image + h * d, case.dxy, case.u, case.v, re, im, case.w, **kw)
     fm = oracle.chi2Image(case.image - h * d, case.dxy, case.u, case.v, re, im, case.w, **kw)
     assert abs((fp - fm) / (2 * h) - np.sum(g * d)) <= 1e-8 * abs(np.sum(np.abs(g * d)))
+
+
+# ---- geometry gradients (not in the paper) --------------------------------
+def _geo_obs(rng, M, scale):
+    return (rng.normal(0, scale, M), rng.normal(0, scale, M), rng.uniform(0.5, 2.0, M))
+
+
+def test_geograd_point_source_closed_form():
+    # a centred point source has G = F at every node: V = cos(inc) F exp(i theta),
+    # so the offset and inclination derivatives are explicit and d/dPA = 0
+    N, dxy, F = 32, 1e-7, 1.7
+    img = np.zeros((N, N))
+    img[N // 2, N // 2] = F
+    rng = np.random.default_rng(31)
+    M = 400
+    du = 1.0 / (N * dxy)
+    rho = du * 10 * np.sqrt(rng.uniform(0, 1, M))
+    phi = rng.uniform(0, 2 * np.pi, M)
+    u, v = rho * np.cos(phi), rho * np.sin(phi)
+    re, im, w = _geo_obs(rng, M, 1.0)
+    PA, dRA, dDec, inc = 0.7, 3e-7, -2e-7, 0.4
+    c2, g = oracle.geograd_image(img, dxy, u, v, re, im, w, PA, dRA, dDec, inc)
+    theta = 2 * np.pi * (u * dRA + v * dDec)
+    V = np.cos(inc) * F * np.exp(1j * theta)
+    R = re + 1j * im - V
+    d_dRA = np.sum(-2 * w * np.real(np.conj(R) * 2j * np.pi * u * V))
+    d_dDec = np.sum(-2 * w * np.real(np.conj(R) * 2j * np.pi * v * V))
+    d_inc = np.sum(-2 * w * np.real(np.conj(R) * (-np.sin(inc)) * F * np.exp(1j * theta)))
+    assert abs(c2 - np.sum(w * np.abs(R) ** 2)) <= 1e-12 * c2
+    assert abs(g[0]) <= 1e-12 * np.sum(w * np.abs(R) * F)
+    for got, want in ((g[1], d_dRA), (g[2], d_dDec), (g[3], d_inc)):
+        assert abs(got - want) <= 1e-10 * abs(want), (got, want)
+
+
+def _central(f, x0, h):
+    return (f(x0 + h) - f(x0 - h)) / (2 * h)
+
+
+@pytest.mark.parametrize("kind", ["image", "profile"])
+def test_geograd_matches_central_differences(kind):
+    # the derivative formulas against the derivative of the (separately pinned)
+    # forward chi^2; steps small enough that no point crosses a cell edge
+    case = wl.random_case(32, 600, seed=3300 + (kind == "profile"), kind=kind, Nr=40, fill=0.7)
+    rng = np.random.default_rng(3310)
+    re, im, w = _geo_obs(rng, case.M, 0.02)
+    base = dict(PA=case.PA, dRA=case.dRA, dDec=case.dDec, inc=0.35)
+    if kind == "image":
+        f = lambda **kw: oracle.chi2Image(case.image, case.dxy, case.u, case.v, re, im, w, **kw)
+        c2, g = oracle.geograd_image(case.image, case.dxy, case.u, case.v, re, im, w, **base)
+    else:
+        f = lambda **kw: oracle.chi2Profile(case.I, case.Rmin, case.dR, case.N, case.dxy, case.u,
+                                            case.v, re, im, w, **kw)
+        c2, g = oracle.geograd_profile(case.I, case.Rmin, case.dR, case.N, case.dxy, case.u,
+                                       case.v, re, im, w, **base)
+    assert abs(c2 - f(**base)) <= 1e-12 * c2
+    steps = {"PA": 1e-6, "dRA": 1e-3 * case.dxy, "dDec": 1e-3 * case.dxy, "inc": 1e-6}
+    for k, name in enumerate(("PA", "dRA", "dDec", "inc")):
+        def fk(x, name=name):
+            kw = dict(base)
+            kw[name] = x
+            return f(**kw)
+        fd = _central(fk, base[name], steps[name])
+        assert abs(g[k] - fd) <= 1e-5 * max(abs(fd), 1e-3 * c2), (name, g[k], fd)
