@@ -167,7 +167,9 @@ int gal_sample_spectrum_f(const float *spec, int Nxy, double dxy, const float *u
  * spectrum that the points can reach (|u'|, |v'| <= rho_max): the samples are
  * the same as on the full spectrum.  `precision` of the arrays is fixed at
  * creation (_d: double, _f: float).  re/im/w may be NULL for a dataset used
- * only by sample calls.  Creation allocates and synchronises `stream`. */
+ * only by sample calls; an empty dataset (M = 0) counts as holding (no)
+ * observations, and its chi^2 is 0.  Creation allocates and synchronises
+ * `stream`. */
 typedef struct gal_dataset gal_dataset;
 int gal_dataset_create_d(const double *u, const double *v, const double *re,
                          const double *im, const double *w, int64_t M, void *stream,
@@ -256,6 +258,35 @@ int gal_chi2Profile_grad_ds_f(const gal_dataset *ds, const float *I, int Nr, dou
                               double dR, int Nxy, double dxy, double inc, double PA, double dRA,
                               double dDec, double *chi2, float *grad, void *ws, size_t ws_bytes,
                               void *stream);
+
+/* ---- gradient with respect to the geometry (not in the paper) --------------
+ * chi^2 and d chi^2 / d (PA, dRA, dDec, inc) of chi2Image / chi2Profile on a
+ * dataset: *chi2 (device double) and dgeo[4] (device doubles, in that order).
+ * Offsets enter through the phase (dV/d dRA = 2 pi i u V); PA through the
+ * rotated, mirrored grid coordinates and the bilinear interpolant's
+ * derivative inside its cell (it jumps across cell edges); the inclination of
+ * an image through the u' cos(inc) deprojection and flux factor (A-15), that
+ * of a swept profile through the image itself: its derivative
+ * (x / cos inc)^2 tan(inc) / rho * dI/drho * dxy^2 is transformed by the same
+ * passes and sampled at the same stencils.  Workspace:
+ * gal_geograd_workspace_bytes (256-byte aligned, first 256 bytes zeroed once).
+ * Errors as the chi^2 calls on datasets. */
+size_t gal_geograd_workspace_bytes_d(int Nxy, int64_t M);
+size_t gal_geograd_workspace_bytes_f(int Nxy, int64_t M);
+int gal_chi2Image_geograd_ds_d(const gal_dataset *ds, const double *image, int Nxy, double dxy,
+                               double PA, double dRA, double dDec, double inc, double *chi2,
+                               double *dgeo, void *ws, size_t ws_bytes, void *stream);
+int gal_chi2Image_geograd_ds_f(const gal_dataset *ds, const float *image, int Nxy, double dxy,
+                               double PA, double dRA, double dDec, double inc, double *chi2,
+                               double *dgeo, void *ws, size_t ws_bytes, void *stream);
+int gal_chi2Profile_geograd_ds_d(const gal_dataset *ds, const double *I, int Nr, double Rmin,
+                                 double dR, int Nxy, double dxy, double inc, double PA,
+                                 double dRA, double dDec, double *chi2, double *dgeo, void *ws,
+                                 size_t ws_bytes, void *stream);
+int gal_chi2Profile_geograd_ds_f(const gal_dataset *ds, const float *I, int Nr, double Rmin,
+                                 double dR, int Nxy, double dxy, double inc, double PA,
+                                 double dRA, double dDec, double *chi2, double *dgeo, void *ws,
+                                 size_t ws_bytes, void *stream);
 
 /* ---- batches: many chi^2 evaluations per launch --------------------------
  * A batch is a fixed list of jobs, planned once.  Jobs with the same

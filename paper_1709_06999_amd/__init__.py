@@ -413,6 +413,42 @@ class Dataset:
                 wsb.numel(), _stream(self.device)), "Dataset.chi2Profile_grad")
         return c2, g
 
+    def _geo_ws(self, Nxy, ws):
+        need = getattr(_lib(), "gal_geograd_workspace_bytes" + _sfx(self.dtype))(int(Nxy), self.M)
+        if need == 0:
+            raise GalarioError(-2, f"geograd workspace size (Nxy={Nxy})")
+        return _ws(self.device, self.dtype, ws).reserve_bytes(int(need))
+
+    def chi2Image_geograd(self, image, dxy, PA=0.0, dRA=0.0, dDec=0.0, inc=0.0,
+                          ws: Workspace | None = None):
+        """(chi^2 0-d tensor, d chi^2 / d [PA, dRA, dDec, inc] as a float64 tensor [4])."""
+        self._chk(image, "image")
+        N = image.shape[0]
+        c2 = torch.empty((), dtype=torch.float64, device=self.device)
+        g = torch.empty(4, dtype=torch.float64, device=self.device)
+        wsb = self._geo_ws(N, ws)
+        with torch.cuda.device(self.device):
+            check(getattr(_lib(), "gal_chi2Image_geograd_ds" + _sfx(self.dtype))(
+                self._h, _ptr(image), N, float(dxy), float(PA), float(dRA), float(dDec),
+                float(inc), _ptr(c2), _ptr(g), _ptr(wsb), wsb.numel(), _stream(self.device)),
+                "Dataset.chi2Image_geograd")
+        return c2, g
+
+    def chi2Profile_geograd(self, I, Rmin, dR, Nxy, dxy, inc=0.0, PA=0.0, dRA=0.0, dDec=0.0,
+                            ws: Workspace | None = None):
+        """(chi^2 0-d tensor, d chi^2 / d [PA, dRA, dDec, inc] as a float64 tensor [4]);
+        the inclination derivative goes through the swept image."""
+        self._chk(I, "I")
+        c2 = torch.empty((), dtype=torch.float64, device=self.device)
+        g = torch.empty(4, dtype=torch.float64, device=self.device)
+        wsb = self._geo_ws(Nxy, ws)
+        with torch.cuda.device(self.device):
+            check(getattr(_lib(), "gal_chi2Profile_geograd_ds" + _sfx(self.dtype))(
+                self._h, _ptr(I), I.numel(), float(Rmin), float(dR), int(Nxy), float(dxy),
+                float(inc), float(PA), float(dRA), float(dDec), _ptr(c2), _ptr(g), _ptr(wsb),
+                wsb.numel(), _stream(self.device)), "Dataset.chi2Profile_geograd")
+        return c2, g
+
     def sampleImage(self, image, dxy, PA=0.0, dRA=0.0, dDec=0.0, inc=0.0,
                     ws: Workspace | None = None):
         self._chk(image, "image")
@@ -544,8 +580,8 @@ def batch_exec(jobs, grads=None, out: torch.Tensor | None = None,
                 _arr(g, "grad", j["ds"].dtype, dev, j["model"].numel())
                 gp[i] = g.data_ptr()
     need = _lib().gal_batch_exec_workspace_bytes(arr, len(jobs), gp)
-    if need == 0:
-        raise GalarioError(-2, "batch_exec plan")
+    if need == 0:  # the plan failed; gal_last_error says why
+        raise GalarioError(_native.GAL_ERR_SIZE, "batch_exec plan")
     if ws is None:
         key = dev.index if dev.index is not None else torch.cuda.current_device()
         ws = _exec_ws.setdefault(key, Workspace(torch.device("cuda", key), torch.float64))

@@ -12,6 +12,7 @@ HERE = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.path.join(HERE, "libgalario_hip.so")
 
 GAL_OK = 0
+GAL_ERR_SIZE = -2
 ERRORS = {
     -1: "GAL_ERR_NULL",
     -2: "GAL_ERR_SIZE",
@@ -59,6 +60,10 @@ _SIG = {
                                  P]),
     "gal_chi2Image_grad_ds": (I, [P, P, I, D, D, D, D, D, P, P, P, SZ, P]),
     "gal_chi2Profile_grad_ds": (I, [P, P, I, D, D, I, D, D, D, D, D, P, P, P, SZ, P]),
+    "gal_geograd_workspace_bytes_d": (SZ, [I, I64]),
+    "gal_geograd_workspace_bytes_f": (SZ, [I, I64]),
+    "gal_chi2Image_geograd_ds": (I, [P, P, I, D, D, D, D, D, P, P, P, SZ, P]),
+    "gal_chi2Profile_geograd_ds": (I, [P, P, I, D, D, I, D, D, D, D, D, P, P, P, SZ, P]),
     "gal_batch_create": (I, [P, I, ctypes.POINTER(P)]),
     "gal_batch_workspace_bytes": (SZ, [P]),
     "gal_batch_info": (I, [P, ctypes.POINTER(I), ctypes.POINTER(I), ctypes.POINTER(I)]),
@@ -79,6 +84,7 @@ _PRECISION_SUFFIXED = {
     "gal_spectrum", "gal_sample_spectrum", "gal_dataset_create", "gal_chi2Image_ds",
     "gal_chi2Profile_ds", "gal_sampleImage_ds", "gal_sampleProfile_ds", "gal_autotune",
     "gal_chi2Image_grad", "gal_chi2Profile_grad", "gal_chi2Image_grad_ds", "gal_chi2Profile_grad_ds",
+    "gal_chi2Image_geograd_ds", "gal_chi2Profile_geograd_ds",
 }
 
 

@@ -20,6 +20,7 @@
 #include "../../include/galario_hip.h"
 #include "adjoint.h"
 #include "batch.h"
+#include "geograd.h"
 #include "kernels.h"
 
 namespace gal {
@@ -459,6 +460,7 @@ static SweepArgs make_sweep(int Nr, double Rmin, double dR, double dxy, double i
     a.inv_cos = 1.0 / std::cos(inc);
     a.pix_area = dxy * dxy;
     a.tmax = (double)(Nr - 1);
+    a.tan_inc = std::tan(inc);
     return a;
 }
 
@@ -663,6 +665,87 @@ static int grad_path(const T *src, bool profile, const SweepArgs &sw, const Geom
     if (profile)
         rc = launch("k_sum_bins", k_sum_bins<T>, dim3((Nr + 255) / 256), dim3(256), s, gI, Nr, grad);
     return rc;
+}
+
+// ---------------------------------------------------------------------------
+// geometry gradient: chi^2 and d chi^2 / d (PA, dRA, dDec, inc)
+template <typename T, int N>
+static int rows_tangent_n(const FftJob<T> &j) {
+    constexpr int B = cols_B(N);
+    using C = CfgE<T, N, B, 8>;
+    const int pairs = N / 4 + 1;
+    return launch("k_rows_sym_dinc", k_rows_sym<T, C, true>, dim3((pairs + B - 1) / B), dim3(C::NT),
+                  j.s, j.src, j.sw, j.g, j.Qe, j.buf);
+}
+
+// the real spectrum of d image / d inc of a swept profile (same passes)
+template <typename T>
+static int transform_tangent(const T *I, const SweepArgs &sw, const Geom &g, void *buf,
+                             hipStream_t s) {
+    FftJob<T> j{I, sw, g, (g.Q + 1) & ~1, buf, s};
+    j.g.CS = g.N / 2 + 2;
+    int rc;
+    switch (g.N) {
+        case 16: rc = rows_tangent_n<T, 16>(j); break;
+        case 32: rc = rows_tangent_n<T, 32>(j); break;
+        case 64: rc = rows_tangent_n<T, 64>(j); break;
+        case 128: rc = rows_tangent_n<T, 128>(j); break;
+        case 256: rc = rows_tangent_n<T, 256>(j); break;
+        case 512: rc = rows_tangent_n<T, 512>(j); break;
+        case 1024: rc = rows_tangent_n<T, 1024>(j); break;
+        case 2048: rc = rows_tangent_n<T, 2048>(j); break;
+        case 4096: rc = rows_tangent_n<T, 4096>(j); break;
+        case 8192: rc = rows_tangent_n<T, 8192>(j); break;
+        default: return fail(GAL_ERR_SIZE, "Nxy=%d unsupported", g.N);
+    }
+    if (rc) return rc;
+    return run_fft<T>(K_COLS_SYM, j);
+}
+
+// [control 256][GEO_N x partials][spectrum][tangent spectrum]
+template <typename T>
+static size_t geo_ws_bytes(int N, int64_t M) {
+    const size_t xt = align256((size_t)(N / 2 + 1) * (size_t)(N + 2) * sizeof(c2<T>));
+    return 256 + align256((size_t)GEO_N * sample_blocks(M) * sizeof(double)) + 2 * xt;
+}
+
+template <typename T>
+static int geograd_path(const T *src, bool profile, const SweepArgs &sw, const Geom &g, double dxy,
+                        const Obs<T> &o, double PA, double dRA, double dDec, double inc,
+                        double *chi2, double *dgeo, void *ws, size_t ws_bytes_, hipStream_t s) {
+    int rc = ensure_init();
+    if (rc) return rc;
+    if (!ws) return fail(GAL_ERR_NULL, "workspace is NULL");
+    const size_t need = geo_ws_bytes<T>(g.N, o.M);
+    if (ws_bytes_ < need)
+        return fail(GAL_ERR_WORKSPACE, "workspace of %zu bytes, need %zu", ws_bytes_, need);
+    if (((uintptr_t)ws & 255) != 0) return fail(GAL_ERR_WORKSPACE, "workspace not 256-byte aligned");
+    const int64_t nblk = sample_blocks(o.M);
+    char *p = (char *)ws;
+    Control *ctl = (Control *)p;
+    double *partials = (double *)(p + 256);
+    const size_t xt = align256((size_t)(g.N / 2 + 1) * (size_t)(g.N + 2) * sizeof(c2<T>));
+    void *S = p + 256 + align256((size_t)GEO_N * nblk * sizeof(double));
+    void *St = (char *)S + xt;
+    Geom gs;
+    rc = transform<T>(src, profile, sw, g, S, s, gs);
+    if (rc) return rc;
+    if (profile) {
+        rc = transform_tangent<T>(src, sw, g, St, s);
+        if (rc) return rc;
+    }
+    const SampleArgs sa = make_sample(g, o.M, dxy, PA, dRA, dDec, profile ? 0.0 : inc);
+    const double sinc = profile ? 0.0 : std::sin(inc);
+    const dim3 grid((unsigned)nblk), blk(SAMPLE_NT);
+    if (profile)
+        rc = launch("k_sample_geo_sym", k_sample_geo<T, true>, grid, blk, s, (const T *)S,
+                    (const T *)St, gs, sa, sinc, o.u, o.v, o.re, o.im, o.w, partials, ctl);
+    else
+        rc = launch("k_sample_geo", k_sample_geo<T, false>, grid, blk, s, (const T *)S,
+                    (const T *)nullptr, gs, sa, sinc, o.u, o.v, o.re, o.im, o.w, partials, ctl);
+    if (rc) return rc;
+    return launch("k_reduce_geo", k_reduce_geo, dim3(GEO_N), dim3(REDUCE_NT), s, partials,
+                  (int)nblk, chi2, dgeo);
 }
 
 // ---------------------------------------------------------------------------
@@ -1059,8 +1142,10 @@ static int dataset_create(const T *u, const T *v, const T *re, const T *im, cons
     if (M < 0) return fail(GAL_ERR_SIZE, "M < 0");
     if (M > (int64_t)0x7fffffff) return fail(GAL_ERR_SIZE, "M above 2^31 - 1");
     if (M > 0 && (!u || !v)) return fail(GAL_ERR_NULL, "NULL u or v");
-    const bool has_obs = re && im && w;
-    if ((re || im || w) && !has_obs) return fail(GAL_ERR_NULL, "re, im, w: give all or none");
+    // an empty dataset holds (no) observations whatever the pointers are: its
+    // chi^2 is 0 (empty arrays may come with NULL pointers)
+    const bool has_obs = (re && im && w) || M == 0;
+    if (M > 0 && (re || im || w) && !has_obs) return fail(GAL_ERR_NULL, "re, im, w: give all or none");
     int rc = ensure_init();
     if (rc) return rc;
     hipStream_t s = (hipStream_t)stream;
@@ -1366,6 +1451,54 @@ GAL_IMAGE_GRAD_DS(f, float)
     }
 GAL_PROFILE_GRAD_DS(d, double)
 GAL_PROFILE_GRAD_DS(f, float)
+
+size_t gal_geograd_workspace_bytes_d(int Nxy, int64_t M) {
+    if (!pow2_in_range(Nxy) || M < 0) return 0;
+    return geo_ws_bytes<double>(Nxy, M);
+}
+size_t gal_geograd_workspace_bytes_f(int Nxy, int64_t M) {
+    if (!pow2_in_range(Nxy) || M < 0) return 0;
+    return geo_ws_bytes<float>(Nxy, M);
+}
+
+#define GAL_IMAGE_GEOGRAD_DS(SFX, T)                                                            \
+    int gal_chi2Image_geograd_ds_##SFX(const gal_dataset *ds, const T *image, int Nxy,          \
+                                       double dxy, double PA, double dRA, double dDec,          \
+                                       double inc, double *chi2, double *dgeo, void *ws,        \
+                                       size_t ws_bytes_, void *stream) {                        \
+        Geom g;                                                                                 \
+        Obs<T> o;                                                                               \
+        int rc = ds_grad<T>(ds, Nxy, dxy, g, o);                                                \
+        if (rc) return rc;                                                                      \
+        if (!image || !chi2 || !dgeo) return fail(GAL_ERR_NULL, "NULL array");                  \
+        rc = check_image_scalars(Nxy, dxy, PA, dRA, dDec, inc);                                 \
+        if (rc) return rc;                                                                      \
+        return geograd_path<T>(image, false, SweepArgs{}, g, dxy, o, PA, dRA, dDec, inc, chi2,  \
+                               dgeo, ws, ws_bytes_, (hipStream_t)stream);                       \
+    }
+GAL_IMAGE_GEOGRAD_DS(d, double)
+GAL_IMAGE_GEOGRAD_DS(f, float)
+
+#define GAL_PROFILE_GEOGRAD_DS(SFX, T)                                                          \
+    int gal_chi2Profile_geograd_ds_##SFX(const gal_dataset *ds, const T *I, int Nr,             \
+                                         double Rmin, double dR, int Nxy, double dxy,           \
+                                         double inc, double PA, double dRA, double dDec,        \
+                                         double *chi2, double *dgeo, void *ws,                  \
+                                         size_t ws_bytes_, void *stream) {                      \
+        Geom g;                                                                                 \
+        Obs<T> o;                                                                               \
+        int rc = ds_grad<T>(ds, Nxy, dxy, g, o);                                                \
+        if (rc) return rc;                                                                      \
+        if (!I || !chi2 || !dgeo) return fail(GAL_ERR_NULL, "NULL array");                      \
+        rc = check_image_scalars(Nxy, dxy, PA, dRA, dDec, inc);                                 \
+        if (rc) return rc;                                                                      \
+        rc = check_profile(Nr, Rmin, dR);                                                       \
+        if (rc) return rc;                                                                      \
+        return geograd_path<T>(I, true, make_sweep(Nr, Rmin, dR, dxy, inc), g, dxy, o, PA, dRA, \
+                               dDec, inc, chi2, dgeo, ws, ws_bytes_, (hipStream_t)stream);      \
+    }
+GAL_PROFILE_GEOGRAD_DS(d, double)
+GAL_PROFILE_GEOGRAD_DS(f, float)
 
 // ---- batches --------------------------------------------------------------
 // Plan a job list: checks, geometry, sample groups (same dataset, kind and

@@ -81,6 +81,7 @@ struct Geom {
 struct SweepArgs {
     int Nr;
     double Rmin, inv_dR, dxy, inv_cos, pix_area, tmax;
+    double tan_inc;  // used by the inclination derivative of the sweep only
 };
 
 // Square root of a squared pixel radius: x is a normal number well above
@@ -117,6 +118,27 @@ __device__ __forceinline__ double sweep_pixel(PI I, int N, int r, int c, const S
         j = j < a.Nr - 2 ? j : a.Nr - 2;
         const double f = t - (double)j;
         return ((1.0 - f) * (double)I[j] + f * (double)I[j + 1]) * a.pix_area;
+    }
+    return 0.0;
+}
+
+// d pixel / d inc of the sweep (not in the paper): on the segment that
+// sweep_pixel interpolates, (I[j+1] - I[j]) / dR times d rho / d inc =
+// (x / cos inc)^2 tan(inc) / rho, times dxy^2; 0 outside the profile and at
+// the centre pixel (its extrapolated value does not depend on inc).
+template <typename PI>
+__device__ __forceinline__ double sweep_pixel_dinc(PI I, int N, int r, int c, const SweepArgs &a) {
+    if (r == N / 2 && c == N / 2) return 0.0;
+    const double x = (double)(N / 2 - c) * a.dxy;
+    const double y = (double)(N / 2 - r) * a.dxy;
+    const double xs = x * a.inv_cos;
+    const double rho = sqrt_pos(xs * xs + y * y);
+    const double t = (rho - a.Rmin) * a.inv_dR;
+    if (t >= 0.0 && t <= a.tmax) {
+        int j = (int)t;
+        j = j < a.Nr - 2 ? j : a.Nr - 2;
+        return ((double)I[j + 1] - (double)I[j]) * a.inv_dR * (xs * xs * a.tan_inc / rho) *
+               a.pix_area;
     }
     return 0.0;
 }
@@ -239,7 +261,8 @@ __global__ __launch_bounds__(Cfg::NT) void k_cols(Geom g, c2<T> *__restrict__ XT
 // Row pass: pair m holds rows 2m and 2m+1; output XR[q * CS + r] (real,
 // shift sign (-1)^q) for r in [0, N/2], q in [0, Qe) (Qe = Q rounded up to
 // even so that the column pass can pair columns).
-template <typename T, typename Cfg, typename PI = const T *__restrict__>
+// TANGENT: the image swept is d image / d inc (sweep_pixel_dinc)
+template <typename T, typename Cfg, typename PI = const T *__restrict__, bool TANGENT = false>
 __device__ __forceinline__ void rows_sym_body(PI I, const SweepArgs &sw, const Geom &g, int Qe,
                                               T *__restrict__ XR, int blk) {
     constexpr int L = Cfg::L, B = Cfg::B, NT = Cfg::NT, E = Cfg::E;
@@ -255,8 +278,12 @@ __device__ __forceinline__ void rows_sym_body(PI I, const SweepArgs &sw, const G
     for (int idx = tid; idx < B * NH; idx += NT) {
         const int b = idx / NH, c = idx % NH;
         const int r = 2 * (m0 + b);  // rows r, r + 1 (r + 1 < N)
-        lds[Cfg::at(b, c)] = c2<T>{(T)sweep_pixel(I, N, r, c, sw),
-                                   (T)sweep_pixel(I, N, r + 1, c, sw)};
+        if constexpr (TANGENT)
+            lds[Cfg::at(b, c)] = c2<T>{(T)sweep_pixel_dinc(I, N, r, c, sw),
+                                       (T)sweep_pixel_dinc(I, N, r + 1, c, sw)};
+        else
+            lds[Cfg::at(b, c)] = c2<T>{(T)sweep_pixel(I, N, r, c, sw),
+                                       (T)sweep_pixel(I, N, r + 1, c, sw)};
     }
     __syncthreads();
     c2<T> v[E];
@@ -285,10 +312,11 @@ __device__ __forceinline__ void rows_sym_body(PI I, const SweepArgs &sw, const G
     });
 }
 
-template <typename T, typename Cfg>
+template <typename T, typename Cfg, bool TANGENT = false>
 __global__ __launch_bounds__(Cfg::NT) void k_rows_sym(const T *__restrict__ I, SweepArgs sw,
                                                       Geom g, int Qe, T *__restrict__ XR) {
-    rows_sym_body<T, Cfg>(I, sw, g, Qe, XR, xcd_remap(blockIdx.x, gridDim.x));
+    rows_sym_body<T, Cfg, const T *__restrict__, TANGENT>(I, sw, g, Qe, XR,
+                                                          xcd_remap(blockIdx.x, gridDim.x));
 }
 
 // Column pass of a swept profile, in place: pair of columns (2m, 2m+1),
