@@ -304,6 +304,10 @@ def main():
     ms_grad = _timed(grad_call, args.grad_steps, args.warmup, torch)
     kern_grad = _kernel_times(gal, grad_call, max(args.grad_steps // 3, 20), torch)
 
+    # ---- plain geometry gradient: chi^2 and d chi^2 / d (PA, dRA, dDec, inc) ----
+    geo_call = lambda: ds.chi2Profile_geograd(I, case.Rmin, case.dR, N, case.dxy, **geo)
+    ms_geo = _timed(geo_call, args.grad_steps, args.warmup, torch)
+
     # ---- batched: K walkers (different profiles and geometry) per step ----
     K = args.batch
     rng = np.random.default_rng(1102)
@@ -457,7 +461,10 @@ def main():
                            "ms_per_eval": round(ms_grad, 5), "kernels": rnd(kern_grad)},
                  "batched": {"value": round(K * 1e3 / ms_bgrad, 1), "unit": "chi2+grad evals/s",
                              "ms_per_step": round(ms_bgrad, 5), "batch": K,
-                             "form": "one gal_batch_exec call per step (planned at the call)"}},
+                             "form": "one gal_batch_exec call per step (planned at the call)"},
+                 "geometry_plain": {"value": round(1e3 / ms_geo, 1),
+                                    "unit": "chi2 + d/d(PA, dRA, dDec, inc) evals/s",
+                                    "ms_per_eval": round(ms_geo, 5)}},
         "path_roofline": path_roofline,
         "served": served,
         "kernels": rnd(kern),
