@@ -23,6 +23,8 @@ Functions and the passages they follow:
   sample_direct  as sample_grid with every node from ``grid_cell``
   chi2           Sec. 3.1, Eq. def.chi.square
   grad_image / grad_profile   transpose of the above (not in the paper)
+  sample_sources / chi2_sources / grad_sources   Sec. 3.2 (a field of several
+                 sources is the sum of their visibilities), on the above
 """
 from __future__ import annotations
 
@@ -241,3 +243,75 @@ def geograd_profile(I, Rmin, dR, Nxy, dxy, u, v, re, im, w, inc=0.0, PA=0.0, dRA
     G = grid(sweep(I, Rmin, dR, Nxy, dxy, inc))
     Gt = grid(sweep_dinc(I, Rmin, dR, Nxy, dxy, inc))
     return _geograd(G, Gt, Nxy, dxy, u, v, re, im, w, PA, dRA, dDec, inc)
+
+
+def _resolve(sources):
+    """Source dicts with every shared spectrum spelled out: a source with
+    "share": k uses the model of source k, and for a profile also its Rmin, dR,
+    Nxy, dxy and inc (those make the transform); its PA and offsets (and inc,
+    for an image) stay its own."""
+    out = []
+    for s in sources:
+        k = s.get("share")
+        if k is None:
+            out.append(s)
+            continue
+        o = sources[k]
+        r = dict(s)
+        keys = ("image", "dxy") if s["kind"] == "image" else ("I", "Rmin", "dR", "Nxy", "dxy", "inc")
+        for key in keys:
+            r[key] = o[key]
+        out.append(r)
+    return out
+
+
+def _vis_one(s, u, v):
+    if s["kind"] == "image":
+        return sampleImage(s["image"], s["dxy"], u, v, s.get("PA", 0.0), s.get("dRA", 0.0),
+                           s.get("dDec", 0.0), s.get("inc", 0.0))
+    return sampleProfile(s["I"], s["Rmin"], s["dR"], s["Nxy"], s["dxy"], u, v, s.get("inc", 0.0),
+                         s.get("PA", 0.0), s.get("dRA", 0.0), s.get("dDec", 0.0))
+
+
+def sample_sources(sources, u, v) -> np.ndarray:
+    """Visibilities of a field of several sources (Sec. 3.2: the sources'
+    visibilities add up, each source placed by its own phase shift).
+    ``sources``: dicts {"kind": "image", "image", "dxy", PA, dRA, dDec, inc}
+    or {"kind": "profile", "I", "Rmin", "dR", "Nxy", "dxy", inc, PA, dRA,
+    dDec} (geometry keys default to 0), optionally "share": k (see _resolve)."""
+    V = np.zeros(np.size(u), dtype=np.complex128)
+    for s in _resolve(sources):
+        V += _vis_one(s, u, v)
+    return V
+
+
+def chi2_sources(sources, u, v, re, im, w) -> float:
+    """chi^2 of the summed model (Eq. def.chi.square on sample_sources)."""
+    return chi2(sample_sources(sources, u, v), re, im, w)
+
+
+def grad_sources(sources, u, v, re, im, w):
+    """(chi2, [d chi2 / d model of each source]) of the summed model.  With the
+    other sources' visibilities moved to the observations, chi^2 is that of
+    one source, so each gradient is grad_image / grad_profile against
+    obs - V_others.  A source with "share" gets None: by the chain rule its
+    gradient is added into the owner's."""
+    res = _resolve(sources)
+    Vs = [_vis_one(s, u, v) for s in res]
+    V = np.sum(Vs, axis=0)
+    c2 = chi2(V, re, im, w)
+    grads = [None] * len(sources)
+    for i, s in enumerate(res):
+        Vo = V - Vs[i]
+        r_i, i_i = np.asarray(re) - Vo.real, np.asarray(im) - Vo.imag
+        if s["kind"] == "image":
+            _, g = grad_image(s["image"], s["dxy"], u, v, r_i, i_i, w, s.get("PA", 0.0),
+                              s.get("dRA", 0.0), s.get("dDec", 0.0), s.get("inc", 0.0))
+        else:
+            _, g = grad_profile(s["I"], s["Rmin"], s["dR"], s["Nxy"], s["dxy"], u, v, r_i, i_i, w,
+                                s.get("inc", 0.0), s.get("PA", 0.0), s.get("dRA", 0.0),
+                                s.get("dDec", 0.0))
+        owner = sources[i].get("share")
+        owner = i if owner is None else owner
+        grads[owner] = g if grads[owner] is None else grads[owner] + g
+    return c2, grads

@@ -479,3 +479,84 @@ def test_geograd_matches_central_differences(kind):
             return f(**kw)
         fd = _central(fk, base[name], steps[name])
         assert abs(g[k] - fd) <= 1e-5 * max(abs(fd), 1e-3 * c2), (name, g[k], fd)
+
+
+# ---- several sources (Sec. 3.2) ---------------------------------------------
+def test_sources_sum_is_the_transform_of_the_summed_image():
+    # sampling is linear in the image: two sources with the same grid and
+    # geometry give the visibilities of their summed image
+    a = wl.random_case(32, 400, seed=3400)
+    b = wl.random_case(32, 400, seed=3401)
+    geo = dict(PA=a.PA, dRA=a.dRA, dDec=a.dDec, inc=0.3)
+    src = [dict(kind="image", image=a.image, dxy=a.dxy, **geo),
+           dict(kind="image", image=b.image, dxy=a.dxy, **geo)]
+    Vs = oracle.sample_sources(src, a.u, a.v)
+    Vsum = oracle.sampleImage(a.image + b.image, a.dxy, a.u, a.v, **geo)
+    assert np.max(np.abs(Vs - Vsum)) <= 1e-12 * np.max(np.abs(Vsum))
+    # a point source moved by (dRA, dDec) is the centred one times its phase ramp
+    N = 32
+    delta = np.zeros((N, N))
+    delta[N // 2, N // 2] = 1.0
+    V1 = oracle.sample_sources([dict(kind="image", image=delta, dxy=a.dxy, PA=0.0, dRA=2e-7,
+                                     dDec=-1e-7, inc=0.0)], a.u, a.v)
+    assert np.allclose(V1, np.exp(2j * np.pi * (a.u * 2e-7 - a.v * 1e-7)), rtol=0, atol=1e-13)
+
+
+def test_sources_sharing_spells_out_the_owner():
+    # a source that shares its owner's spectrum with the owner's geometry
+    # doubles the owner (image: any inc; profile: the owner's inc applies)
+    a = wl.random_case(32, 300, seed=3410)
+    img = dict(kind="image", image=a.image, dxy=a.dxy, PA=0.4, dRA=a.dRA, dDec=a.dDec, inc=0.5)
+    V = oracle.sample_sources([img, dict(img, image=None, share=0)], a.u, a.v)
+    V2 = oracle.sampleImage(2.0 * a.image, a.dxy, a.u, a.v, 0.4, a.dRA, a.dDec, 0.5)
+    assert np.max(np.abs(V - V2)) <= 1e-12 * np.max(np.abs(V2))
+    p = wl.random_case(32, 300, seed=3411, kind="profile")
+    prof = dict(kind="profile", I=p.I, Rmin=p.Rmin, dR=p.dR, Nxy=p.N, dxy=p.dxy, inc=0.6, PA=0.2,
+                dRA=0.0, dDec=0.0)
+    # the sharer's own inc is not used: the transform is the owner's
+    sharer = dict(kind="profile", I=None, Rmin=None, dR=None, Nxy=None, dxy=None, inc=1.2, PA=0.2,
+                  dRA=3 * p.dxy, dDec=0.0, share=0)
+    V = oracle.sample_sources([prof, sharer], p.u, p.v)
+    V0 = oracle.sampleProfile(p.I, p.Rmin, p.dR, p.N, p.dxy, p.u, p.v, 0.6, 0.2, 0.0, 0.0)
+    ramp = np.exp(2j * np.pi * p.u * 3 * p.dxy)
+    assert np.max(np.abs(V - V0 * (1.0 + ramp))) <= 1e-12 * np.max(np.abs(V0))
+
+
+def test_grad_sources_matches_central_differences():
+    # a scene of an image, a profile and a copy of the profile elsewhere:
+    # every gradient entry (the owner's including its copy) against central
+    # differences of chi2_sources
+    a = wl.random_case(16, 120, seed=3420)
+    p = wl.random_case(16, 120, seed=3421, kind="profile", Nr=10)
+    p.I[:] = p.I / np.max(p.I) * np.max(np.abs(a.image)) / p.dxy ** 2 * 0.3
+    src = [dict(kind="image", image=a.image, dxy=a.dxy, PA=0.3, dRA=a.dRA, dDec=a.dDec, inc=0.4),
+           dict(kind="profile", I=p.I, Rmin=p.Rmin, dR=p.dR, Nxy=16, dxy=a.dxy, inc=0.5, PA=1.0,
+                dRA=0.0, dDec=0.0),
+           dict(kind="profile", I=None, PA=2.0, dRA=2 * a.dxy, dDec=-a.dxy, share=1)]
+    V = oracle.sample_sources(src, a.u, a.v)
+    re, im = 1.1 * V.real + a.noise_re, 0.9 * V.imag + a.noise_im
+    c2, g = oracle.grad_sources(src, a.u, a.v, re, im, a.w)
+    assert g[2] is None and g[0].shape == a.image.shape and g[1].shape == p.I.shape
+    assert abs(c2 - oracle.chi2_sources(src, a.u, a.v, re, im, a.w)) <= 1e-13 * c2
+
+    def f_img(k, h):
+        x = a.image.copy()
+        x.flat[k] += h
+        s = [dict(src[0], image=x), src[1], src[2]]
+        return oracle.chi2_sources(s, a.u, a.v, re, im, a.w)
+
+    def f_prof(k, h):
+        x = p.I.copy()
+        x[k] += h
+        s = [src[0], dict(src[1], I=x), src[2]]
+        return oracle.chi2_sources(s, a.u, a.v, re, im, a.w)
+
+    rng = np.random.default_rng(3422)
+    hi = 1e-4 * np.max(np.abs(a.image))
+    for k in rng.choice(a.image.size, 12, replace=False):
+        fd = (f_img(k, hi) - f_img(k, -hi)) / (2 * hi)
+        assert abs(g[0].flat[k] - fd) <= 1e-6 * np.max(np.abs(g[0])), (k, g[0].flat[k], fd)
+    hp = 1e-4 * np.max(p.I)
+    for k in range(p.I.size):
+        fd = (f_prof(k, hp) - f_prof(k, -hp)) / (2 * hp)
+        assert abs(g[1][k] - fd) <= 1e-6 * np.max(np.abs(g[1])), (k, g[1][k], fd)
