@@ -291,15 +291,32 @@ int gal_chi2Profile_geograd_ds_f(const gal_dataset *ds, const float *I, int Nr, 
 /* ---- batches: many chi^2 evaluations per launch --------------------------
  * A batch is a fixed list of jobs, planned once.  Jobs with the same
  * precision, kind and image size share the FFT launches; jobs on the same
- * dataset, kind and image grid (up to 16 per group) share one pass over the
- * observations, which are then read once for the whole group (the typical
- * case: the walkers of an MCMC ensemble).  At execution the kernels read the
- * current model arrays and geometry from the device pointers in the jobs, so
- * a plan -- and a HIP graph captured from gal_batch_chi2 -- is reused while
- * the caller rewrites those buffers between executions.  The geometry is not
- * checked at execution: cos(inc) <= 0 or dR <= 0 give a NaN chi^2 for that
- * job.  Creation checks everything else (like the dataset calls), allocates
- * the batch's device table and synchronises the device. */
+ * dataset with the same kind and image grid (up to 16 per group) share one
+ * pass over the observations, which are then read once for the whole group
+ * (the typical case: the walkers of an MCMC ensemble).  At execution the
+ * kernels read the current model arrays and geometry from the device pointers
+ * in the jobs, so a plan -- and a HIP graph captured from gal_batch_chi2 -- is
+ * reused while the caller rewrites those buffers between executions.  The
+ * geometry is not checked at execution: cos(inc) <= 0 or dR <= 0 give a NaN
+ * chi^2 for that job.  Creation checks everything else (like the dataset
+ * calls), allocates the batch's device table and synchronises the device.
+ *
+ * Scenes (Sec. 3.2: a field of several sources is the sum of the sources'
+ * visibilities, each placed by its own phase shift).  Jobs with the same
+ * nonzero `scene` are the sources of one model: they must use the same
+ * dataset and may differ in kind, image size, pixel size and geometry.  The
+ * sampling pass sums their visibilities at every point before the residual;
+ * chi2[j] of every member is the scene's chi^2, and a member's gradient is
+ * d chi^2(scene) / d model of that member.  A member with share = k + 1 reads
+ * the spectrum of member k of its scene (same kind, Nxy, dxy) instead of
+ * transforming its own model (which may then be NULL): an identical source
+ * placed elsewhere costs one more gather and no FFT.  Only its PA, dRA and
+ * dDec (and inc, for an image) act; a profile's Rmin, dR and inc are the
+ * owner's, being part of the transform.  A sharing job has no gradient
+ * output of its own: its part of the gradient is added into the owner's.
+ * Datasets without observations (gal_dataset_create_* with re, im, w NULL)
+ * are accepted for jobs without gradient: their chi^2 is 0 and `vis` gives
+ * the visibilities. */
 #define GAL_JOB_IMAGE   0
 #define GAL_JOB_PROFILE 1
 typedef struct {
@@ -310,6 +327,11 @@ typedef struct {
     int Nr;                 /* profile samples (profile jobs) */
     const void *model;      /* device: image [Nxy*Nxy] or profile [Nr], dataset precision */
     const double *geo;      /* device: {Rmin, dR, inc, PA, dRA, dDec}; Rmin, dR unused for images */
+    int scene;              /* 0: the job alone; > 0: the scene it is a source of */
+    int share;              /* 0: own spectrum; k + 1: the spectrum of job k (same scene) */
+    void *vis;              /* device, nullable: the scene's model visibilities at the
+                               dataset's points in registration order, interleaved
+                               (re, im) [2M], dataset precision; written at execution */
 } gal_job;
 typedef struct gal_batch gal_batch;
 int gal_batch_create(const gal_job *jobs, int n, gal_batch **out);

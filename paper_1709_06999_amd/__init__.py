@@ -449,6 +449,58 @@ class Dataset:
                 wsb.numel(), _stream(self.device)), "Dataset.chi2Profile_geograd")
         return c2, g
 
+    def _scene_jobs(self, sources):
+        """Jobs of one scene from source dicts: kind ("image" / "profile" or
+        JOB_*), model (image [Nxy, Nxy] or profile [Nr]; None with share),
+        dxy, Nxy (profiles, and sharing images), Rmin, dR (profiles), inc,
+        PA, dRA, dDec (default 0), share (index of the source whose spectrum
+        this one reads)."""
+        if not sources:
+            raise ValueError("a scene needs at least one source")
+        jobs = []
+        for k, s in enumerate(sources):
+            kind = s["kind"]
+            kind = {"image": JOB_IMAGE, "profile": JOB_PROFILE}.get(kind, kind)
+            if kind not in (JOB_IMAGE, JOB_PROFILE):
+                raise ValueError(f"source {k}: kind must be 'image' or 'profile'")
+            m = s.get("model")
+            if kind == JOB_IMAGE and m is not None:
+                N = m.shape[0]
+            else:
+                N = s.get("Nxy")
+                if N is None and s.get("share") is not None:
+                    N = sources[s["share"]].get("Nxy") or sources[s["share"]]["model"].shape[0]
+            geo = torch.tensor([float(s.get(key, 0.0)) for key in
+                                ("Rmin", "dR", "inc", "PA", "dRA", "dDec")],
+                               dtype=torch.float64, device=self.device)
+            jobs.append({"ds": self, "kind": kind, "Nxy": int(N), "dxy": float(s["dxy"]),
+                         "model": m, "geo": geo, "scene": 1, "share": s.get("share")})
+        return jobs
+
+    def sampleSources(self, sources, ws: Workspace | None = None):
+        """Model visibilities (complex [M]) of a field of several sources:
+        the sum of each source's visibilities, each placed and oriented by its
+        own geometry (one sampling pass; sources that share a spectrum are
+        transformed once)."""
+        jobs = self._scene_jobs(sources)
+        vis = torch.empty(self.M, dtype=_COMPLEX[self.dtype], device=self.device)
+        jobs[0]["vis"] = vis
+        batch_exec(jobs, ws=ws)
+        return vis
+
+    def chi2Sources(self, sources, grad: bool = False, ws: Workspace | None = None):
+        """chi^2 (0-d tensor) of the field of several sources against the
+        observations; with grad=True also a list with d chi^2 / d model of
+        every source that owns a model (None for sources that share one: their
+        part is in the owner's)."""
+        jobs = self._scene_jobs(sources)
+        grads = None
+        if grad:
+            grads = [torch.empty_like(j["model"]) if j["model"] is not None else None
+                     for j in jobs]
+        c2 = batch_exec(jobs, grads, ws=ws)[0]
+        return (c2, grads) if grad else c2
+
     def sampleImage(self, image, dxy, PA=0.0, dRA=0.0, dDec=0.0, inc=0.0,
                     ws: Workspace | None = None):
         self._chk(image, "image")
@@ -475,18 +527,35 @@ class Dataset:
 
 
 # ----------------------------------------------------------------------------
+_COMPLEX = {torch.float64: torch.complex128, torch.float32: torch.complex64}
+
+
 def _job_array(jobs, dev: torch.device):
+    """gal_job array of job dicts: ds, kind, Nxy, dxy, model, geo and the
+    optional scene (int, 0 = alone), share (index of the job whose spectrum
+    this one reads, or None) and vis (complex tensor [M] for the scene's
+    visibilities)."""
     arr = (_native.GalJob * len(jobs))()
     for i, j in enumerate(jobs):
         ds = j["ds"]
         if ds.device != dev:
             raise ValueError(f"job {i}: dataset on {ds.device}, expected {dev}")
-        m, geo = j["model"], j["geo"]
-        _arr(m, "model", ds.dtype, dev)
+        m, geo = j.get("model"), j["geo"]
+        share = j.get("share")
+        share = 0 if share is None else int(share) + 1
+        if m is None and not share:
+            raise ValueError(f"job {i}: a model is needed unless the job shares a spectrum")
+        if m is not None:
+            _arr(m, "model", ds.dtype, dev)
         _arr(geo, "geo", torch.float64, dev, 6)
-        arr[i] = _native.GalJob(ds._h.value, int(j["kind"]), int(j["Nxy"]), float(j["dxy"]),
-                                int(m.numel()) if j["kind"] == JOB_PROFILE else 0,
-                                m.data_ptr(), geo.data_ptr())
+        vis = j.get("vis")
+        if vis is not None:
+            _arr(vis, "vis", _COMPLEX[ds.dtype], dev, ds.M)
+        nr = int(m.numel()) if (m is not None and j["kind"] == JOB_PROFILE) else 0
+        arr[i] = _native.GalJob(ds._h.value, int(j["kind"]), int(j["Nxy"]), float(j["dxy"]), nr,
+                                m.data_ptr() if m is not None else None, geo.data_ptr(),
+                                int(j.get("scene", 0)), share,
+                                vis.data_ptr() if vis is not None else None)
     return arr
 
 
@@ -496,9 +565,14 @@ class Batch:
     ``jobs`` is a list of dicts with keys: ds (Dataset), kind (JOB_IMAGE or
     JOB_PROFILE), Nxy, dxy, model (device tensor: image [Nxy, Nxy] or
     profile [Nr]) and geo (device float64 tensor of 6 values: Rmin, dR, inc,
-    PA, dRA, dDec).  The kernels read model and geo at every ``chi2()`` call,
-    so update those tensors in place between calls; the plan (and any HIP
-    graph captured around ``chi2``) stays valid as long as they live."""
+    PA, dRA, dDec), and optionally scene, share and vis: jobs with the same
+    nonzero scene are the sources of one field, whose visibilities add up
+    (their chi^2 entries are the scene's); share = k makes a job read the
+    spectrum of job k of its scene (model may then be None); vis (complex
+    tensor [M]) receives the scene's model visibilities.  The kernels read
+    model and geo at every ``chi2()`` call, so update those tensors in place
+    between calls; the plan (and any HIP graph captured around ``chi2``)
+    stays valid as long as they live."""
 
     def __init__(self, jobs):
         if not jobs:
@@ -562,7 +636,7 @@ def batch_exec(jobs, grads=None, out: torch.Tensor | None = None,
 
     ``jobs`` as for ``Batch``; ``grads`` (optional) is a list with one entry
     per job: None (chi^2 only) or a device tensor of the model's shape and
-    dtype that receives d chi^2 / d model.  Returns chi^2 as a device float64
+    dtype that receives d chi^2 / d model (of the job's scene).  Returns chi^2 as a device float64
     tensor [n], on the current stream.  Nothing is allocated beyond the
     (growing, per-device) workspace."""
     jobs = list(jobs)
@@ -577,6 +651,8 @@ def batch_exec(jobs, grads=None, out: torch.Tensor | None = None,
         gp = (ctypes.c_void_p * len(jobs))()
         for i, (j, g) in enumerate(zip(jobs, grads)):
             if g is not None:
+                if j.get("model") is None:
+                    raise ValueError(f"job {i}: a job without a model has no gradient output")
                 _arr(g, "grad", j["ds"].dtype, dev, j["model"].numel())
                 gp[i] = g.data_ptr()
     need = _lib().gal_batch_exec_workspace_bytes(arr, len(jobs), gp)

@@ -136,4 +136,5 @@ class GalJob(ctypes.Structure):
     """Mirror of gal_job (include/galario_hip.h)."""
     _fields_ = [("ds", ctypes.c_void_p), ("kind", ctypes.c_int), ("Nxy", ctypes.c_int),
                 ("dxy", ctypes.c_double), ("Nr", ctypes.c_int), ("model", ctypes.c_void_p),
-                ("geo", ctypes.c_void_p)]
+                ("geo", ctypes.c_void_p), ("scene", ctypes.c_int), ("share", ctypes.c_int),
+                ("vis", ctypes.c_void_p)]

@@ -3,14 +3,21 @@
 // A batch is a fixed list of jobs (model + dataset + image size).  Its
 // structure is planned once on the host (gal_batch_create): jobs with the same
 // precision, kind and image size share the FFT launches (one block row per
-// job, blockIdx.y), and jobs on the same dataset, kind and image grid share
-// the sampling launch: a block loads its chunk of observations once and
-// evaluates every job of its group on it, so the uv data is read once per
-// group instead of once per job.  The per-job geometry (Rmin, dR, inc, PA,
-// dRA, dDec) and the model arrays are read from device memory at execution,
-// so one plan (and a HIP graph captured from it) serves every step of a
-// fitter that updates those buffers in place.
+// job, blockIdx.y), and jobs on the same dataset share the sampling launch: a
+// block loads its chunk of observations once and evaluates every job of its
+// group on it, so the uv data is read once per group instead of once per job.
+// Jobs of one scene are the sources of one field (Sec. 3.2: the visibilities
+// of several sources add up): the sampling pass sums their visibilities at
+// each point before the residual, and a source may read the spectrum of an
+// identical source instead of transforming its own, so that copies of one
+// model at other offsets and orientations cost one gather each and no FFT.
+// The per-job geometry (Rmin, dR, inc, PA, dRA, dDec) and the model arrays
+// are read from device memory at execution, so one plan (and a HIP graph
+// captured from it) serves every step of a fitter that updates those buffers
+// in place.
 #pragma once
+#include <type_traits>
+
 #include "adjoint.h"
 #include "kernels.h"
 
@@ -27,6 +34,7 @@ struct JobDesc {
     size_t part_off;     // partial sums: byte offset in the workspace
     size_t a_off;        // scatter grid of a gradient job
     size_t gi_off;       // profile-bin accumulator (double) of a gradient profile job
+    void *vis;           // visibilities of the job's scene [M] (c2, dataset precision), or NULL
     int kind;            // 0 image, 1 profile
     int N, Nr, Q, P, CS, Qe;
     double dxy;
@@ -56,12 +64,13 @@ __global__ __launch_bounds__(64) void kb_prepare(JobDesc *__restrict__ jobs, int
     j.inv_cos = 1.0 / ci;
 }
 
-struct SGroup {          // jobs sharing one pass over a dataset
-    const void *u, *v, *re, *im, *w;
+struct SGroup {          // scenes sharing one pass over a dataset
+    const void *u, *v, *re, *im, *w;  // re, im, w NULL: no observations (chi^2 = 0)
+    const int32_t *perm;              // stored point -> registration index
     int64_t M;
     int blk0, nblk;      // flattened block range of the group
-    int nj;
-    int jobs[KMAX];
+    int job_off, nj;     // lists[job_off + m]: job indices, scene members adjacent
+    int sc_off, nsc;     // lists[sc_off + s]: first member of scene s; [sc_off + nsc] = nj
 };
 
 __device__ __forceinline__ SweepArgs sweep_of(const JobDesc &j) {
@@ -125,13 +134,150 @@ __global__ __launch_bounds__(Cfg::NT) void kb_cols_sym(const JobDesc *__restrict
 }
 
 // ---- sampling stage ------------------------------------------------------
-// Block -> group by binary search over the groups' first blocks (after the
-// XCD remap); each thread
-// keeps SAMPLE_PPT points in registers and evaluates every job of the group.
-// GRAD: jobs with a gradient output also scatter their residuals.
+// One job at one point: the bilinear value of its spectrum (cos(inc) for
+// images) times the phase of its offset, plus the stencil for a scatter.
+template <typename T, bool REAL>
+struct JobPoint {
+    std::conditional_t<REAL, StencilR<T>, Stencil<T>> st;
+    double Vre, Vim, sn, cs;
+};
+
+template <typename T, bool REAL>
+__device__ __forceinline__ JobPoint<T, REAL> job_point(const JobDesc &J, const SampleArgs &a,
+                                                       const Geom &g, const char *ws, double u,
+                                                       double v) {
+    JobPoint<T, REAL> r;
+    // exp(i theta), theta = 2 pi (u dRA + v dDec)
+    sincospi_tab(2.0 * (u * a.dRA + v * a.dDec), r.sn, r.cs);
+    // an off-grid stencil points at valid nodes; its value is discarded
+    if constexpr (REAL) {
+        r.st = locate_r<T>((const T *)(ws + J.spec_off), g, a, u, v);
+        const StencilR<T> &st = r.st;
+        const T x0 = st.c0[0], x1 = st.c0[1], y0 = st.c0[g.CS], y1 = st.c0[g.CS + 1];
+        const double a00 = st.swap ? x1 : x0, a10 = st.swap ? x0 : x1;
+        const double a01 = st.swap ? y1 : y0, a11 = st.swap ? y0 : y1;
+        const double s = st.s, t = st.t;
+        const double b = a.cinc * ((1.0 - t) * ((1.0 - s) * a00 + s * a01) +
+                                   t * ((1.0 - s) * a10 + s * a11));
+        r.Vre = st.ok ? b * r.cs : __builtin_nan("");
+        r.Vim = st.ok ? b * r.sn : __builtin_nan("");
+    } else {
+        r.st = locate<T>((const c2<T> *)(ws + J.spec_off), g, a, u, v);
+        const Stencil<T> &st = r.st;
+        const c2<T> n00 = st.c0[0], n10 = st.c0[1], n01 = st.c0[g.CS], n11 = st.c0[g.CS + 1];
+        const double s = st.s, t = st.t;
+        const double w00 = (1.0 - t) * (1.0 - s), w01 = (1.0 - t) * s;
+        const double w10 = t * (1.0 - s), w11 = t * s;
+        double br = w00 * (double)n00.x + w01 * (double)n01.x + w10 * (double)n10.x +
+                    w11 * (double)n11.x;
+        double bi = w00 * (double)n00.y + w01 * (double)n01.y + w10 * (double)n10.y +
+                    w11 * (double)n11.y;
+        if (st.mirror) bi = -bi;
+        br *= a.cinc;
+        bi *= a.cinc;
+        r.Vre = st.ok ? br * r.cs - bi * r.sn : __builtin_nan("");
+        r.Vim = st.ok ? br * r.sn + bi * r.cs : __builtin_nan("");
+    }
+    return r;
+}
+
+// the point's share of d chi^2 / d spectrum for residual R = obs - V (weight w)
+template <typename T, bool REAL>
+__device__ __forceinline__ PointAdd<REAL ? 1 : 2> job_point_add(const JobPoint<T, REAL> &q,
+                                                                 double w, double cinc, double R0,
+                                                                 double R1) {
+    if constexpr (REAL) return point_add_real<T>(q.st, w * cinc * (R0 * q.cs + R1 * q.sn));
+    else return point_add_cplx<T>(q.st, w * cinc, R0, R1, q.sn, q.cs);
+}
+
+template <typename T>
+__device__ __forceinline__ void store_vis(void *vis, const int32_t *perm, int64_t k, double re,
+                                          double im) {
+    ((c2<T> *)vis)[perm ? (int64_t)perm[k] : k] = c2<T>{(T)re, (T)im};
+}
+
+// Points held by one thread of a sampling block.
+template <int PPT>
+struct BlockPoints {
+    int64_t base, M;
+    double uu[PPT], vv[PPT], rr[PPT], ii[PPT], ww[PPT];
+    __device__ __forceinline__ bool in(int p) const { return base + p * SAMPLE_NT < M; }
+    __device__ __forceinline__ int64_t idx(int p) const { return base + p * SAMPLE_NT; }
+};
+
+// A job alone in its scene (of the scene kernel): value, residual, chi^2 term,
+// visibility output and scatter in one sweep over the thread's points.
+// Returns the thread's chi^2 sum.
+template <typename T, bool REAL, bool GRAD, int PPT>
+__device__ __forceinline__ double job_alone(const JobDesc &J, const BlockPoints<PPT> &X,
+                                            const int32_t *perm, char *ws, double *tile,
+                                            int *box, bool &bad) {
+    constexpr int NV = REAL ? 1 : 2;
+    const SampleArgs a = sample_from_job(J, X.M);
+    const Geom g = geom_of(J);
+    double acc = 0.0;
+    PointAdd<NV> pa[PPT];
+#pragma unroll
+    for (int p = 0; p < PPT; ++p) {
+        const bool in = X.in(p);
+        pa[p].q = -1;
+        const JobPoint<T, REAL> q = job_point<T, REAL>(J, a, g, ws, X.uu[p], X.vv[p]);
+        if (GRAD && J.grad && in && q.st.ok)
+            pa[p] = job_point_add<T, REAL>(q, X.ww[p], a.cinc, X.rr[p] - q.Vre, X.ii[p] - q.Vim);
+        bad |= in && !q.st.ok;
+        if (in) {
+            const double dr = q.Vre - X.rr[p], di = q.Vim - X.ii[p];
+            acc += X.ww[p] * (dr * dr + di * di);
+            if (J.vis) store_vis<T>(J.vis, perm, X.idx(p), q.Vre, q.Vim);
+        }
+    }
+    if (GRAD && J.grad) block_scatter<T, NV, PPT>((T *)(ws + J.a_off), g.CS, pa, tile, box);
+    return acc;
+}
+
+// V += the job's visibilities at the thread's points
+template <typename T, bool REAL, int PPT>
+__device__ __forceinline__ void job_add(const JobDesc &J, const BlockPoints<PPT> &X,
+                                        const char *ws, double (&Vr)[PPT], double (&Vi)[PPT],
+                                        bool &bad) {
+    const SampleArgs a = sample_from_job(J, X.M);
+    const Geom g = geom_of(J);
+#pragma unroll
+    for (int p = 0; p < PPT; ++p) {
+        const JobPoint<T, REAL> q = job_point<T, REAL>(J, a, g, ws, X.uu[p], X.vv[p]);
+        bad |= X.in(p) && !q.st.ok;
+        Vr[p] += q.Vre;
+        Vi[p] += q.Vim;
+    }
+}
+
+// the job's part of d chi^2 / d spectrum for the scene's residual R
+template <typename T, bool REAL, int PPT>
+__device__ __forceinline__ void job_scatter(const JobDesc &J, const BlockPoints<PPT> &X,
+                                            char *ws, const double (&Rr)[PPT],
+                                            const double (&Ri)[PPT], double *tile, int *box) {
+    constexpr int NV = REAL ? 1 : 2;
+    const SampleArgs a = sample_from_job(J, X.M);
+    const Geom g = geom_of(J);
+    PointAdd<NV> pa[PPT];
+#pragma unroll
+    for (int p = 0; p < PPT; ++p) {
+        pa[p].q = -1;
+        const JobPoint<T, REAL> q = job_point<T, REAL>(J, a, g, ws, X.uu[p], X.vv[p]);
+        if (X.in(p) && q.st.ok) pa[p] = job_point_add<T, REAL>(q, X.ww[p], a.cinc, Rr[p], Ri[p]);
+    }
+    block_scatter<T, NV, PPT>((T *)(ws + J.a_off), g.CS, pa, tile, box);
+}
+
+// Plain groups (every job alone in its scene, with observations and no
+// visibility output).  Block -> group by binary search over the groups' first
+// blocks (after the XCD remap); each thread keeps SAMPLE_PPT points in
+// registers and evaluates every job of the group.  GRAD: jobs with a gradient
+// output also scatter their residuals.
 template <typename T, bool REAL, bool GRAD>
 __global__ __launch_bounds__(SAMPLE_NT) void kb_sample_chi2(const JobDesc *__restrict__ jobs,
                                                             const SGroup *__restrict__ groups,
+                                                            const int *__restrict__ lists,
                                                             int ngroups, char *ws) {
     constexpr int PPT = SAMPLE_PPT;
     constexpr int NV = REAL ? 1 : 2;
@@ -165,7 +311,7 @@ __global__ __launch_bounds__(SAMPLE_NT) void kb_sample_chi2(const JobDesc *__res
     Control *ctl = (Control *)ws;
     bool bad = false;
     for (int jj = 0; jj < G.nj; ++jj) {
-        const JobDesc &J = jobs[G.jobs[jj]];
+        const JobDesc &J = jobs[lists[G.job_off + jj]];
         const SampleArgs a = sample_from_job(J, G.M);
         const Geom g = geom_of(J);
         double acc = 0.0;
@@ -232,8 +378,124 @@ __global__ __launch_bounds__(SAMPLE_NT) void kb_sample_chi2(const JobDesc *__res
     if (bad) ctl->flag = 1;
 }
 
-// chi2[j] = sum of job j's partials in a fixed order (one block per job,
-// as k_reduce).  Bitwise repeatable.
+// KC: the kinds of the class's jobs -- 0 images, 1 profiles, 2 both (the kind
+// is then read per job; a uniform branch).
+template <int KC>
+__device__ __forceinline__ bool real_job(const JobDesc &J) {
+    if constexpr (KC == 2) return J.kind == 1;
+    else return KC == 1;
+}
+
+// Groups of scenes: several sources, visibility outputs or datasets without
+// observations (a kernel of its own, so that the registers these need do not
+// lower the occupancy of the plain one).  As kb_sample_chi2, per scene: the
+// members' visibilities add up before the residual, and members with a
+// gradient scatter the scene's residual.
+template <typename T, int KC, bool GRAD>
+__global__ __launch_bounds__(SAMPLE_NT) void kb_sample_scene(const JobDesc *__restrict__ jobs,
+                                                            const SGroup *__restrict__ groups,
+                                                            const int *__restrict__ lists,
+                                                            int ngroups, char *ws) {
+    constexpr int PPT = SAMPLE_PPT;
+    __shared__ double tile[GRAD ? SCAT_TILE : 1];
+    __shared__ int box[GRAD ? 4 * WAVES : 1];
+    // every XCD takes a contiguous run of chunks: a compact patch of the
+    // (locality-ordered) uv plane, whose spectrum nodes then stay in its L2
+    const int bid = xcd_remap(blockIdx.x, gridDim.x);
+    int lo = 0, hi = ngroups - 1;
+    while (lo < hi) {
+        const int mid = (lo + hi + 1) >> 1;
+        if (groups[mid].blk0 <= bid) lo = mid;
+        else hi = mid - 1;
+    }
+    const SGroup &G = groups[lo];
+    const int chunk = bid - G.blk0;
+    BlockPoints<PPT> X;
+    X.base = (int64_t)chunk * (SAMPLE_NT * PPT) + threadIdx.x;
+    X.M = G.M;
+    const gptr<T> u = as_global<T>(G.u), v = as_global<T>(G.v);
+    const gptr<T> re = as_global<T>(G.re), im = as_global<T>(G.im), w = as_global<T>(G.w);
+    const bool obs = G.re != nullptr;
+#pragma unroll
+    for (int p = 0; p < PPT; ++p) {
+        const int64_t k = X.idx(p);
+        const bool in = k < G.M;
+        X.uu[p] = in ? (double)u[k] : 0.0;
+        X.vv[p] = in ? (double)v[k] : 0.0;
+        X.rr[p] = in && obs ? (double)re[k] : 0.0;
+        X.ii[p] = in && obs ? (double)im[k] : 0.0;
+        X.ww[p] = in && obs ? (double)w[k] : 0.0;  // points past M weigh nothing
+    }
+    Control *ctl = (Control *)ws;
+    bool bad = false;
+    const int *mem = lists + G.job_off;
+    for (int sc = 0; sc < G.nsc; ++sc) {
+        const int m0 = lists[G.sc_off + sc], m1 = lists[G.sc_off + sc + 1];
+        const JobDesc &L = jobs[mem[m0]];
+        double acc = 0.0;
+        if (m1 - m0 == 1) {
+            if (real_job<KC>(L)) {
+                if constexpr (KC != 0)
+                    acc = job_alone<T, true, GRAD, PPT>(L, X, G.perm, ws, tile, box, bad);
+            } else {
+                if constexpr (KC != 1)
+                    acc = job_alone<T, false, GRAD, PPT>(L, X, G.perm, ws, tile, box, bad);
+            }
+        } else {
+            // a scene of several sources: V = sum of the sources' visibilities
+            double Vr[PPT], Vi[PPT];
+#pragma unroll
+            for (int p = 0; p < PPT; ++p) Vr[p] = Vi[p] = 0.0;
+            for (int m = m0; m < m1; ++m) {
+                const JobDesc &J = jobs[mem[m]];
+                if (real_job<KC>(J)) {
+                    if constexpr (KC != 0) job_add<T, true, PPT>(J, X, ws, Vr, Vi, bad);
+                } else {
+                    if constexpr (KC != 1) job_add<T, false, PPT>(J, X, ws, Vr, Vi, bad);
+                }
+            }
+#pragma unroll
+            for (int p = 0; p < PPT; ++p) {
+                if (!X.in(p)) continue;
+                const double dr = Vr[p] - X.rr[p], di = Vi[p] - X.ii[p];
+                acc += X.ww[p] * (dr * dr + di * di);
+            }
+            for (int m = m0; m < m1; ++m) {
+                const JobDesc &J = jobs[mem[m]];
+                if (!J.vis) continue;
+#pragma unroll
+                for (int p = 0; p < PPT; ++p)
+                    if (X.in(p)) store_vis<T>(J.vis, G.perm, X.idx(p), Vr[p], Vi[p]);
+            }
+            if constexpr (GRAD) {
+                double Rr[PPT], Ri[PPT];
+#pragma unroll
+                for (int p = 0; p < PPT; ++p) {
+                    Rr[p] = X.rr[p] - Vr[p];
+                    Ri[p] = X.ii[p] - Vi[p];
+                }
+                for (int m = m0; m < m1; ++m) {
+                    const JobDesc &J = jobs[mem[m]];
+                    if (!J.grad) continue;
+                    if (real_job<KC>(J)) {
+                        if constexpr (KC != 0) job_scatter<T, true, PPT>(J, X, ws, Rr, Ri, tile, box);
+                    } else {
+                        if constexpr (KC != 1) job_scatter<T, false, PPT>(J, X, ws, Rr, Ri, tile, box);
+                    }
+                }
+            }
+        }
+        // one partial per wave and scene (no barrier between chi^2-only
+        // scenes); kb_reduce adds them
+        const double wsum = wave_sum(acc);
+        if ((threadIdx.x & 63) == 0)
+            ((double *)(ws + L.part_off))[chunk * WAVES + (threadIdx.x >> 6)] = wsum;
+    }
+    if (bad) ctl->flag = 1;
+}
+
+// chi2[j] = sum of the partials of job j's scene in a fixed order (one block
+// per job, as k_reduce).  Bitwise repeatable.
 __global__ __launch_bounds__(REDUCE_NT) void kb_reduce(const JobDesc *__restrict__ jobs,
                                                        const SGroup *__restrict__ groups,
                                                        const int *__restrict__ job_group,

@@ -859,7 +859,7 @@ struct BatchPlan {
     std::vector<int> lists;
     struct SClass {
         int prec;
-        bool real;
+        int kc;                     // kinds: 0 images, 1 profiles, 2 both; + 3: scenes
         int group_off, count, blocks;
     };
     std::vector<SClass> sclasses;
@@ -1501,10 +1501,12 @@ GAL_PROFILE_GEOGRAD_DS(d, double)
 GAL_PROFILE_GEOGRAD_DS(f, float)
 
 // ---- batches --------------------------------------------------------------
-// Plan a job list: checks, geometry, sample groups (same dataset, kind and
-// grid, <= KMAX jobs), FFT groups (same precision, kind and size), adjoint
-// groups (the gradient jobs), workspace layout starting at `base`:
-// [partials][spectra][scatter grids][bin accumulators].
+// Plan a job list: checks, geometry, scenes (jobs whose visibilities add up),
+// sample groups (scenes on the same dataset with the same member kinds and
+// grids, <= KMAX jobs unless one scene is larger), FFT groups (same
+// precision, kind and size; jobs that read another's spectrum have none),
+// adjoint groups (gradient jobs that own a spectrum), workspace layout
+// starting at `base`: [partials][spectra][scatter grids][bin accumulators].
 static int plan_batch(const gal_job *jobs, int n, void *const *grads, size_t base,
                       BatchPlan &P) {
     if (n < 1) return fail(GAL_ERR_SIZE, "a batch needs at least one job");
@@ -1517,17 +1519,31 @@ static int plan_batch(const gal_job *jobs, int n, void *const *grads, size_t bas
     P.job_group.assign(n, -1);
     for (int i = 0; i < n; ++i) {
         const gal_job &J = jobs[i];
-        if (!J.ds || !J.model || !J.geo) return fail(GAL_ERR_NULL, "job %d: NULL dataset, model or geo", i);
-        if (!J.ds->re) return fail(GAL_ERR_UNSUPPORTED, "job %d: dataset holds no observations", i);
+        void *gr = grads ? grads[i] : nullptr;
+        if (J.scene < 0 || J.share < 0 || J.share > n)
+            return fail(GAL_ERR_UNSUPPORTED, "job %d: scene and share must be >= 0, share <= n", i);
+        if (!J.ds || !J.geo || (!J.model && !J.share))
+            return fail(GAL_ERR_NULL, "job %d: NULL dataset, model or geo", i);
+        if (!J.ds->re && gr) return fail(GAL_ERR_UNSUPPORTED, "job %d: a gradient needs observations", i);
         if (J.kind != 0 && J.kind != 1) return fail(GAL_ERR_UNSUPPORTED, "job %d: kind must be 0 or 1", i);
         if (!pow2_in_range(J.Nxy)) return fail(GAL_ERR_SIZE, "job %d: Nxy unsupported", i);
         if (!(J.dxy >= DXY_MIN) || !std::isfinite(J.dxy)) return fail(GAL_ERR_SCALAR, "job %d: dxy must be >= 1e-100", i);
-        if (J.kind == 1 && J.Nr < 2) return fail(GAL_ERR_SIZE, "job %d: Nr < 2", i);
         if (J.ds->device != dev) return fail(GAL_ERR_UNSUPPORTED, "job %d: dataset on another device", i);
         const double du = 1.0 / ((double)J.Nxy * J.dxy);
         if (!(J.ds->rho_max < ((double)(J.Nxy / 2) - 1.0) * du))
             return fail(GAL_ERR_UV_RANGE, "job %d: dataset rho_max reaches beyond the half spectrum", i);
-        void *gr = grads ? grads[i] : nullptr;
+        if (J.share) {
+            const int o = J.share - 1;
+            const gal_job &O = jobs[o];
+            if (o == i || O.share) return fail(GAL_ERR_UNSUPPORTED, "job %d: shares the spectrum of a job that shares one", i);
+            if (!J.scene || O.scene != J.scene)
+                return fail(GAL_ERR_UNSUPPORTED, "job %d: shares a spectrum outside its scene", i);
+            if (O.kind != J.kind || O.Nxy != J.Nxy || O.dxy != J.dxy || O.ds != J.ds)
+                return fail(GAL_ERR_UNSUPPORTED, "job %d: shares a spectrum of another kind or grid", i);
+            if (gr) return fail(GAL_ERR_UNSUPPORTED, "job %d: a sharing job's gradient goes to the owner's output", i);
+            continue;  // described below, from its owner
+        }
+        if (J.kind == 1 && J.Nr < 2) return fail(GAL_ERR_SIZE, "job %d: Nr < 2", i);
         if (gr && J.kind == 1) {
             if (J.Nr > GRAD_NR_MAX) return fail(GAL_ERR_SIZE, "job %d: gradient needs Nr <= %d", i, GRAD_NR_MAX);
             const size_t lds = (size_t)cols_B(J.Nxy) * J.Nxy * 2 * (size_t)J.ds->precision +
@@ -1540,6 +1556,7 @@ static int plan_batch(const gal_job *jobs, int n, void *const *grads, size_t bas
         d.src = J.model;
         d.geo = J.geo;
         d.grad = gr;
+        d.vis = J.vis;
         d.kind = J.kind;
         d.N = J.Nxy;
         d.Nr = J.kind == 1 ? J.Nr : 0;
@@ -1550,62 +1567,125 @@ static int plan_batch(const gal_job *jobs, int n, void *const *grads, size_t bas
         d.dxy = J.dxy;
         P.grads = P.grads || gr;
     }
-    for (int i = 0; i < n; ++i) {
-        if (P.job_group[i] >= 0) continue;
-        const gal_job &Ji = jobs[i];
-        SGroup G{};
-        G.u = Ji.ds->u;
-        G.v = Ji.ds->v;
-        G.re = Ji.ds->re;
-        G.im = Ji.ds->im;
-        G.w = Ji.ds->w;
-        G.M = Ji.ds->M;
-        G.nj = 0;
-        for (int k = i; k < n && G.nj < KMAX; ++k) {
-            const gal_job &Jk = jobs[k];
-            if (P.job_group[k] >= 0 || Jk.ds != Ji.ds || Jk.kind != Ji.kind ||
-                Jk.Nxy != Ji.Nxy || Jk.dxy != Ji.dxy)
-                continue;
-            P.job_group[k] = (int)P.groups.size();
-            G.jobs[G.nj++] = k;
+    // scenes: units of the sampling pass (a job with scene 0 is alone)
+    std::vector<std::vector<int>> units;
+    {
+        std::vector<std::pair<int, int>> first;  // scene id -> unit
+        for (int i = 0; i < n; ++i) {
+            const int sid = jobs[i].scene;
+            int u = -1;
+            if (sid) {
+                for (const auto &f : first)
+                    if (f.first == sid) u = f.second;
+            }
+            if (u < 0) {
+                u = (int)units.size();
+                units.emplace_back();
+                if (sid) first.push_back({sid, u});
+            } else if (jobs[units[u][0]].ds != jobs[i].ds) {
+                return fail(GAL_ERR_UNSUPPORTED, "job %d: a scene spans two datasets", i);
+            }
+            units[u].push_back(i);
         }
-        G.nblk = (int)sample_blocks(G.M);
-        P.groups.push_back(G);
     }
-    auto cls = [&](const SGroup &G) {
-        return (jobs[G.jobs[0]].ds->precision == 8 ? 0 : 2) + (jobs[G.jobs[0]].kind == 1 ? 1 : 0);
+    // a unit's member kinds and grids; units with equal signatures on one
+    // dataset share a group
+    auto same_sig = [&](const std::vector<int> &a, const std::vector<int> &c) {
+        if (a.size() != c.size() || jobs[a[0]].ds != jobs[c[0]].ds) return false;
+        for (size_t m = 0; m < a.size(); ++m) {
+            const gal_job &x = jobs[a[m]], &y = jobs[c[m]];
+            if (x.kind != y.kind || x.Nxy != y.Nxy || x.dxy != y.dxy || !x.share != !y.share ||
+                !x.vis != !y.vis)
+                return false;
+        }
+        return true;
     };
-    std::vector<int> order(P.groups.size());
+    auto kind_class = [&](const std::vector<int> &u) {
+        int has = 0;
+        for (int i : u) has |= jobs[i].kind == 1 ? 2 : 1;
+        return has == 1 ? 0 : has == 2 ? 1 : 2;
+    };
+    struct GroupDraft {
+        std::vector<int> units;
+        int nj = 0;
+    };
+    std::vector<GroupDraft> drafts;
+    {
+        std::vector<char> used(units.size(), 0);
+        for (size_t a0 = 0; a0 < units.size(); ++a0) {
+            if (used[a0]) continue;
+            GroupDraft G;
+            for (size_t c = a0; c < units.size(); ++c) {
+                if (used[c] || !same_sig(units[a0], units[c])) continue;
+                if (G.nj > 0 && G.nj + (int)units[c].size() > KMAX) continue;
+                used[c] = 1;
+                G.units.push_back((int)c);
+                G.nj += (int)units[c].size();
+            }
+            drafts.push_back(G);
+        }
+    }
+    // class: precision, member kinds, and whether the scene kernel is needed
+    // (several sources, a visibility output or no observations)
+    auto needs_scene = [&](const std::vector<int> &u) {
+        bool r = u.size() > 1 || !jobs[u[0]].ds->re;
+        for (int i : u) r = r || jobs[i].vis;
+        return r;
+    };
+    auto cls = [&](const GroupDraft &G) {
+        const std::vector<int> &u = units[G.units[0]];
+        return (jobs[u[0]].ds->precision == 8 ? 0 : 6) + (needs_scene(u) ? 3 : 0) + kind_class(u);
+    };
+    std::vector<int> order(drafts.size());
     for (size_t g = 0; g < order.size(); ++g) order[g] = (int)g;
     std::stable_sort(order.begin(), order.end(),
-                     [&](int a, int c) { return cls(P.groups[a]) < cls(P.groups[c]); });
-    std::vector<SGroup> sorted;
-    std::vector<int> remap(order.size());
-    for (size_t k = 0; k < order.size(); ++k) {
-        remap[order[k]] = (int)k;
-        sorted.push_back(P.groups[order[k]]);
-    }
-    P.groups.swap(sorted);
-    for (int i = 0; i < n; ++i) P.job_group[i] = remap[P.job_group[i]];
-    for (size_t g = 0; g < P.groups.size(); ++g) {
-        const int c = cls(P.groups[g]);
-        const int prec = c < 2 ? 8 : 4;
-        const bool real = (c & 1) == 1;
-        if (P.sclasses.empty() || P.sclasses.back().prec != prec || P.sclasses.back().real != real)
-            P.sclasses.push_back({prec, real, (int)g, 0, 0});
+                     [&](int a, int c) { return cls(drafts[a]) < cls(drafts[c]); });
+    for (int gi : order) {
+        const GroupDraft &D = drafts[gi];
+        const gal_dataset *ds = jobs[units[D.units[0]][0]].ds;
+        SGroup G{};
+        G.u = ds->u;
+        G.v = ds->v;
+        G.re = ds->re;
+        G.im = ds->im;
+        G.w = ds->w;
+        G.perm = ds->perm;
+        G.M = ds->M;
+        G.nblk = (int)sample_blocks(G.M);
+        G.job_off = (int)P.lists.size();
+        G.nj = D.nj;
+        for (int u : D.units)
+            for (int i : units[u]) {
+                P.job_group[i] = (int)P.groups.size();
+                P.lists.push_back(i);
+            }
+        G.sc_off = (int)P.lists.size();
+        G.nsc = (int)D.units.size();
+        int m = 0;
+        for (int u : D.units) {
+            P.lists.push_back(m);
+            m += (int)units[u].size();
+        }
+        P.lists.push_back(m);
+        const int c = cls(D);
+        const int prec = c < 6 ? 8 : 4;
+        const int kc = c % 6;
+        if (P.sclasses.empty() || P.sclasses.back().prec != prec || P.sclasses.back().kc != kc)
+            P.sclasses.push_back({prec, kc, (int)P.groups.size(), 0, 0});
         BatchPlan::SClass &sc = P.sclasses.back();
-        P.groups[g].blk0 = sc.blocks;
-        sc.blocks += P.groups[g].nblk;
+        G.blk0 = sc.blocks;
+        sc.blocks += G.nblk;
         sc.count += 1;
+        P.groups.push_back(G);
     }
     auto make_groups = [&](bool grad_only, std::vector<BatchPlan::FGroup> &out) {
         std::vector<char> used(n, 0);
         for (int i = 0; i < n; ++i) {
-            if (used[i] || (grad_only && !P.jobs[i].grad)) continue;
+            if (used[i] || jobs[i].share || (grad_only && !P.jobs[i].grad)) continue;
             const int prec = jobs[i].ds->precision;
             BatchPlan::FGroup f{prec, jobs[i].kind, jobs[i].Nxy, (int)P.lists.size(), 0, 0, 0, 0};
             for (int k = i; k < n; ++k) {
-                if (used[k] || (grad_only && !P.jobs[k].grad)) continue;
+                if (used[k] || jobs[k].share || (grad_only && !P.jobs[k].grad)) continue;
                 if (jobs[k].ds->precision != prec || jobs[k].kind != f.kind || jobs[k].Nxy != f.N)
                     continue;
                 used[k] = 1;
@@ -1620,13 +1700,15 @@ static int plan_batch(const gal_job *jobs, int n, void *const *grads, size_t bas
     };
     make_groups(false, P.fgroups);
     make_groups(true, P.agroups);
-    // layout
+    // layout: partials per scene (at its first member), spectra, scatter
+    // grids and bin accumulators per owning job
     P.table_bytes = align256(sizeof(JobDesc) * n) + align256(sizeof(SGroup) * P.groups.size()) +
                     align256(sizeof(int) * P.lists.size()) + align256(sizeof(int) * n);
     size_t off = base;
-    for (int i = 0; i < n; ++i) {
-        P.jobs[i].part_off = off;
-        off += align256((size_t)P.groups[P.job_group[i]].nblk * WAVES * sizeof(double));
+    for (const auto &u : units) {
+        P.jobs[u[0]].part_off = off;
+        off += align256((size_t)P.groups[P.job_group[u[0]]].nblk * WAVES * sizeof(double));
+        for (int i : u) P.jobs[i].part_off = P.jobs[u[0]].part_off;
     }
     auto spec_bytes = [&](int i) {
         const JobDesc &d = P.jobs[i];
@@ -1634,12 +1716,13 @@ static int plan_batch(const gal_job *jobs, int n, void *const *grads, size_t bas
         return d.kind == 1 ? (size_t)d.Qe * d.CS * el : (size_t)d.Q * d.CS * 2 * el;
     };
     for (int i = 0; i < n; ++i) {
+        if (jobs[i].share) continue;
         P.jobs[i].spec_off = off;
         off += align256(spec_bytes(i));
     }
     P.zero_begin = off;
     for (int i = 0; i < n; ++i) {
-        if (!P.jobs[i].grad) continue;
+        if (!P.jobs[i].grad || jobs[i].share) continue;
         P.jobs[i].a_off = off;
         off += align256(spec_bytes(i));
         if (P.jobs[i].kind == 1) {
@@ -1649,6 +1732,16 @@ static int plan_batch(const gal_job *jobs, int n, void *const *grads, size_t bas
     }
     P.zero_end = off;
     P.ws_need = off;
+    // a sharing job: the owner's transform, spectrum and gradient buffers;
+    // its own geometry, scene partials and visibility output
+    for (int i = 0; i < n; ++i) {
+        if (!jobs[i].share) continue;
+        JobDesc d = P.jobs[jobs[i].share - 1];
+        d.geo = jobs[i].geo;
+        d.vis = jobs[i].vis;
+        d.part_off = P.jobs[i].part_off;
+        P.jobs[i] = d;
+    }
     return GAL_OK;
 }
 
@@ -1737,14 +1830,37 @@ static int batch_adj(const BatchPlan::FGroup &f, const BatchTables &t, char *ws,
     }
 }
 
-template <typename T, bool REAL>
+template <typename T, int KC>
 static int batch_sample(const BatchPlan::SClass &c, bool grads, const BatchTables &t, char *ws,
                         hipStream_t s) {
     const SGroup *g = t.groups + c.group_off;
     const dim3 grid(c.blocks), blk(SAMPLE_NT);
+    if (KC >= 3) {  // scenes
+        constexpr int K = KC >= 3 ? KC - 3 : 0;
+        if (grads)
+            return launch("kb_sample_scene", kb_sample_scene<T, K, true>, grid, blk, s, t.jobs, g,
+                          t.lists, c.count, ws);
+        return launch("kb_sample_scene", kb_sample_scene<T, K, false>, grid, blk, s, t.jobs, g,
+                      t.lists, c.count, ws);
+    }
+    constexpr bool REAL = KC == 1;
     const char *name = REAL ? "kb_sample_sym_chi2" : "kb_sample_chi2";
-    if (grads) return launch(name, kb_sample_chi2<T, REAL, true>, grid, blk, s, t.jobs, g, c.count, ws);
-    return launch(name, kb_sample_chi2<T, REAL, false>, grid, blk, s, t.jobs, g, c.count, ws);
+    if (grads)
+        return launch(name, kb_sample_chi2<T, REAL, true>, grid, blk, s, t.jobs, g, t.lists, c.count, ws);
+    return launch(name, kb_sample_chi2<T, REAL, false>, grid, blk, s, t.jobs, g, t.lists, c.count, ws);
+}
+
+template <typename T>
+static int batch_sample_any(const BatchPlan::SClass &c, bool grads, const BatchTables &t,
+                            char *ws, hipStream_t s) {
+    switch (c.kc) {
+        case 0: return batch_sample<T, 0>(c, grads, t, ws, s);
+        case 1: return batch_sample<T, 1>(c, grads, t, ws, s);
+        case 3: return batch_sample<T, 3>(c, grads, t, ws, s);
+        case 4: return batch_sample<T, 4>(c, grads, t, ws, s);
+        case 5: return batch_sample<T, 5>(c, grads, t, ws, s);
+        default: return fail(GAL_ERR_UNSUPPORTED, "sample class %d", c.kc);
+    }
 }
 
 static int exec_plan(const BatchPlan &P, const BatchTables &t, char *ws, double *chi2, hipStream_t s) {
@@ -1760,12 +1876,8 @@ static int exec_plan(const BatchPlan &P, const BatchTables &t, char *ws, double 
         if (rc) return rc;
     }
     for (const auto &c : P.sclasses) {
-        if (c.prec == 8)
-            rc = c.real ? batch_sample<double, true>(c, P.grads, t, ws, s)
-                        : batch_sample<double, false>(c, P.grads, t, ws, s);
-        else
-            rc = c.real ? batch_sample<float, true>(c, P.grads, t, ws, s)
-                        : batch_sample<float, false>(c, P.grads, t, ws, s);
+        rc = c.prec == 8 ? batch_sample_any<double>(c, P.grads, t, ws, s)
+                         : batch_sample_any<float>(c, P.grads, t, ws, s);
         if (rc) return rc;
     }
     rc = launch("kb_reduce", kb_reduce, dim3(P.n), dim3(REDUCE_NT), s, t.jobs, t.groups, t.job_group,

@@ -199,6 +199,20 @@ def profile_2048(M: int = 1_000_000) -> Workload:
                     PA=120 * DEG, inc=45 * DEG, I=I, Rmin=Rmin, dR=dR)
 
 
+def field_of_copies(c: Workload, n: int, seed: int) -> list:
+    """A field of n copies of the profile workload ``c``: the first at c's own
+    geometry, the others (sharing its spectrum) at random PA and offsets of up
+    to 1'' from the phase centre.  Source dicts as the oracle takes them."""
+    rng = np.random.default_rng(seed)
+    out = [dict(kind="profile", I=c.I, Rmin=c.Rmin, dR=c.dR, Nxy=c.N, dxy=c.dxy, inc=c.inc,
+                PA=c.PA, dRA=c.dRA, dDec=c.dDec)]
+    for _ in range(n - 1):
+        out.append(dict(kind="profile", I=None, share=0, dxy=c.dxy, Nxy=c.N,
+                        PA=rng.uniform(0.0, math.pi),
+                        dRA=rng.uniform(-1.0, 1.0) * ARCSEC, dDec=rng.uniform(-1.0, 1.0) * ARCSEC))
+    return out
+
+
 def blobs_4096(M: int = 5_000_000) -> Workload:
     """chi2Image, 4096^2: 200 Gaussian blobs, dxy = 0.013'' (ALMA C43-6),
     M = 5e6 log-uniform in [1.123e4, 1.936e6] lambda, noise sigma 1e-3 Jy."""
