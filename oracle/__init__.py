@@ -265,12 +265,28 @@ def _resolve(sources):
     return out
 
 
-def _vis_one(s, u, v):
-    if s["kind"] == "image":
-        return sampleImage(s["image"], s["dxy"], u, v, s.get("PA", 0.0), s.get("dRA", 0.0),
-                           s.get("dDec", 0.0), s.get("inc", 0.0))
-    return sampleProfile(s["I"], s["Rmin"], s["dR"], s["Nxy"], s["dxy"], u, v, s.get("inc", 0.0),
-                         s.get("PA", 0.0), s.get("dRA", 0.0), s.get("dDec", 0.0))
+def _source_vis(sources, u, v):
+    """Each source's visibilities.  A source samples the half spectrum of its
+    own model -- for an image, with its inclination applied at sampling; for
+    a profile, the transform of the inclined swept image (as sampleImage and
+    sampleProfile) -- and a source with "share" samples its owner's, which is
+    transformed once."""
+    res = _resolve(sources)
+    spectra = {}
+    out = []
+    for i, s in enumerate(res):
+        owner = sources[i].get("share")
+        owner = i if owner is None else owner
+        if owner not in spectra:
+            o = res[owner]
+            img = o["image"] if o["kind"] == "image" else sweep(
+                o["I"], o["Rmin"], o["dR"], o["Nxy"], o["dxy"], o.get("inc", 0.0))
+            spectra[owner] = (grid(img), np.shape(img)[0])
+        G, N = spectra[owner]
+        inc = s.get("inc", 0.0) if s["kind"] == "image" else 0.0
+        out.append(sample_grid(G, N, s["dxy"], u, v, s.get("PA", 0.0), s.get("dRA", 0.0),
+                               s.get("dDec", 0.0), inc))
+    return out
 
 
 def sample_sources(sources, u, v) -> np.ndarray:
@@ -280,8 +296,8 @@ def sample_sources(sources, u, v) -> np.ndarray:
     or {"kind": "profile", "I", "Rmin", "dR", "Nxy", "dxy", inc, PA, dRA,
     dDec} (geometry keys default to 0), optionally "share": k (see _resolve)."""
     V = np.zeros(np.size(u), dtype=np.complex128)
-    for s in _resolve(sources):
-        V += _vis_one(s, u, v)
+    for Vs in _source_vis(sources, u, v):
+        V += Vs
     return V
 
 
@@ -297,7 +313,7 @@ def grad_sources(sources, u, v, re, im, w):
     obs - V_others.  A source with "share" gets None: by the chain rule its
     gradient is added into the owner's."""
     res = _resolve(sources)
-    Vs = [_vis_one(s, u, v) for s in res]
+    Vs = _source_vis(sources, u, v)
     V = np.sum(Vs, axis=0)
     c2 = chi2(V, re, im, w)
     grads = [None] * len(sources)
