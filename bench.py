@@ -215,6 +215,8 @@ def main():
     ap.add_argument("--plain-steps", type=int, default=2000)
     ap.add_argument("--latency-samples", type=int, default=300)
     ap.add_argument("--grad-steps", type=int, default=300, help="timed plain gradient calls")
+    ap.add_argument("--field-sources", type=int, default=16,
+                    help="sources in the field section (copies of the profile)")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-graph", action="store_true", help="launch batches without a HIP graph")
     ap.add_argument("--calib-copy", action="store_true",
@@ -307,6 +309,28 @@ def main():
     # ---- plain geometry gradient: chi^2 and d chi^2 / d (PA, dRA, dDec, inc) ----
     geo_call = lambda: ds.chi2Profile_geograd(I, case.Rmin, case.dR, N, case.dxy, **geo)
     ms_geo = _timed(geo_call, args.grad_steps, args.warmup, torch)
+
+    # ---- a field of several sources (Sec. 3.2): copies of the profile at
+    # other offsets and orientations, one scene; with the copies reading the
+    # first one's spectrum, and with a transform per copy --------------------
+    S = args.field_sources
+    src_o = wl.field_of_copies(case, S, seed=1103)
+    shared = []
+    for s in src_o:
+        d = {k: x for k, x in s.items() if k != "I"}
+        d["model"] = I if s.get("share") is None else None
+        shared.append(d)
+    own = [dict(d, model=I, share=None, Rmin=case.Rmin, dR=case.dR, inc=case.inc) for d in shared]
+    fb_shared, fb_own = gal.Batch(ds._scene_jobs(shared)), gal.Batch(ds._scene_jobs(own))
+    ms_field = _timed(fb_shared.chi2, args.grad_steps, args.warmup, torch)
+    kern_field = _kernel_times(gal, fb_shared.chi2, max(args.grad_steps // 3, 20), torch)
+    ms_field_own = _timed(fb_own.chi2, args.grad_steps, args.warmup, torch)
+    field_c2 = float(fb_shared.chi2()[0])
+    field_match = abs(float(fb_own.chi2()[0]) - field_c2) <= 1e-12 * abs(field_c2)
+    ms_field_call = _timed(lambda: ds.chi2Sources(shared), max(args.grad_steps // 3, 20),
+                           args.warmup, torch)
+    fb_shared.close()
+    fb_own.close()
 
     # ---- batched: K walkers (different profiles and geometry) per step ----
     K = args.batch
@@ -465,6 +489,18 @@ def main():
                  "geometry_plain": {"value": round(1e3 / ms_geo, 1),
                                     "unit": "chi2 + d/d(PA, dRA, dDec, inc) evals/s",
                                     "ms_per_eval": round(ms_geo, 5)}},
+        "field": {"sources": S,
+                  "shared_spectrum": {"value": round(1e3 / ms_field, 1), "unit": "field chi2 evals/s",
+                                      "ms_per_eval": round(ms_field, 5),
+                                      "kernels": rnd(kern_field)},
+                  "transform_per_source": {"value": round(1e3 / ms_field_own, 1),
+                                           "unit": "field chi2 evals/s",
+                                           "ms_per_eval": round(ms_field_own, 5)},
+                  "sharing_gain": round(ms_field_own / ms_field, 3),
+                  "one_shot_call_ms": round(ms_field_call, 5),
+                  "same_chi2": field_match,
+                  "form": f"{S} copies of the 2048^2 profile (one scene) on the M=1e6 dataset; "
+                          "persistent plan, one gal_batch_chi2 per evaluation"},
         "path_roofline": path_roofline,
         "served": served,
         "kernels": rnd(kern),
