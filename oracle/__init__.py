@@ -25,6 +25,7 @@ Functions and the passages they follow:
   grad_image / grad_profile   transpose of the above (not in the paper)
   sample_sources / chi2_sources / grad_sources   Sec. 3.2 (a field of several
                  sources is the sum of their visibilities), on the above
+  get_image_size Sec. 3.4, criteria (i), (iia), (iib)
 """
 from __future__ import annotations
 
@@ -331,3 +332,22 @@ def grad_sources(sources, u, v, re, im, w):
         owner = i if owner is None else owner
         grads[owner] = g if grads[owner] is None else grads[owner] + g
     return c2, grads
+
+
+def get_image_size(u, v, PB=0.0, f_min=5.0, f_max=2.5, Gamma=0.6):
+    """(N, dxy [rad]) for the uv points by the image-size criteria of Sec. 3.4.
+
+    uv cell: criterion (iia), the image spans f_min times the largest
+    recoverable scale Gamma / rho_min, so du = rho_min / (Gamma f_min); with a
+    primary-beam FWHM PB > 0, criterion (iib), the image spans the beam, du =
+    1 / PB.  Size: criterion (i), the grid reaches f_max times the longest
+    baseline, N du / 2 >= f_max rho_max, with N the smallest power of two that
+    does (the advice after the paper's table).  Pixel: dxy = 1 / (N du), so the
+    image keeps the field of (iia) or (iib) exactly."""
+    rho = np.hypot(np.asarray(u, dtype=np.float64), np.asarray(v, dtype=np.float64))
+    rho_min, rho_max = float(rho.min()), float(rho.max())
+    du = 1.0 / PB if PB > 0 else rho_min / (Gamma * f_min)
+    N = 2
+    while N * du / 2.0 < f_max * rho_max:
+        N *= 2
+    return N, 1.0 / (N * du)

@@ -7,6 +7,7 @@ dropped term, a wrong sign or index, or a transposed operand in the oracle
 fails at least one of them.
 """
 import math
+import os
 
 import numpy as np
 import pytest
@@ -560,3 +561,47 @@ def test_grad_sources_matches_central_differences():
     for k in range(p.I.size):
         fd = (f_prof(k, hp) - f_prof(k, -hp)) / (2 * hp)
         assert abs(g[1][k] - fd) <= 1e-6 * np.max(np.abs(g[1])), (k, g[1][k], fd)
+
+
+# ---- image size criteria (Sec. 3.4) -----------------------------------------
+def _matrix_table():
+    rows = []
+    path = os.path.join(os.path.dirname(__file__), "golden", "matrix_sizes_table.txt")
+    for line in open(path):
+        if line.startswith("#") or not line.strip():
+            continue
+        f = line.split()
+        rows.append((f[0] + " " + f[1], float(f[2]), float(f[3]), int(f[4]), float(f[6]),
+                     float(f[7]), float(f[8])))
+    return rows
+
+
+def test_image_size_reproduces_the_paper_table():
+    # every row of the paper's table: N (iia) exactly, the pixel size and the
+    # resolution to the printed digits (f_min = 5, f_max = 2.5, Gamma = 0.6)
+    rows = _matrix_table()
+    assert len(rows) == 14
+    arcsec = np.pi / 648000.0
+    for name, bmin, bmax, N_iia, dth, res, lam in rows:
+        # two points on the extreme baselines, along different directions
+        u = np.array([bmin / lam, 0.0])
+        v = np.array([0.0, bmax / lam])
+        N, dxy = oracle.get_image_size(u, v)
+        assert N == N_iia, (name, N, N_iia)
+        assert abs(dxy / arcsec - dth) <= 0.5e-3 + 1e-12, (name, dxy / arcsec, dth)
+        assert abs(lam / bmax / arcsec - res) <= 0.5e-3 + 1e-12, name
+
+
+def test_image_size_primary_beam_criterion():
+    # (iib): the image spans the beam exactly and the grid is the smallest
+    # power of two reaching f_max rho_max
+    rng = np.random.default_rng(3500)
+    for _ in range(20):
+        r = np.exp(rng.uniform(np.log(1e4), np.log(1e7), 50))
+        a = rng.uniform(0, 2 * np.pi, 50)
+        u, v = r * np.cos(a), r * np.sin(a)
+        PB = rng.uniform(5.0, 60.0) * np.pi / 648000.0
+        N, dxy = oracle.get_image_size(u, v, PB=PB)
+        assert abs(N * dxy - PB) <= 1e-15 * PB
+        du = 1.0 / PB
+        assert N * du / 2 >= 2.5 * r.max() > (N // 2) * du / 2
