@@ -288,6 +288,26 @@ int gal_chi2Profile_geograd_ds_f(const gal_dataset *ds, const float *I, int Nr, 
                                  double dRA, double dDec, double *chi2, double *dgeo, void *ws,
                                  size_t ws_bytes, void *stream);
 
+/* ---- image size (Sec. 3.4, criteria (i), (iia), (iib)) -------------------
+ * Host-side planning from the uv coverage, no device work.  The uv cell is
+ * du = rho_min / (Gamma f_min) -- the image spans f_min times the largest
+ * recoverable scale Gamma / rho_min, criterion (iia) -- or, with a primary-beam
+ * FWHM PB > 0 [rad], du = 1 / PB (criterion (iib)).  Nxy is the smallest power
+ * of two with Nxy du / 2 >= f_max rho_max (criterion (i)) and dxy = 1 / (Nxy du)
+ * [rad].  Typical values: f_min = 5, f_max = 2.5, Gamma = 0.6 (they reproduce
+ * the paper's table of ALMA and VLA configurations).  Errors: GAL_ERR_SCALAR
+ * for f_max <= 2, f_min <= 1 or Gamma <= 0 with PB = 0, rho_min = 0 with PB = 0,
+ * PB < 0, an empty or non-finite uv range; GAL_ERR_SIZE above 2^30.  The
+ * result may exceed the largest image the other calls take (8192).
+ * gal_uv_range_*: shortest and longest baseline of HOST arrays u, v [M]
+ * (M >= 1).  gal_dataset_image_size: from a dataset's registered range. */
+int gal_image_size(double rho_min, double rho_max, double f_min, double f_max, double PB,
+                   double Gamma, int *Nxy, double *dxy);
+int gal_uv_range_d(const double *u, const double *v, int64_t M, double *rho_min, double *rho_max);
+int gal_uv_range_f(const float *u, const float *v, int64_t M, double *rho_min, double *rho_max);
+int gal_dataset_image_size(const gal_dataset *ds, double f_min, double f_max, double PB,
+                           double Gamma, int *Nxy, double *dxy);
+
 /* ---- batches: many chi^2 evaluations per launch --------------------------
  * A batch is a fixed list of jobs, planned once.  Jobs with the same
  * precision, kind and image size share the FFT launches; jobs on the same

@@ -34,6 +34,7 @@ __all__ = [
     "sample_spectrum", "Dataset", "Workspace", "read_status", "timing", "GalarioError",
     "version", "init", "autotune", "autotune_batch", "tune_get", "tune_set", "Batch", "profile_batch",
     "JOB_IMAGE", "JOB_PROFILE", "batch_exec", "chi2Image_grad", "chi2Profile_grad", "chi2_profile", "chi2_image",
+    "get_image_size",
 ]
 
 JOB_IMAGE = 0
@@ -309,6 +310,32 @@ def sample_spectrum(spec, dxy, u, v, PA=0.0, dRA=0.0, dDec=0.0, inc=0.0,
 
 
 # ----------------------------------------------------------------------------
+def get_image_size(u, v, PB: float = 0.0, f_min: float = 5.0, f_max: float = 2.5,
+                   Gamma: float = 0.6):
+    """(Nxy, dxy [rad]) for the uv points by the criteria of Sec. 3.4
+    (gal_image_size): the image spans f_min times the largest recoverable scale
+    Gamma / rho_min (or, with PB > 0, the primary beam of FWHM PB [rad]), the
+    grid reaches f_max times the longest baseline, Nxy a power of two.  u, v:
+    numpy arrays or tensors (read on the host)."""
+    import numpy as np
+
+    host = [np.ascontiguousarray(x.detach().cpu().numpy() if isinstance(x, torch.Tensor) else x)
+            for x in (u, v)]
+    if host[0].dtype != host[1].dtype or host[0].dtype not in (np.float64, np.float32):
+        raise TypeError("u and v must both be float64 or both float32")
+    if host[0].shape != host[1].shape:
+        raise ValueError("u and v must have the same shape")
+    sfx = "_d" if host[0].dtype == np.float64 else "_f"
+    lo, hi = ctypes.c_double(0), ctypes.c_double(0)
+    check(getattr(_lib(), "gal_uv_range" + sfx)(host[0].ctypes.data, host[1].ctypes.data,
+                                                host[0].size, ctypes.byref(lo), ctypes.byref(hi)),
+          "get_image_size")
+    n, d = ctypes.c_int(0), ctypes.c_double(0)
+    check(_lib().gal_image_size(lo.value, hi.value, float(f_min), float(f_max), float(PB),
+                                float(Gamma), ctypes.byref(n), ctypes.byref(d)), "get_image_size")
+    return int(n.value), float(d.value)
+
+
 class Dataset:
     """An observation registered once in library-owned device memory.
 
@@ -336,6 +363,15 @@ class Dataset:
         check(_lib().gal_dataset_info(h, ctypes.byref(m), ctypes.byref(rho), ctypes.byref(prec)),
               "gal_dataset_info")
         self.rho_max = float(rho.value)
+
+    def image_size(self, PB: float = 0.0, f_min: float = 5.0, f_max: float = 2.5,
+                   Gamma: float = 0.6):
+        """(Nxy, dxy) for this dataset's uv range (as ``get_image_size``)."""
+        n, d = ctypes.c_int(0), ctypes.c_double(0)
+        check(_lib().gal_dataset_image_size(self._h, float(f_min), float(f_max), float(PB),
+                                            float(Gamma), ctypes.byref(n), ctypes.byref(d)),
+              "Dataset.image_size")
+        return int(n.value), float(d.value)
 
     def geometry(self, Nxy, dxy):
         """(Q, P): columns [0, Q) and rows [-P, P] of the half spectrum that

@@ -64,6 +64,9 @@ _SIG = {
     "gal_geograd_workspace_bytes_f": (SZ, [I, I64]),
     "gal_chi2Image_geograd_ds": (I, [P, P, I, D, D, D, D, D, P, P, P, SZ, P]),
     "gal_chi2Profile_geograd_ds": (I, [P, P, I, D, D, I, D, D, D, D, D, P, P, P, SZ, P]),
+    "gal_image_size": (I, [D, D, D, D, D, D, ctypes.POINTER(I), ctypes.POINTER(D)]),
+    "gal_uv_range": (I, [P, P, I64, ctypes.POINTER(D), ctypes.POINTER(D)]),
+    "gal_dataset_image_size": (I, [P, D, D, D, D, ctypes.POINTER(I), ctypes.POINTER(D)]),
     "gal_batch_create": (I, [P, I, ctypes.POINTER(P)]),
     "gal_batch_workspace_bytes": (SZ, [P]),
     "gal_batch_info": (I, [P, ctypes.POINTER(I), ctypes.POINTER(I), ctypes.POINTER(I)]),
@@ -84,7 +87,7 @@ _PRECISION_SUFFIXED = {
     "gal_spectrum", "gal_sample_spectrum", "gal_dataset_create", "gal_chi2Image_ds",
     "gal_chi2Profile_ds", "gal_sampleImage_ds", "gal_sampleProfile_ds", "gal_autotune",
     "gal_chi2Image_grad", "gal_chi2Profile_grad", "gal_chi2Image_grad_ds", "gal_chi2Profile_grad_ds",
-    "gal_chi2Image_geograd_ds", "gal_chi2Profile_geograd_ds",
+    "gal_chi2Image_geograd_ds", "gal_chi2Profile_geograd_ds", "gal_uv_range",
 }
 
 

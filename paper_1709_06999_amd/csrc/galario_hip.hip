@@ -837,6 +837,7 @@ struct gal_dataset {
     int device;
     int64_t M;
     double rho_max;
+    double rho_min;  // shortest baseline (image-size criterion (iia))
     void *buf;      // one allocation: u, v, re, im, w, perm (locality order)
     void *u, *v, *re, *im, *w;
     int32_t *perm;  // perm[k] = registration index of stored point k
@@ -1156,13 +1157,14 @@ static int dataset_create(const T *u, const T *v, const T *re, const T *im, cons
     for (int c = 0; c < n_cols && M > 0; ++c)
         GAL_HIP(hipMemcpyAsync(h[c].data(), src[c], (size_t)M * sizeof(T), hipMemcpyDeviceToHost, s));
     GAL_HIP(hipStreamSynchronize(s));
-    double r2max = 0.0;
+    double r2max = 0.0, r2min = M > 0 ? INFINITY : 0.0;
     for (int64_t k = 0; k < M; ++k) {
         const double uu = h[0][k], vv = h[1][k];
         const double r2 = uu * uu + vv * vv;
         if (!std::isfinite(r2)) return fail(GAL_ERR_SCALAR, "non-finite uv coordinate at %lld",
                                             (long long)k);
         r2max = r2 > r2max ? r2 : r2max;
+        r2min = r2 < r2min ? r2 : r2min;
     }
     const double rho_max = std::sqrt(r2max);
     // locality order
@@ -1186,6 +1188,7 @@ static int dataset_create(const T *u, const T *v, const T *re, const T *im, cons
     GAL_HIP(hipGetDevice(&ds->device));
     ds->M = M;
     ds->rho_max = rho_max;
+    ds->rho_min = std::sqrt(r2min);
     const size_t col = align256((size_t)(M > 0 ? M : 1) * sizeof(T));
     const size_t pcol = align256((size_t)(M > 0 ? M : 1) * sizeof(int32_t));
     if (hipMalloc(&ds->buf, col * n_cols + pcol) != hipSuccess) {
@@ -1243,6 +1246,65 @@ int gal_dataset_info(const gal_dataset *ds, int64_t *M, double *rho_max, int *pr
     if (rho_max) *rho_max = ds->rho_max;
     if (precision) *precision = ds->precision;
     return GAL_OK;
+}
+
+// ---- image size (Sec. 3.4 criteria) ---------------------------------------
+int gal_image_size(double rho_min, double rho_max, double f_min, double f_max, double PB,
+                   double Gamma, int *Nxy, double *dxy) {
+    if (!Nxy || !dxy) return fail(GAL_ERR_NULL, "NULL output");
+    if (!(f_max > 2.0) || !std::isfinite(f_max)) return fail(GAL_ERR_SCALAR, "f_max must be > 2");
+    if (!(PB >= 0.0) || !std::isfinite(PB)) return fail(GAL_ERR_SCALAR, "PB must be >= 0");
+    if (!(rho_max > 0.0) || !std::isfinite(rho_max) || !(rho_min <= rho_max))
+        return fail(GAL_ERR_SCALAR, "uv range [%g, %g] unusable", rho_min, rho_max);
+    double du;
+    if (PB > 0.0) {
+        du = 1.0 / PB;  // (iib): the image spans the primary beam
+    } else {
+        if (!(f_min > 1.0) || !std::isfinite(f_min)) return fail(GAL_ERR_SCALAR, "f_min must be > 1");
+        if (!(Gamma > 0.0) || !std::isfinite(Gamma)) return fail(GAL_ERR_SCALAR, "Gamma must be > 0");
+        if (!(rho_min > 0.0)) return fail(GAL_ERR_SCALAR, "criterion (iia) needs rho_min > 0");
+        du = rho_min / (Gamma * f_min);  // (iia): f_min times the largest recoverable scale
+    }
+    // (i): the grid reaches f_max times the longest baseline; N a power of two
+    int64_t n = 2;
+    while ((double)n * du / 2.0 < f_max * rho_max) {
+        n *= 2;
+        if (n > ((int64_t)1 << 30)) return fail(GAL_ERR_SIZE, "image size above 2^30");
+    }
+    *Nxy = (int)n;
+    *dxy = 1.0 / ((double)n * du);
+    return GAL_OK;
+}
+
+template <typename T>
+static int uv_range(const T *u, const T *v, int64_t M, double *rho_min, double *rho_max) {
+    if (!rho_min || !rho_max) return fail(GAL_ERR_NULL, "NULL output");
+    if (M < 1) return fail(GAL_ERR_SIZE, "M < 1");
+    if (!u || !v) return fail(GAL_ERR_NULL, "NULL u or v");
+    double lo = INFINITY, hi = 0.0;
+    for (int64_t k = 0; k < M; ++k) {
+        const double uu = u[k], vv = v[k];
+        const double r = std::sqrt(uu * uu + vv * vv);
+        if (!std::isfinite(r)) return fail(GAL_ERR_SCALAR, "non-finite uv coordinate at %lld", (long long)k);
+        lo = r < lo ? r : lo;
+        hi = r > hi ? r : hi;
+    }
+    *rho_min = lo;
+    *rho_max = hi;
+    return GAL_OK;
+}
+int gal_uv_range_d(const double *u, const double *v, int64_t M, double *rho_min, double *rho_max) {
+    return uv_range(u, v, M, rho_min, rho_max);
+}
+int gal_uv_range_f(const float *u, const float *v, int64_t M, double *rho_min, double *rho_max) {
+    return uv_range(u, v, M, rho_min, rho_max);
+}
+
+int gal_dataset_image_size(const gal_dataset *ds, double f_min, double f_max, double PB,
+                           double Gamma, int *Nxy, double *dxy) {
+    if (!ds) return fail(GAL_ERR_NULL, "NULL dataset");
+    if (ds->M < 1) return fail(GAL_ERR_SIZE, "empty dataset");
+    return gal_image_size(ds->rho_min, ds->rho_max, f_min, f_max, PB, Gamma, Nxy, dxy);
 }
 
 int gal_dataset_geometry(const gal_dataset *ds, int Nxy, double dxy, int *Q, int *P) {

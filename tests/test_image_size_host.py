@@ -1,0 +1,73 @@
+"""Image size from the uv coverage (Sec. 3.4): the library's host-side planner
+against the oracle on the paper's table and on random coverages, and its
+argument checks.  No device work: runs without a GPU."""
+import math
+import os
+
+import numpy as np
+import pytest
+
+import oracle
+
+
+def _gal():
+    pytest.importorskip("torch")
+    import paper_1709_06999_amd as gal
+
+    return gal
+
+
+def _table():
+    path = os.path.join(os.path.dirname(__file__), "golden", "matrix_sizes_table.txt")
+    for line in open(path):
+        if line.startswith("#") or not line.strip():
+            continue
+        f = line.split()
+        yield f[0] + " " + f[1], float(f[2]), float(f[3]), float(f[8])
+
+
+def test_library_matches_oracle_on_the_paper_table():
+    gal = _gal()
+    for name, bmin, bmax, lam in _table():
+        u = np.array([bmin / lam, 0.0, 0.3 * bmax / lam])
+        v = np.array([0.0, bmax / lam, 0.1 * bmax / lam])
+        assert gal.get_image_size(u, v) == oracle.get_image_size(u, v), name
+
+
+@pytest.mark.parametrize("dtype", [np.float64, np.float32])
+def test_library_matches_oracle_on_random_coverages(dtype):
+    gal = _gal()
+    rng = np.random.default_rng(3600)
+    for _ in range(50):
+        M = int(rng.integers(1, 2000))
+        r = np.exp(rng.uniform(np.log(1e3), np.log(2e7), M))
+        a = rng.uniform(0, 2 * np.pi, M)
+        u, v = (r * np.cos(a)).astype(dtype), (r * np.sin(a)).astype(dtype)
+        kw = dict(f_min=rng.uniform(1.5, 8.0), f_max=rng.uniform(2.1, 4.0),
+                  Gamma=rng.uniform(0.4, 0.8))
+        if rng.random() < 0.3:
+            kw["PB"] = rng.uniform(5.0, 60.0) * math.pi / 648000.0
+        N, d = gal.get_image_size(u, v, **kw)
+        No, do = oracle.get_image_size(u.astype(np.float64), v.astype(np.float64), **kw)
+        assert N == No
+        assert abs(d - do) <= 1e-15 * do
+
+
+def test_argument_checks():
+    gal = _gal()
+    u, v = np.array([1e4, 2e5]), np.array([0.0, 1e5])
+    for kw in (dict(f_max=2.0), dict(f_min=1.0), dict(Gamma=0.0), dict(PB=-1.0)):
+        with pytest.raises(gal.GalarioError):
+            gal.get_image_size(u, v, **kw)
+    # a zero-length baseline: (iia) is undefined, (iib) is not
+    u0, v0 = np.array([0.0, 2e5]), np.array([0.0, 1e5])
+    with pytest.raises(gal.GalarioError):
+        gal.get_image_size(u0, v0)
+    N, d = gal.get_image_size(u0, v0, PB=1e-4)
+    assert abs(N * d - 1e-4) <= 1e-19
+    with pytest.raises(gal.GalarioError):
+        gal.get_image_size(np.array([]), np.array([]))
+    with pytest.raises(gal.GalarioError):
+        gal.get_image_size(np.array([np.nan, 1.0]), np.array([0.0, 1.0]))
+    with pytest.raises(gal.GalarioError):  # beyond 2^30
+        gal.get_image_size(np.array([1.0, 1e12]), np.array([0.0, 0.0]))
