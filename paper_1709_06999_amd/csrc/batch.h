@@ -127,6 +127,14 @@ __global__ __launch_bounds__(Cfg::NT) void kb_rows_sym(const JobDesc *__restrict
 }
 
 template <typename T, typename Cfg>
+__global__ __launch_bounds__(Cfg::NT) void kb_rows_even(const JobDesc *__restrict__ jobs,
+                                                        const int *__restrict__ list, char *ws) {
+    const JobDesc &j = jobs[list[blockIdx.y]];
+    rows_even_body<T, Cfg, gptr<T>>(as_global<T>(j.src), sweep_of(j), geom_of(j), j.Qe,
+                                    (T *)(ws + j.spec_off), xcd_remap(blockIdx.x, gridDim.x));
+}
+
+template <typename T, typename Cfg>
 __global__ __launch_bounds__(Cfg::NT) void kb_cols_sym(const JobDesc *__restrict__ jobs,
                                                        const int *__restrict__ list, char *ws) {
     const JobDesc &j = jobs[list[blockIdx.y]];

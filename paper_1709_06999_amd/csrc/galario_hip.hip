@@ -218,13 +218,22 @@ static int run_cols(const FftJob<T> &j) {
     using C = CfgE<T, N, B, var_E(VAR)>;
     return launch("k_cols", k_cols<T, C>, dim3((j.g.Q + B - 1) / B), dim3(C::NT), j.s, j.g, j.buf);
 }
+// rows of a swept profile: variant 1 transforms each row pair at full length
+// (rows_sym_body, E = 8); variants 0 and 2 use the half-length transform of
+// even rows (rows_even_body, E = 8 and 4)
 template <typename T, int N, int VAR>
 static int run_rows_sym(const FftJob<T> &j) {
     constexpr int B = cols_B(N);
-    using C = CfgE<T, N, B, var_E(VAR)>;
     const int pairs = N / 4 + 1;
-    return launch("k_rows_sym", k_rows_sym<T, C>, dim3((pairs + B - 1) / B), dim3(C::NT), j.s,
-                  j.src, j.sw, j.g, j.Qe, j.buf);
+    if constexpr (VAR == 1) {
+        using C = CfgE<T, N, B, 8>;
+        return launch("k_rows_sym", k_rows_sym<T, C>, dim3((pairs + B - 1) / B), dim3(C::NT), j.s,
+                      j.src, j.sw, j.g, j.Qe, j.buf);
+    } else {
+        using C = CfgE<T, N / 2, B, VAR == 0 ? 8 : 4>;
+        return launch("k_rows_even", k_rows_even<T, C>, dim3((pairs + B - 1) / B), dim3(C::NT),
+                      j.s, j.src, j.sw, j.g, j.Qe, j.buf);
+    }
 }
 template <typename T, int N, int VAR>
 static int run_cols_sym(const FftJob<T> &j) {
@@ -345,9 +354,15 @@ static int runb_cols(const FftJobB &j) {
 template <typename T, int N, int VAR>
 static int runb_rows_sym(const FftJobB &j) {
     constexpr int B = cols_B(N);
-    using C = CfgE<T, N, B, var_E(VAR)>;
-    return launch("kb_rows_sym", kb_rows_sym<T, C>, dim3((N / 4 + 1 + B - 1) / B, j.count),
-                  dim3(C::NT), j.s, j.jobs, j.list, j.ws);
+    if constexpr (VAR == 1) {
+        using C = CfgE<T, N, B, 8>;
+        return launch("kb_rows_sym", kb_rows_sym<T, C>, dim3((N / 4 + 1 + B - 1) / B, j.count),
+                      dim3(C::NT), j.s, j.jobs, j.list, j.ws);
+    } else {
+        using C = CfgE<T, N / 2, B, VAR == 0 ? 8 : 4>;
+        return launch("kb_rows_even", kb_rows_even<T, C>, dim3((N / 4 + 1 + B - 1) / B, j.count),
+                      dim3(C::NT), j.s, j.jobs, j.list, j.ws);
+    }
 }
 template <typename T, int N, int VAR>
 static int runb_cols_sym(const FftJobB &j) {

@@ -312,6 +312,143 @@ __device__ __forceinline__ void rows_sym_body(PI I, const SweepArgs &sw, const G
     });
 }
 
+// sum over the 64 lanes of a wave (every lane gets it)
+__device__ __forceinline__ double wave_sum(double x) {
+#pragma unroll
+    for (int o = 32; o >= 1; o >>= 1) x += __shfl_xor(x, o, 64);
+    return x;
+}
+
+// exclusive prefix sum over the 64 lanes of a wave (lane order)
+__device__ __forceinline__ double wave_excl_scan(double x) {
+    const int lane = threadIdx.x & 63;
+    double incl = x;
+#pragma unroll
+    for (int o = 1; o < 64; o <<= 1) {
+        const double y = __shfl_up(incl, o, 64);
+        if (lane >= o) incl += y;
+    }
+    const double e = __shfl_up(incl, 1, 64);
+    return lane == 0 ? 0.0 : e;
+}
+
+// Row pass of a swept profile by half-length transforms.  A row x of the
+// (centred) swept image is real and even, x[n] = x[N - n], so its spectrum is
+// real and even as well, and X[k] for k <= N/2 follows from one real DFT of
+// length h = N/2 (the two rows of a pair share one complex transform).  With
+//   a[n] = x[n] + x[h - n],  b[n] = x[n] - x[h - n]   (n in [0, h)),
+// the even outputs are the (real) DFT of a, X[2m] = sum_n a[n] cos(2 pi n m / h),
+// and the odd ones X[2m+1] = sum_n b[n] cos(pi n (2m+1) / h) obey
+//   X[2m+1] - X[2m-1] = -2 sum_n b[n] sin(pi n / h) sin(2 pi n m / h),
+// the (imaginary) DFT of the odd sequence b[n] sin(pi n / h).  So with
+//   y[n] = a[n] + sin(pi n / h) b[n],  Y = DFT_h(y):
+//   X[2m] = Re Y[m],  X[2m+1] = X[1] + 2 sum_{j=1..m} Im Y[j],
+//   X[1] = sum_n b[n] cos(pi n / h).
+// Half the FFT work of the length-N transform of rows_sym_body; the odd
+// outputs come from a prefix sum (in FP64) over the kept columns.  Same
+// output as rows_sym_body: XR[q * CS + r] = (-1)^q X_r[q], q < Qe.
+template <typename T, typename Cfg, typename PI, bool TANGENT = false>
+__device__ __forceinline__ void rows_even_body(PI I, const SweepArgs &sw, const Geom &g, int Qe,
+                                               T *__restrict__ XR, int blk) {
+    constexpr int L = Cfg::L, B = Cfg::B, NT = Cfg::NT, E = Cfg::E;
+    constexpr int H = L, N = 2 * L;
+    constexpr int R0 = pass_radix(L, 1, Cfg::RMAX);
+    constexpr int LR = L / R0;
+    constexpr int NW = NT >= 64 ? NT / 64 : 1;
+    __shared__ c2<T> lds[B * Cfg::LS];
+    __shared__ c2<T> xh[B];               // x[h] of each row pair
+    __shared__ c2<double> part[B * LR];   // per-butterfly parts of X[1]
+    const int tid = threadIdx.x;
+    const int m0 = blk * B;
+
+    // sweep: columns c in [0, h] (c and N - c hold the same pixel)
+    for (int idx = tid; idx < B * (H + 1); idx += NT) {
+        const int b = idx / (H + 1), c = idx % (H + 1);
+        const int r = 2 * (m0 + b);  // rows r, r + 1
+        c2<T> px;
+        if constexpr (TANGENT)
+            px = c2<T>{(T)sweep_pixel_dinc(I, N, r, c, sw), (T)sweep_pixel_dinc(I, N, r + 1, c, sw)};
+        else
+            px = c2<T>{(T)sweep_pixel(I, N, r, c, sw), (T)sweep_pixel(I, N, r + 1, c, sw)};
+        if (c < H) lds[Cfg::at(b, c)] = px;
+        else xh[b] = px;
+    }
+    __syncthreads();
+    const c2<T> *tw = twiddles<T>();
+    const c2<T> *wN = tw + N;  // exp(-2 pi i n / N) = (cos(pi n / h), -sin(pi n / h))
+    c2<T> v[E];
+#pragma unroll
+    for (int i = 0; i < E / R0; ++i) {
+        const int gi = tid + i * NT;  // butterfly gi = b * LR + j of the first pass
+        const int b = gi / LR, j = gi % LR;
+        double p1 = 0.0, p2 = 0.0;
+#pragma unroll
+        for (int t = 0; t < R0; ++t) {
+            const int n = j + t * LR;
+            const c2<T> xa = lds[Cfg::at(b, n)];
+            const c2<T> xb = n == 0 ? xh[b] : lds[Cfg::at(b, H - n)];
+            const c2<T> w = wN[n];
+            const T b1 = xa.x - xb.x, b2 = xa.y - xb.y;
+            v[i * R0 + t] = c2<T>{xa.x + xb.x - w.y * b1, xa.y + xb.y - w.y * b2};
+            p1 += (double)w.x * (double)b1;
+            p2 += (double)w.x * (double)b2;
+        }
+        part[gi] = c2<double>{p1, p2};
+    }
+    // (the first pass's barrier orders these LDS reads before its writes)
+    fft_passes<Cfg, 1>(v, lds, tw, tid);
+
+    // one wave per row pair: X[1] in a fixed order, then the outputs with the
+    // prefix sum of the odd ones over contiguous runs of m per lane
+    const int wave = tid >> 6, lane = tid & 63;
+    const int Mq = Qe / 2;  // m in [0, Mq): columns 2m and 2m + 1 < Qe (Qe even, <= h + 2)
+    const int ch = (Mq + 63) / 64;
+    const int mb = lane * ch, me = min(mb + ch, Mq);
+    for (int b = wave; b < B; b += NW) {
+        const int r = 2 * (m0 + b);
+        if (r > N / 2) continue;
+        double x1 = 0.0, x2 = 0.0;
+        for (int k = lane; k < LR; k += 64) {
+            x1 += part[b * LR + k].x;
+            x2 += part[b * LR + k].y;
+        }
+        x1 = wave_sum(x1);
+        x2 = wave_sum(x2);
+        // 2 Im Y[m] of each row from Z[m], Z[h - m] (Y1 = (Z[m] + conj Z[h-m]) / 2,
+        // Y2 = (Z[m] - conj Z[h-m]) / 2i)
+        double t1 = 0.0, t2 = 0.0;
+        for (int m = mb; m < me; ++m) {
+            const c2<T> z = lds[Cfg::at(b, m)], zc = lds[Cfg::at(b, (H - m) & (H - 1))];
+            t1 += (double)z.y - (double)zc.y;
+            t2 += (double)zc.x - (double)z.x;
+        }
+        double a1 = x1 + wave_excl_scan(t1), a2 = x2 + wave_excl_scan(t2);
+        for (int m = mb; m < me; ++m) {
+            const c2<T> z = lds[Cfg::at(b, m)], zc = lds[Cfg::at(b, (H - m) & (H - 1))];
+            a1 += (double)z.y - (double)zc.y;
+            a2 += (double)zc.x - (double)z.x;
+            const c2<T> ev{(T)(0.5 * ((double)z.x + (double)zc.x)),
+                           (T)(0.5 * ((double)z.y + (double)zc.y))};  // X[2m]
+            const c2<T> od{(T)(-a1), (T)(-a2)};                       // -X[2m+1]
+            T *dst = XR + (size_t)(2 * m) * g.CS + r;
+            if (r + 1 <= N / 2) {
+                *reinterpret_cast<c2<T> *>(dst) = ev;
+                if (2 * m + 1 < Qe) *reinterpret_cast<c2<T> *>(dst + g.CS) = od;
+            } else {
+                dst[0] = ev.x;
+                if (2 * m + 1 < Qe) dst[g.CS] = od.x;
+            }
+        }
+    }
+}
+
+template <typename T, typename Cfg, bool TANGENT = false>
+__global__ __launch_bounds__(Cfg::NT) void k_rows_even(const T *__restrict__ I, SweepArgs sw,
+                                                       Geom g, int Qe, T *__restrict__ XR) {
+    rows_even_body<T, Cfg, const T *__restrict__, TANGENT>(I, sw, g, Qe, XR,
+                                                           xcd_remap(blockIdx.x, gridDim.x));
+}
+
 template <typename T, typename Cfg, bool TANGENT = false>
 __global__ __launch_bounds__(Cfg::NT) void k_rows_sym(const T *__restrict__ I, SweepArgs sw,
                                                       Geom g, int Qe, T *__restrict__ XR) {
@@ -448,11 +585,6 @@ __device__ __forceinline__ void finish(const Stencil<T> &st, c2<T> a00, c2<T> a1
     Vim = br * sn + bi * cs;
 }
 
-__device__ __forceinline__ double wave_sum(double x) {
-#pragma unroll
-    for (int o = 32; o >= 1; o >>= 1) x += __shfl_xor(x, o, 64);
-    return x;
-}
 
 // sum over the block in a fixed order; result valid in thread 0
 __device__ __forceinline__ double block_sum(double x, double *red) {
