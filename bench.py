@@ -63,7 +63,7 @@ def algorithmic_bytes(N, Nr, M, Q, P, kind="profile", p=8):
         Qe = Q + (Q & 1)
         inter = (N // 2 + 1) * Qe * p
         spec = (P + 1) * Qe * p
-        return {"k_rows_sym": Nr * p + inter, "k_cols_sym": inter + spec,
+        return {"k_rows_sym": Nr * p + inter, "k_rows_even": Nr * p + inter, "k_cols_sym": inter + spec,
                 "k_sample_sym_chi2": 5 * p * M + spec, "k_reduce": red}
     inter = N * Q * 2 * p
     spec = Q * (2 * P + 1) * 2 * p
@@ -83,13 +83,29 @@ def path_bytes(N, Nr, M, p=8):
     return {"chi2": chi2, "chi2_grad": chi2 + 2 * p * M + 5 * p * M + 4 * (2 * p * H) + p * Nr}
 
 
+# algorithmic FP64 operations per unit (FMA = 2, sin / cos / sqrt = 1 each)
+SWEEP_FLOPS_PER_PIXEL = 13   # x, y 2, x / cos(inc) 1, rho^2 2, sqrt 1, t 2, fraction 1, lerp 3, area 1
+SAMPLE_FLOPS_PER_POINT = 35  # per profile job and uv point: rotation 6, grid scale 2, fractions
+                             # 2, bilinear 11, phase argument 3, sin + cos 2, V 2, chi^2 term 7
+
+
 def fft_flops(N, Q, K=1):
-    """Algorithmic flops of the two FFT passes of the profile path for K jobs,
-    counted as 5 L log2 L per complex FFT of length L: the row pass transforms
-    rows [0, N/2] two at a time, the column pass columns [0, Qe) two at a time."""
+    """Algorithmic flops of the two FFT passes of the profile path for K jobs.
+    Row pass: the sweep of the quarter image ((N/2+1)^2 pixels) and, per pair
+    of (even) rows, a complex FFT of length N/2 at 5 L log2 L plus 12 flops per
+    point of pre- and post-processing -- the half-length transform, whichever
+    variant runs (the full-length one does redundant work).  Column pass:
+    columns [0, Qe) two at a time, complex FFT of length N."""
     Qe = Q + (Q & 1)
-    per = 5.0 * N * math.log2(N)
-    return {"kb_rows_sym": K * ((N // 2 + 2) // 2) * per, "kb_cols_sym": K * (Qe // 2) * per}
+    h = N // 2
+    rows = (N // 4 + 1) * (5.0 * h * math.log2(h) + 12.0 * h) + (h + 1) ** 2 * SWEEP_FLOPS_PER_PIXEL
+    cols = (Qe // 2) * 5.0 * N * math.log2(N)
+    return {"kb_rows_sym": K * rows, "kb_rows_even": K * rows, "kb_cols_sym": K * cols}
+
+
+def sample_flops(M, K=1):
+    """Algorithmic flops of the sampling pass: K profile jobs at M points."""
+    return {"kb_sample_sym_chi2": float(K) * M * SAMPLE_FLOPS_PER_POINT}
 
 
 def source_digest():
@@ -226,6 +242,9 @@ def main():
                     help="fixed FFT variants rows_image,cols,rows_sym,cols_sym (0: E=16, 1: E=8, "
                          "2: E=4) instead of autotuning, e.g. for counter runs that must see "
                          "the same kernels")
+    ap.add_argument("--fft-variants-batch", default=None,
+                    help="fixed FFT variants for the batched sections (default: as "
+                         "--fft-variants, else autotuned on the batch)")
     ap.add_argument("--no-serve", action="store_true", help="skip the served-load section")
     ap.add_argument("--serve-only", action="store_true",
                     help="run only the served-load section and print its JSON (profiling aid)")
@@ -343,7 +362,10 @@ def main():
     batch = gal.profile_batch(ds, Ib, geob, N, case.dxy)
     batch_tune_ms = {}
     tuned_plain = list(tuned)
-    if not args.fft_variants:
+    if args.fft_variants_batch:
+        tuned = [int(x) for x in args.fft_variants_batch.split(",")]
+        gal.tune_set(N, tuned, torch.float64)
+    elif not args.fft_variants:
         tuned = gal.autotune_batch(batch, N, torch.float64, times=batch_tune_ms)
     step = batch.chi2
     graph = None
@@ -377,7 +399,8 @@ def main():
     ab = algorithmic_bytes(N, Nr, M, Q, P, "profile")
     Qe = Q + (Q & 1)
     spec = (P + 1) * Qe * 8
-    ab_batch = {"kb_rows_sym": K * ab["k_rows_sym"], "kb_cols_sym": K * ab["k_cols_sym"],
+    ab_batch = {"kb_rows_sym": K * ab["k_rows_sym"], "kb_rows_even": K * ab["k_rows_sym"],
+                "kb_cols_sym": K * ab["k_cols_sym"],
                 "kb_sample_sym_chi2": 5 * 8 * M + K * spec, "kb_reduce": K * ab["k_reduce"]}
     for k in kern:
         if k in ab_batch:
@@ -387,12 +410,12 @@ def main():
         if k in ab:
             kern_plain[k]["alg_bytes"] = ab[k]
             kern_plain[k]["alg_GBps"] = ab[k] / (kern_plain[k]["avg_us"] * 1e-6) / 1e9
-    fl_batch = fft_flops(N, Q, K)
+    fl_batch = {**fft_flops(N, Q, K), **sample_flops(M, K)}
     for k in kern:
         if k in fl_batch:
             kern[k]["alg_flops"] = fl_batch[k]
             kern[k]["alg_TFLOPs"] = fl_batch[k] / (kern[k]["avg_us"] * 1e-6) / 1e12
-    fl_plain = fft_flops(N, Q, 1)
+    fl_plain = {**fft_flops(N, Q, 1), **sample_flops(M, 1)}
     for k in kern_plain:
         kk = k.replace("k_", "kb_", 1)
         if kk in fl_plain:
@@ -400,7 +423,8 @@ def main():
             kern_plain[k]["alg_TFLOPs"] = fl_plain[kk] / (kern_plain[k]["avg_us"] * 1e-6) / 1e12
     dom = max((k for k in kern if k in ab_batch), key=lambda k: kern[k]["avg_us"])
     if dom in fl_batch:
-        # FFT passes: FP64 arithmetic bounds them (their HBM bytes take far less)
+        # FFT passes, and the sampler with K jobs per point: FP64 arithmetic and
+        # its issue bound them (their HBM bytes take far less)
         achieved = kern[dom]["alg_TFLOPs"]
         roofline = {"bound": "alu", "kernel": dom, "achieved": round(achieved, 3),
                     "peak": FP64_PEAK_TFLOPS, "unit": "TFLOP/s",
@@ -414,9 +438,9 @@ def main():
                     "peak": HBM_PEAK_GBS, "unit": "GB/s",
                     "frac": round(achieved / HBM_PEAK_GBS, 4),
                     "traffic": stored_traffic(dom), "alg_bytes_per_launch": ab_batch[dom]}
-    roofline["step_alg_bytes"] = sum(ab_batch.values())
-    roofline["step_hbm_frac"] = round(sum(ab_batch.values()) / (ms_batch * 1e-3) / 1e9 /
-                                      HBM_PEAK_GBS, 4)
+    step_bytes = sum(ab_batch[k] for k in kern if k in ab_batch)  # the kernels the step ran
+    roofline["step_alg_bytes"] = step_bytes
+    roofline["step_hbm_frac"] = round(step_bytes / (ms_batch * 1e-3) / 1e9 / HBM_PEAK_GBS, 4)
 
     pb = path_bytes(N, Nr, M)
     path_roofline = {

@@ -280,11 +280,11 @@ __global__ __launch_bounds__(SAMPLE_NT) void k_sample_scatter(
             const double s = st.s, t = st.t;
             const double b = (1.0 - t) * ((1.0 - s) * a00 + s * a01) +
                              t * ((1.0 - s) * a10 + s * a11);
-            const double Vre = a.cinc * b * cs, Vim = a.cinc * b * sn;
+            const double Vre = b * cs, Vim = b * sn;  // cos(inc) = 1 on real spectra
             const double rr = (double)re[k] - Vre, ri = (double)im[k] - Vim;
             acc += (double)w[k] * (rr * rr + ri * ri);
             // Re(conj(R) e^{i theta}) = rr cs + ri sn
-            pa[p] = point_add_real<T>(st, (double)w[k] * a.cinc * (rr * cs + ri * sn));
+            pa[p] = point_add_real<T>(st, (double)w[k] * (rr * cs + ri * sn));
         } else {
             const c2<T> *Sc = (const c2<T> *)S;
             const Stencil<T> st = locate<T>(Sc, g, a, uu, vv);

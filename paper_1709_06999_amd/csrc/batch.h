@@ -41,6 +41,7 @@ struct JobDesc {
     // constants of the job's geometry, written by kb_prepare at the head of
     // every execution (geo may change between executions)
     double cpa, spa, cinc, dRA, dDec;  // sampling
+    double cpa_du, spa_du;             // cos PA, sin PA times N dxy
     double Rmin, inv_dR, inv_cos;      // sweep (profiles)
 };
 
@@ -56,6 +57,8 @@ __global__ __launch_bounds__(64) void kb_prepare(JobDesc *__restrict__ jobs, int
     const double ci = cos(geo[2]);
     j.cpa = cs;
     j.spa = sn;
+    j.cpa_du = cs * ((double)j.N * j.dxy);
+    j.spa_du = sn * ((double)j.N * j.dxy);
     j.cinc = j.kind == 1 ? 1.0 : ci;
     j.dRA = geo[4];
     j.dDec = geo[5];
@@ -92,6 +95,8 @@ __device__ __forceinline__ SampleArgs sample_from_job(const JobDesc &j, int64_t 
     a.cpa = j.cpa;
     a.spa = j.spa;
     a.cinc = j.cinc;
+    a.cpa_du = j.cpa_du;
+    a.spa_du = j.spa_du;
     a.dRA = j.dRA;
     a.dDec = j.dDec;
     a.jmax = min(j.Q - 2, j.N / 2 - 1);
@@ -165,8 +170,8 @@ __device__ __forceinline__ JobPoint<T, REAL> job_point(const JobDesc &J, const S
         const double a00 = st.swap ? x1 : x0, a10 = st.swap ? x0 : x1;
         const double a01 = st.swap ? y1 : y0, a11 = st.swap ? y0 : y1;
         const double s = st.s, t = st.t;
-        const double b = a.cinc * ((1.0 - t) * ((1.0 - s) * a00 + s * a01) +
-                                   t * ((1.0 - s) * a10 + s * a11));
+        const double b = (1.0 - t) * ((1.0 - s) * a00 + s * a01) +
+                         t * ((1.0 - s) * a10 + s * a11);  // cos(inc) = 1 on real spectra
         r.Vre = st.ok ? b * r.cs : __builtin_nan("");
         r.Vim = st.ok ? b * r.sn : __builtin_nan("");
     } else {
@@ -194,7 +199,7 @@ template <typename T, bool REAL>
 __device__ __forceinline__ PointAdd<REAL ? 1 : 2> job_point_add(const JobPoint<T, REAL> &q,
                                                                  double w, double cinc, double R0,
                                                                  double R1) {
-    if constexpr (REAL) return point_add_real<T>(q.st, w * cinc * (R0 * q.cs + R1 * q.sn));
+    if constexpr (REAL) return point_add_real<T>(q.st, w * (R0 * q.cs + R1 * q.sn));  // cinc = 1
     else return point_add_cplx<T>(q.st, w * cinc, R0, R1, q.sn, q.cs);
 }
 
@@ -342,14 +347,14 @@ __global__ __launch_bounds__(SAMPLE_NT) void kb_sample_chi2(const JobDesc *__res
                 const double a00 = st.swap ? x1 : x0, a10 = st.swap ? x0 : x1;
                 const double a01 = st.swap ? y1 : y0, a11 = st.swap ? y0 : y1;
                 const double s = st.s, t = st.t;
-                const double b = a.cinc * ((1.0 - t) * ((1.0 - s) * a00 + s * a01) +
-                                           t * ((1.0 - s) * a10 + s * a11));
+                const double b = (1.0 - t) * ((1.0 - s) * a00 + s * a01) +
+                                 t * ((1.0 - s) * a10 + s * a11);  // cos(inc) = 1 on real spectra
                 Vre = ok ? b * cs : __builtin_nan("");
                 Vim = ok ? b * sn : __builtin_nan("");
                 if (GRAD && J.grad && in && ok) {
                     // Re(conj(R) e^{i theta}) on the real spectrum
                     const double R0 = rr[p] - Vre, R1 = ii[p] - Vim;
-                    pa[p] = point_add_real<T>(st, ww[p] * a.cinc * (R0 * cs + R1 * sn));
+                    pa[p] = point_add_real<T>(st, ww[p] * (R0 * cs + R1 * sn));
                 }
             } else {
                 const c2<T> *S = (const c2<T> *)(ws + J.spec_off);

@@ -500,6 +500,8 @@ static SampleArgs make_sample(const Geom &g, int64_t M, double dxy, double PA, d
     a.cpa = std::cos(PA);
     a.spa = std::sin(PA);
     a.cinc = std::cos(inc);
+    a.cpa_du = a.cpa * a.inv_du;
+    a.spa_du = a.spa * a.inv_du;
     a.dRA = dRA;
     a.dDec = dDec;
     a.jmax = min_c(g.Q - 2, g.N / 2 - 1);

@@ -53,7 +53,7 @@ __global__ __launch_bounds__(SAMPLE_NT) void k_sample_geo(
                 acc[0] = __builtin_nan("");
                 continue;
             }
-            mirror = up * a.cinc < 0.0;  // as locate_r decides it
+            mirror = uu * a.cpa_du - vv * a.spa_du < 0.0;  // the sign test of locate_r
             s = st.s;
             t = st.t;
             // node values at (q, p~0), (q, p~0+1), (q+1, p~0), (q+1, p~0+1)

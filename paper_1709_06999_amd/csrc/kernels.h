@@ -512,6 +512,7 @@ struct SampleArgs {
     int64_t M;
     double inv_du;             // N dxy
     double cpa, spa, cinc;     // cos PA, sin PA, cos inc
+    double cpa_du, spa_du;     // cos PA, sin PA times N dxy (= 1 / du)
     double dRA, dDec;
     int jmax, imin, imax;      // valid stencil corners: j0 <= jmax, imin <= i0 <= imax
 };
@@ -539,15 +540,15 @@ template <typename T>
 __device__ __forceinline__ Stencil<T> locate(const c2<T> *__restrict__ S, const Geom &g,
                                              const SampleArgs &a, double u, double v) {
     Stencil<T> st;
-    double ur = u * a.cpa - v * a.spa;
-    double vr = u * a.spa + v * a.cpa;
-    ur *= a.cinc;
-    st.mirror = ur < 0.0;
+    // grid coordinates of the rotated, deprojected point (1 / du folded into
+    // the rotation)
+    double fu = (u * a.cpa_du - v * a.spa_du) * a.cinc;
+    double fv = u * a.spa_du + v * a.cpa_du;
+    st.mirror = fu < 0.0;
     if (st.mirror) {
-        ur = -ur;
-        vr = -vr;
+        fu = -fu;
+        fv = -fv;
     }
-    const double fu = ur * a.inv_du, fv = vr * a.inv_du;
     const double j0f = floor(fu), i0f = floor(fv);
     st.ok = (j0f >= 0.0) && (j0f <= (double)a.jmax) && (i0f >= (double)a.imin) &&
             (i0f <= (double)a.imax);
@@ -656,14 +657,14 @@ template <typename T>
 __device__ __forceinline__ StencilR<T> locate_r(const T *__restrict__ S, const Geom &g,
                                                 const SampleArgs &a, double u, double v) {
     StencilR<T> st;
-    double ur = u * a.cpa - v * a.spa;
-    double vr = u * a.spa + v * a.cpa;
-    ur *= a.cinc;
-    if (ur < 0.0) {
-        ur = -ur;
-        vr = -vr;
+    // real spectra are those of swept profiles, whose inclination is in the
+    // swept image: they are sampled with cos(inc) = 1 (a.cinc is 1 here)
+    double fu = u * a.cpa_du - v * a.spa_du;
+    double fv = u * a.spa_du + v * a.cpa_du;
+    if (fu < 0.0) {
+        fu = -fu;
+        fv = -fv;
     }
-    const double fu = ur * a.inv_du, fv = vr * a.inv_du;
     const double j0f = floor(fu), i0f = floor(fv);
     st.ok = (j0f >= 0.0) && (j0f <= (double)a.jmax) && (i0f >= (double)a.imin) &&
             (i0f <= (double)a.imax);
@@ -734,8 +735,8 @@ __global__ __launch_bounds__(SAMPLE_NT) void k_sample_sym(
                                  t * ((1.0 - s) * a10 + s * a11);
                 double sn, cs;
                 sincospi_tab(2.0 * (uu[p] * a.dRA + vv[p] * a.dDec), sn, cs);
-                Vre = a.cinc * b * cs;
-                Vim = a.cinc * b * sn;
+                Vre = b * cs;  // cos(inc) = 1 on real spectra
+                Vim = b * sn;
             }
             if constexpr (CHI2) {
                 const double dr = Vre - rr[p];
