@@ -376,7 +376,9 @@ int gal_batch_exec(const gal_job *jobs, int n, double *chi2, void *const *grads,
 /* ---- FFT schedule autotuning -------------------------------------------
  * Every FFT pass exists in NVAR = 3 compiled variants that differ in the
  * values each thread holds (16, 8 or 4: more threads per transform, more
- * waves in flight, more radix passes).  gal_autotune_* times all variants of
+ * waves in flight, more radix passes); for the rows of a swept profile they
+ * are the half-length transform of even rows with 8 values, the full-length
+ * transform of a row pair with 8, and the half-length one with 4.  gal_autotune_* times all variants of
  * the four passes (rows of an image, columns, rows and columns of a swept
  * profile) for one image size on the current device -- with frac the part of
  * the half spectrum transformed (rho_max / ((Nxy/2 - 1) du), 1 = all) -- and
