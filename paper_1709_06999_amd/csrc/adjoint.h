@@ -253,8 +253,15 @@ __global__ __launch_bounds__(SAMPLE_NT) void k_sample_scatter(
     __shared__ double tile[SCAT_TILE];
     __shared__ int box[4 * (SAMPLE_NT / 64)];
     const int blk = xcd_remap(blockIdx.x, gridDim.x);
+    if (a.M == 0) {  // an empty dataset: one block, nothing to read
+        if (threadIdx.x == 0) partials[blk] = 0.0;
+        return;
+    }
     // each thread takes SAMPLE_PPT consecutive points: neighbours in the
-    // locality order of datasets, which in dense regions share a stencil
+    // locality order of datasets, which in dense regions share a stencil.
+    // No branch per point: a point past M re-reads point M - 1 and adds
+    // nothing, so the loads and gathers of all points can be in flight
+    // together.
     const int64_t base = (int64_t)blk * (SAMPLE_NT * SAMPLE_PPT) + threadIdx.x * SAMPLE_PPT;
     double acc = 0.0;
     bool bad = false;
@@ -263,17 +270,15 @@ __global__ __launch_bounds__(SAMPLE_NT) void k_sample_scatter(
     for (int p = 0; p < SAMPLE_PPT; ++p) {
         pa[p].q = -1;
         const int64_t k = base + p;
-        if (k >= a.M) continue;
-        const double uu = u[k], vv = v[k];
+        const bool in = k < a.M;
+        const int64_t kk = in ? k : a.M - 1;
+        const double uu = u[kk], vv = v[kk];
+        const double ov = re[kk], oi = im[kk], wk = w[kk];
         double sn, cs;
         sincospi_tab(2.0 * (uu * a.dRA + vv * a.dDec), sn, cs);
         if constexpr (REAL) {
+            // an off-grid stencil points at valid nodes; its value is discarded
             const StencilR<T> st = locate_r<T>(S, g, a, uu, vv);
-            if (!st.ok) {
-                bad = true;
-                acc = __builtin_nan("");
-                continue;
-            }
             const T x0 = st.c0[0], x1 = st.c0[1], y0 = st.c0[g.CS], y1 = st.c0[g.CS + 1];
             const double a00 = st.swap ? x1 : x0, a10 = st.swap ? x0 : x1;
             const double a01 = st.swap ? y1 : y0, a11 = st.swap ? y0 : y1;
@@ -281,18 +286,14 @@ __global__ __launch_bounds__(SAMPLE_NT) void k_sample_scatter(
             const double b = (1.0 - t) * ((1.0 - s) * a00 + s * a01) +
                              t * ((1.0 - s) * a10 + s * a11);
             const double Vre = b * cs, Vim = b * sn;  // cos(inc) = 1 on real spectra
-            const double rr = (double)re[k] - Vre, ri = (double)im[k] - Vim;
-            acc += (double)w[k] * (rr * rr + ri * ri);
+            const double rr = ov - Vre, ri = oi - Vim;
+            bad |= in && !st.ok;
+            acc += (in && st.ok) ? wk * (rr * rr + ri * ri) : (in ? __builtin_nan("") : 0.0);
             // Re(conj(R) e^{i theta}) = rr cs + ri sn
-            pa[p] = point_add_real<T>(st, (double)w[k] * (rr * cs + ri * sn));
+            if (in && st.ok) pa[p] = point_add_real<T>(st, wk * (rr * cs + ri * sn));
         } else {
             const c2<T> *Sc = (const c2<T> *)S;
             const Stencil<T> st = locate<T>(Sc, g, a, uu, vv);
-            if (!st.ok) {
-                bad = true;
-                acc = __builtin_nan("");
-                continue;
-            }
             const c2<T> n00 = st.c0[0], n10 = st.c0[1], n01 = st.c0[g.CS], n11 = st.c0[g.CS + 1];
             const double s = st.s, t = st.t;
             const double w00 = (1.0 - t) * (1.0 - s), w01 = (1.0 - t) * s;
@@ -303,9 +304,10 @@ __global__ __launch_bounds__(SAMPLE_NT) void k_sample_scatter(
             br *= a.cinc;
             bi *= a.cinc;
             const double Vre = br * cs - bi * sn, Vim = br * sn + bi * cs;
-            const double rr = (double)re[k] - Vre, ri = (double)im[k] - Vim;
-            acc += (double)w[k] * (rr * rr + ri * ri);
-            pa[p] = point_add_cplx<T>(st, (double)w[k] * a.cinc, rr, ri, sn, cs);
+            const double rr = ov - Vre, ri = oi - Vim;
+            bad |= in && !st.ok;
+            acc += (in && st.ok) ? wk * (rr * rr + ri * ri) : (in ? __builtin_nan("") : 0.0);
+            if (in && st.ok) pa[p] = point_add_cplx<T>(st, wk * a.cinc, rr, ri, sn, cs);
         }
     }
     if (bad) ctl->flag = 1;

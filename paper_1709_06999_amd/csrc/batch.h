@@ -238,11 +238,10 @@ __device__ __forceinline__ double job_alone(const JobDesc &J, const BlockPoints<
         if (GRAD && J.grad && in && q.st.ok)
             pa[p] = job_point_add<T, REAL>(q, X.ww[p], a.cinc, X.rr[p] - q.Vre, X.ii[p] - q.Vim);
         bad |= in && !q.st.ok;
-        if (in) {
-            const double dr = q.Vre - X.rr[p], di = q.Vim - X.ii[p];
-            acc += X.ww[p] * (dr * dr + di * di);
-            if (J.vis) store_vis<T>(J.vis, perm, X.idx(p), q.Vre, q.Vim);
-        }
+        // (w = 0 past M, where the stencil at u = v = 0 is valid)
+        const double dr = q.Vre - X.rr[p], di = q.Vim - X.ii[p];
+        acc += X.ww[p] * (dr * dr + di * di);
+        if (in && J.vis) store_vis<T>(J.vis, perm, X.idx(p), q.Vre, q.Vim);
     }
     if (GRAD && J.grad) block_scatter<T, NV, PPT>((T *)(ws + J.a_off), g.CS, pa, tile, box);
     return acc;
@@ -377,10 +376,11 @@ __global__ __launch_bounds__(SAMPLE_NT) void kb_sample_chi2(const JobDesc *__res
                     pa[p] = point_add_cplx<T>(st, ww[p] * a.cinc, rr[p] - Vre, ii[p] - Vim, sn, cs);
             }
             bad |= in && !ok;
-            if (in) {
-                const double dr = Vre - rr[p], di = Vim - ii[p];
-                acc += ww[p] * (dr * dr + di * di);
-            }
+            // no branch on `in`: a point past M has w = 0 and a valid stencil
+            // at u = v = 0 (finite V), so it adds 0, and the four points'
+            // gathers can be in flight together
+            const double dr = Vre - rr[p], di = Vim - ii[p];
+            acc += ww[p] * (dr * dr + di * di);
         }
         if (GRAD && J.grad) block_scatter<T, NV, PPT>((T *)(ws + J.a_off), g.CS, pa, tile, box);
         // one partial per wave (no barrier between chi^2-only jobs); kb_reduce adds them
@@ -468,8 +468,7 @@ __global__ __launch_bounds__(SAMPLE_NT) void kb_sample_scene(const JobDesc *__re
                 }
             }
 #pragma unroll
-            for (int p = 0; p < PPT; ++p) {
-                if (!X.in(p)) continue;
+            for (int p = 0; p < PPT; ++p) {  // w = 0 past M
                 const double dr = Vr[p] - X.rr[p], di = Vi[p] - X.ii[p];
                 acc += X.ww[p] * (dr * dr + di * di);
             }
