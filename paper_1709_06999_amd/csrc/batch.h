@@ -210,19 +210,19 @@ __device__ __forceinline__ void store_vis(void *vis, const int32_t *perm, int64_
 }
 
 // Points held by one thread of a sampling block.
-template <int PPT>
+template <int PPT, int64_t STEP>
 struct BlockPoints {
-    int64_t base, M;
+    int64_t base, M;  // point p of the thread: base + p STEP
     double uu[PPT], vv[PPT], rr[PPT], ii[PPT], ww[PPT];
-    __device__ __forceinline__ bool in(int p) const { return base + p * SAMPLE_NT < M; }
-    __device__ __forceinline__ int64_t idx(int p) const { return base + p * SAMPLE_NT; }
+    __device__ __forceinline__ bool in(int p) const { return base + p * STEP < M; }
+    __device__ __forceinline__ int64_t idx(int p) const { return base + p * STEP; }
 };
 
 // A job alone in its scene (of the scene kernel): value, residual, chi^2 term,
 // visibility output and scatter in one sweep over the thread's points.
 // Returns the thread's chi^2 sum.
-template <typename T, bool REAL, bool GRAD, int PPT>
-__device__ __forceinline__ double job_alone(const JobDesc &J, const BlockPoints<PPT> &X,
+template <typename T, bool REAL, bool GRAD, int PPT, int64_t STEP>
+__device__ __forceinline__ double job_alone(const JobDesc &J, const BlockPoints<PPT, STEP> &X,
                                             const int32_t *perm, char *ws, double *tile,
                                             int *box, bool &bad) {
     constexpr int NV = REAL ? 1 : 2;
@@ -248,8 +248,8 @@ __device__ __forceinline__ double job_alone(const JobDesc &J, const BlockPoints<
 }
 
 // V += the job's visibilities at the thread's points
-template <typename T, bool REAL, int PPT>
-__device__ __forceinline__ void job_add(const JobDesc &J, const BlockPoints<PPT> &X,
+template <typename T, bool REAL, int PPT, int64_t STEP>
+__device__ __forceinline__ void job_add(const JobDesc &J, const BlockPoints<PPT, STEP> &X,
                                         const char *ws, double (&Vr)[PPT], double (&Vi)[PPT],
                                         bool &bad) {
     const SampleArgs a = sample_from_job(J, X.M);
@@ -264,8 +264,8 @@ __device__ __forceinline__ void job_add(const JobDesc &J, const BlockPoints<PPT>
 }
 
 // the job's part of d chi^2 / d spectrum for the scene's residual R
-template <typename T, bool REAL, int PPT>
-__device__ __forceinline__ void job_scatter(const JobDesc &J, const BlockPoints<PPT> &X,
+template <typename T, bool REAL, int PPT, int64_t STEP>
+__device__ __forceinline__ void job_scatter(const JobDesc &J, const BlockPoints<PPT, STEP> &X,
                                             char *ws, const double (&Rr)[PPT],
                                             const double (&Ri)[PPT], double *tile, int *box) {
     constexpr int NV = REAL ? 1 : 2;
@@ -306,13 +306,18 @@ __global__ __launch_bounds__(SAMPLE_NT) void kb_sample_chi2(const JobDesc *__res
     }
     const SGroup &G = groups[lo];
     const int chunk = bid - G.blk0;
-    const int64_t base = (int64_t)chunk * (SAMPLE_NT * PPT) + threadIdx.x;
+    // chi^2 only: points strided by the block size (each load instruction
+    // reads one contiguous run); with gradients: SAMPLE_PPT consecutive
+    // points per thread, neighbours in the locality order of datasets, whose
+    // equal stencils block_scatter folds in registers before the LDS atomics
+    constexpr int64_t PSTEP = GRAD ? 1 : SAMPLE_NT;
+    const int64_t base = (int64_t)chunk * (SAMPLE_NT * PPT) + threadIdx.x * (GRAD ? PPT : 1);
     const gptr<T> u = as_global<T>(G.u), v = as_global<T>(G.v);
     const gptr<T> re = as_global<T>(G.re), im = as_global<T>(G.im), w = as_global<T>(G.w);
     double uu[PPT], vv[PPT], rr[PPT], ii[PPT], ww[PPT];
 #pragma unroll
     for (int p = 0; p < PPT; ++p) {
-        const int64_t k = base + p * SAMPLE_NT;
+        const int64_t k = base + p * PSTEP;
         const bool in = k < G.M;
         uu[p] = in ? (double)u[k] : 0.0;
         vv[p] = in ? (double)v[k] : 0.0;
@@ -330,7 +335,7 @@ __global__ __launch_bounds__(SAMPLE_NT) void kb_sample_chi2(const JobDesc *__res
         PointAdd<NV> pa[PPT];
 #pragma unroll
         for (int p = 0; p < PPT; ++p) {
-            const bool in = base + p * SAMPLE_NT < G.M;
+            const bool in = base + p * PSTEP < G.M;
             pa[p].q = -1;
             // exp(i theta), theta = 2 pi (u dRA + v dDec)
             double sn, cs;
@@ -423,8 +428,11 @@ __global__ __launch_bounds__(SAMPLE_NT) void kb_sample_scene(const JobDesc *__re
     }
     const SGroup &G = groups[lo];
     const int chunk = bid - G.blk0;
-    BlockPoints<PPT> X;
-    X.base = (int64_t)chunk * (SAMPLE_NT * PPT) + threadIdx.x;
+    // points strided by the block size, or consecutive with gradients (as
+    // kb_sample_chi2)
+    constexpr int64_t STEP = GRAD ? 1 : SAMPLE_NT;
+    BlockPoints<PPT, STEP> X;
+    X.base = (int64_t)chunk * (SAMPLE_NT * PPT) + threadIdx.x * (GRAD ? PPT : 1);
     X.M = G.M;
     const gptr<T> u = as_global<T>(G.u), v = as_global<T>(G.v);
     const gptr<T> re = as_global<T>(G.re), im = as_global<T>(G.im), w = as_global<T>(G.w);
@@ -449,10 +457,10 @@ __global__ __launch_bounds__(SAMPLE_NT) void kb_sample_scene(const JobDesc *__re
         if (m1 - m0 == 1) {
             if (real_job<KC>(L)) {
                 if constexpr (KC != 0)
-                    acc = job_alone<T, true, GRAD, PPT>(L, X, G.perm, ws, tile, box, bad);
+                    acc = job_alone<T, true, GRAD, PPT, STEP>(L, X, G.perm, ws, tile, box, bad);
             } else {
                 if constexpr (KC != 1)
-                    acc = job_alone<T, false, GRAD, PPT>(L, X, G.perm, ws, tile, box, bad);
+                    acc = job_alone<T, false, GRAD, PPT, STEP>(L, X, G.perm, ws, tile, box, bad);
             }
         } else {
             // a scene of several sources: V = sum of the sources' visibilities
@@ -462,9 +470,9 @@ __global__ __launch_bounds__(SAMPLE_NT) void kb_sample_scene(const JobDesc *__re
             for (int m = m0; m < m1; ++m) {
                 const JobDesc &J = jobs[mem[m]];
                 if (real_job<KC>(J)) {
-                    if constexpr (KC != 0) job_add<T, true, PPT>(J, X, ws, Vr, Vi, bad);
+                    if constexpr (KC != 0) job_add<T, true, PPT, STEP>(J, X, ws, Vr, Vi, bad);
                 } else {
-                    if constexpr (KC != 1) job_add<T, false, PPT>(J, X, ws, Vr, Vi, bad);
+                    if constexpr (KC != 1) job_add<T, false, PPT, STEP>(J, X, ws, Vr, Vi, bad);
                 }
             }
 #pragma unroll
@@ -490,9 +498,9 @@ __global__ __launch_bounds__(SAMPLE_NT) void kb_sample_scene(const JobDesc *__re
                     const JobDesc &J = jobs[mem[m]];
                     if (!J.grad) continue;
                     if (real_job<KC>(J)) {
-                        if constexpr (KC != 0) job_scatter<T, true, PPT>(J, X, ws, Rr, Ri, tile, box);
+                        if constexpr (KC != 0) job_scatter<T, true, PPT, STEP>(J, X, ws, Rr, Ri, tile, box);
                     } else {
-                        if constexpr (KC != 1) job_scatter<T, false, PPT>(J, X, ws, Rr, Ri, tile, box);
+                        if constexpr (KC != 1) job_scatter<T, false, PPT, STEP>(J, X, ws, Rr, Ri, tile, box);
                     }
                 }
             }

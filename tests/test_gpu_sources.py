@@ -88,8 +88,10 @@ def test_field_matches_oracle(dtype):
             assert a is None
             continue
         assert _rel(a.cpu().numpy().astype(np.float64), b) <= tol, k
-    # the chi^2-only call gives the same chi^2, bit for bit
-    assert float(ds.chi2Sources(src)) == float(c2g)
+    # the chi^2-only call gives the same chi^2 (its points are summed in
+    # another order: strided instead of consecutive per thread)
+    c2_only = float(ds.chi2Sources(src))
+    assert abs(c2_only - float(c2g)) <= 1e-12 * abs(float(c2g))
 
 
 def test_field_in_a_mixed_call_equals_alone():
