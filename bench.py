@@ -394,6 +394,7 @@ def main():
     gjobs = batch.jobs
     gstep = lambda: gal.batch_exec(gjobs, gbuf)
     ms_bgrad = _timed(gstep, max(args.steps // 4, 20), args.warmup, torch)
+    kern_bgrad = _kernel_times(gal, gstep, 20, torch)
 
     # ---- roofline of the dominant kernel of the batched step ---------------
     ab = algorithmic_bytes(N, Nr, M, Q, P, "profile")
@@ -509,7 +510,8 @@ def main():
                            "ms_per_eval": round(ms_grad, 5), "kernels": rnd(kern_grad)},
                  "batched": {"value": round(K * 1e3 / ms_bgrad, 1), "unit": "chi2+grad evals/s",
                              "ms_per_step": round(ms_bgrad, 5), "batch": K,
-                             "form": "one gal_batch_exec call per step (planned at the call)"},
+                             "form": "one gal_batch_exec call per step (planned at the call)",
+                             "kernels": rnd(kern_bgrad)},
                  "geometry_plain": {"value": round(1e3 / ms_geo, 1),
                                     "unit": "chi2 + d/d(PA, dRA, dDec, inc) evals/s",
                                     "ms_per_eval": round(ms_geo, 5)}},

@@ -61,7 +61,7 @@ __global__ __launch_bounds__(256) void k_zero2(T *__restrict__ p, int64_t n, dou
 // scanning the box would cost more than the atomics it saves) falls back to
 // direct global atomics.
 constexpr int SCAT_TILE = 4096;  // doubles of LDS per block
-constexpr int SCAT_WINDOWS = 4;
+constexpr int SCAT_WINDOWS = 2;
 
 template <int NV>
 struct PointAdd {
