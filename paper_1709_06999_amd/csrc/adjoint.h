@@ -30,20 +30,25 @@
 
 namespace gal {
 
-template <typename T>
-__global__ __launch_bounds__(256) void k_zero(T *__restrict__ p, int64_t n) {
-    for (int64_t i = (int64_t)blockIdx.x * 256 + threadIdx.x; i < n; i += (int64_t)gridDim.x * 256)
-        p[i] = T(0);
+// Zero [p, p + pb) and [q, q + qb) (16-byte aligned, sizes multiples of 8
+// bytes) with 16-byte stores; the grid is sized to the ranges (zero_grid).
+__global__ __launch_bounds__(256) void k_zero16(void *__restrict__ p, int64_t pb,
+                                                void *__restrict__ q, int64_t qb) {
+    const int64_t n1 = pb >> 4, n2 = qb >> 4;
+    const int64_t stride = (int64_t)gridDim.x * 256;
+    for (int64_t i = (int64_t)blockIdx.x * 256 + threadIdx.x; i < n1 + n2; i += stride) {
+        uint4 *d = i < n1 ? (uint4 *)p + i : (uint4 *)q + (i - n1);
+        *d = make_uint4(0u, 0u, 0u, 0u);
+    }
+    if (blockIdx.x == 0 && threadIdx.x == 0) {  // an 8-byte tail of either range
+        if (pb & 8) ((unsigned long long *)p)[(pb >> 3) - 1] = 0ull;
+        if (qb & 8) ((unsigned long long *)q)[(qb >> 3) - 1] = 0ull;
+    }
 }
 
-// two ranges cleared by one launch
-template <typename T>
-__global__ __launch_bounds__(256) void k_zero2(T *__restrict__ p, int64_t n, double *__restrict__ q,
-                                               int64_t m) {
-    for (int64_t i = (int64_t)blockIdx.x * 256 + threadIdx.x; i < n + m; i += (int64_t)gridDim.x * 256) {
-        if (i < n) p[i] = T(0);
-        else q[i - n] = 0.0;
-    }
+inline unsigned zero_grid(int64_t bytes) {
+    const int64_t b = (bytes / 16 + 255) / 256;
+    return (unsigned)(b < 1 ? 1 : (b > 4096 ? 4096 : b));
 }
 
 // ---- block scatter through an LDS tile --------------------------------------

@@ -663,8 +663,12 @@ static int grad_path(const T *src, bool profile, const SweepArgs &sw, const Geom
     const int Qe = (g.Q + 1) & ~1;
     const int64_t a_elems = profile ? (int64_t)Qe * gs.CS : (int64_t)2 * gs.Q * gs.CS;
     // the scatter grid and, for profiles, the bin accumulator copies
-    rc = launch("k_zero", k_zero2<T>, dim3(256), dim3(256), s, (T *)A, a_elems, gI,
-                profile ? (int64_t)GI_COPIES * Nr : (int64_t)0);
+    {
+        const int64_t ab = a_elems * (int64_t)sizeof(T);
+        const int64_t gb = profile ? (int64_t)GI_COPIES * Nr * (int64_t)sizeof(double) : 0;
+        rc = launch("k_zero", k_zero16, dim3(zero_grid(ab + gb)), dim3(256), s, A, ab, (void *)gI,
+                    gb);
+    }
     if (rc) return rc;
     const SampleArgs sa = make_sample(g, o.M, dxy, PA, dRA, dDec, inc);
     const dim3 grid((unsigned)sample_blocks(o.M)), blk(SAMPLE_NT);
@@ -1946,8 +1950,9 @@ static int exec_plan(const BatchPlan &P, const BatchTables &t, char *ws, double 
     int rc = launch("kb_prepare", kb_prepare, dim3((P.n + 63) / 64), dim3(64), s, t.jobs, P.n);
     if (rc) return rc;
     if (P.zero_end > P.zero_begin) {
-        rc = launch("k_zero", k_zero<double>, dim3(256), dim3(256), s, ws + P.zero_begin,
-                    (int64_t)((P.zero_end - P.zero_begin) / sizeof(double)));
+        const int64_t zb = (int64_t)(P.zero_end - P.zero_begin);
+        rc = launch("k_zero", k_zero16, dim3(zero_grid(zb)), dim3(256), s, (void *)(ws + P.zero_begin),
+                    zb, (void *)nullptr, (int64_t)0);
         if (rc) return rc;
     }
     for (const auto &f : P.fgroups) {
