@@ -59,3 +59,46 @@ def test_every_variant_matches_oracle(N, M, dtype):
     finally:
         gal.tune_set(N, [-1] * 4, tdt)
         ds.close()
+
+
+def test_every_variant_at_the_largest_image():
+    # 8192^2 (the largest size), FP64 profile: every variant against the
+    # oracle's direct double sums at sampled points (tolerance relative to the
+    # total flux, |V(0, 0)|), the variants against each other at every point,
+    # and the batch against the single call
+    dev = device()
+    import torch
+
+    import paper_1709_06999_amd as gal
+
+    N, d = 8192, np.float64
+    c = wl.random_case(N, 20000, seed=3901, kind="profile", fill=0.9)
+    geo = dict(inc=c.inc, PA=c.PA, dRA=c.dRA, dDec=c.dDec)
+    img = oracle.sweep(c.I, c.Rmin, c.dR, N, c.dxy, c.inc)
+    flux = float(np.sum(img))
+    pick = np.random.default_rng(3902).choice(c.M, 8, replace=False)
+    Vo = oracle.sample_direct(img, c.dxy, c.u[pick], c.v[pick], c.PA, c.dRA, c.dDec, 0.0)
+    del img
+    ds = gal.Dataset(*(t(a, d, dev) for a in (c.u, c.v, c.noise_re, c.noise_im, c.w)))
+    It = t(c.I, d, dev)
+    geob = torch.tensor([[c.Rmin, c.dR, c.inc, c.PA, c.dRA, c.dDec]] * 2, dtype=torch.float64,
+                        device=dev)
+    Ib = It.unsqueeze(0).repeat(2, 1).contiguous()
+    ref = None
+    try:
+        for var in range(3):
+            gal.tune_set(N, [var] * 4, torch.float64)
+            Vg = ds.sampleProfile(It, c.Rmin, c.dR, N, c.dxy, **geo).cpu().numpy()
+            err = np.max(np.abs(Vg[pick] - Vo)) / flux
+            assert err <= 1e-10, (var, err)
+            if ref is None:
+                ref = Vg
+            assert np.max(np.abs(Vg - ref)) <= 1e-12 * flux, var
+            b = gal.profile_batch(ds, Ib, geob, N, c.dxy)
+            c2b = b.chi2().cpu().numpy()
+            b.close()
+            c2s = float(ds.chi2Profile(It, c.Rmin, c.dR, N, c.dxy, **geo))
+            assert abs(c2b[0] - c2s) <= 1e-12 * c2s and c2b[0] == c2b[1], var
+    finally:
+        gal.tune_set(N, [-1] * 4, torch.float64)
+        ds.close()
