@@ -102,24 +102,27 @@ __device__ __forceinline__ double sqrt_pos(double x) {
 }
 
 // PI: pointer to the profile (generic, or global for pointers read from tables)
+// Branch-free, so that the profile loads of neighbouring pixels can be in
+// flight together: the bin index is clamped in floating point (every load is
+// in bounds, NaN included) and a pixel outside [Rmin, Rmin + (Nr-1) dR] is
+// selected to 0.  The centre pixel's rule -- the first segment extrapolated
+// to rho = 0 -- is the same interpolation at bin 0 with t = -Rmin / dR <= 0:
+// rho^2 is kept >= 1e-300 (every other pixel has rho^2 >= dxy^2 >= 1e-200), so
+// there the root is 1e-150 instead of 0 and t differs by 1e-150 / dR.
 template <typename PI>
 __device__ __forceinline__ double sweep_pixel(PI I, int N, int r, int c, const SweepArgs &a) {
-    if (r == N / 2 && c == N / 2) {
-        const double I0 = I[0], I1 = I[1];
-        return (I0 - a.Rmin * (I1 - I0) * a.inv_dR) * a.pix_area;
-    }
+    const bool centre = (r == N / 2) && (c == N / 2);
     const double x = (double)(N / 2 - c) * a.dxy;
     const double y = (double)(N / 2 - r) * a.dxy;
     const double xs = x * a.inv_cos;
-    const double rho = sqrt_pos(xs * xs + y * y);
+    const double rho = sqrt_pos(fmax(xs * xs + y * y, 1e-300));
     const double t = (rho - a.Rmin) * a.inv_dR;
-    if (t >= 0.0 && t <= a.tmax) {
-        int j = (int)t;
-        j = j < a.Nr - 2 ? j : a.Nr - 2;
-        const double f = t - (double)j;
-        return ((1.0 - f) * (double)I[j] + f * (double)I[j + 1]) * a.pix_area;
-    }
-    return 0.0;
+    const int j = (int)fmin(fmax(t, 0.0), (double)(a.Nr - 2));
+    const double f = t - (double)j;
+    // a multiply by 0 or 1 rather than a select, which the compiler would
+    // turn back into a branch around the loads' use
+    const double m = (centre || (t >= 0.0 && t <= a.tmax)) ? a.pix_area : 0.0;
+    return ((1.0 - f) * (double)I[j] + f * (double)I[j + 1]) * m;
 }
 
 // d pixel / d inc of the sweep (not in the paper): on the segment that
@@ -128,19 +131,16 @@ __device__ __forceinline__ double sweep_pixel(PI I, int N, int r, int c, const S
 // the centre pixel (its extrapolated value does not depend on inc).
 template <typename PI>
 __device__ __forceinline__ double sweep_pixel_dinc(PI I, int N, int r, int c, const SweepArgs &a) {
-    if (r == N / 2 && c == N / 2) return 0.0;
+    const bool centre = (r == N / 2) && (c == N / 2);
     const double x = (double)(N / 2 - c) * a.dxy;
     const double y = (double)(N / 2 - r) * a.dxy;
     const double xs = x * a.inv_cos;
-    const double rho = sqrt_pos(xs * xs + y * y);
+    const double rho = sqrt_pos(fmax(xs * xs + y * y, 1e-300));  // as sweep_pixel
     const double t = (rho - a.Rmin) * a.inv_dR;
-    if (t >= 0.0 && t <= a.tmax) {
-        int j = (int)t;
-        j = j < a.Nr - 2 ? j : a.Nr - 2;
-        return ((double)I[j + 1] - (double)I[j]) * a.inv_dR * (xs * xs * a.tan_inc / rho) *
-               a.pix_area;
-    }
-    return 0.0;
+    const int j = (int)fmin(fmax(t, 0.0), (double)(a.Nr - 2));
+    const double v = ((double)I[j + 1] - (double)I[j]) * a.inv_dR *
+                     (xs * xs * a.tan_inc / rho) * a.pix_area;
+    return (!centre && t >= 0.0 && t <= a.tmax) ? v : 0.0;
 }
 
 // ---------------------------------------------------------------------------
