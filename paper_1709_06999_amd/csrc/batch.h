@@ -296,7 +296,7 @@ __global__ __launch_bounds__(SAMPLE_NT) void kb_sample_chi2(const JobDesc *__res
     __shared__ double tile[GRAD ? SCAT_TILE : 1];
     __shared__ int box[GRAD ? 4 * WAVES : 1];
     // every XCD takes a contiguous run of chunks: a compact patch of the
-    // (Morton-ordered) uv plane, whose spectrum nodes then stay in its L2
+    // (locality-ordered) uv plane, whose spectrum nodes then stay in its L2
     const int bid = xcd_remap(blockIdx.x, gridDim.x);
     int lo = 0, hi = ngroups - 1;
     while (lo < hi) {

@@ -1124,14 +1124,13 @@ int gal_sample_spectrum_f(const float *spec, int Nxy, double dxy, const float *u
 }
 
 // ---- datasets -------------------------------------------------------------
-// Morton (Z-order) key of a uv point on a 2^16 x 2^16 grid over
-// [-rho_max, rho_max]^2: neighbouring keys are neighbouring points, and a
-// rotation by PA keeps neighbours together, so a wavefront of consecutive
-// points gathers from a few cache lines of the spectrum.
 // Locality order of a dataset: position along a Hilbert curve over a
-// 65536^2 grid spanning [-rho_max, rho_max]^2.  Consecutive runs of points are
-// connected patches of the uv plane (a Z-order curve jumps between distant
-// quadrants), so a sampling block's stencil nodes span a compact box.
+// 65536^2 grid spanning [-rho_max, rho_max]^2.  Neighbouring keys are
+// neighbouring points and a rotation by PA keeps neighbours together, so a
+// wavefront of consecutive points gathers from a few cache lines of the
+// spectrum; consecutive runs of points are connected patches of the uv plane
+// (a Z-order curve jumps between distant quadrants), so a sampling block's
+// stencil nodes span a compact box.
 static uint64_t hilbert_key(double u, double v, double rho_max) {
     const double sc = rho_max > 0.0 ? 32767.5 / rho_max : 0.0;
     double xf = (u * sc) + 32767.5, yf = (v * sc) + 32767.5;

@@ -199,6 +199,63 @@ def profile_2048(M: int = 1_000_000) -> Workload:
                     PA=120 * DEG, inc=45 * DEG, I=I, Rmin=Rmin, dR=dR)
 
 
+def spectral_cube(n_chan: int = 64, N: int = 1024, M_range=(200_000, 1_000_000),
+                  seed: int = 1600):
+    """Channels of a spectral cube at N^2 (64 channels at 1024^2 by default).
+    One base uv set (log-uniform radius over the C43-5 baselines at 1.3 mm)
+    is scaled by each channel's frequency ratio, 1 to 1.05 across the band;
+    channel k keeps the first M_k points, M_k log-uniform in M_range (ragged).
+    The pixel keeps the widest channel inside 0.9 of the valid radius.  Each
+    channel's model is an elliptical Gaussian whose flux and position drift
+    across the band; noise sigma 1e-3 Jy.  Yields one Workload per channel."""
+    rng = np.random.default_rng(seed)
+    rho_lo, rho_hi = 14.6 / 1.3e-3, 1397.9 / 1.3e-3
+    u0, v0 = uv_log_uniform(M_range[1], rho_lo, rho_hi, seed=seed + 1)
+    dxy = 0.9 * (N / 2 - 1) / (N * 1.05 * rho_hi)
+    Ms = np.exp(rng.uniform(math.log(M_range[0]), math.log(M_range[1]), n_chan)).astype(int)
+    for k in range(n_chan):
+        f = 1.0 + 0.05 * k / max(n_chan - 1, 1)
+        M = int(Ms[k])
+        nre, nim, w = noise(M, 1e-3, seed=seed + 10 + k)
+        x0 = (k / n_chan - 0.5) * 8.0 * dxy
+        img = gaussian_image(N, dxy, 1.0 + 0.5 * math.sin(2.0 * math.pi * k / n_chan),
+                             6.0 * dxy, 4.0 * dxy, x0, 0.5 * x0, 0.4)
+        yield Workload(f"cube_chan{k}_N{N}_M{M}", "image", N, dxy, u0[:M] * f, v0[:M] * f, nre,
+                       nim, w, PA=30 * DEG, inc=0.0, dRA=0.0, dDec=0.0, image=img)
+
+
+def mixed_models(n: int = 32, sizes=(512, 1024, 2048, 4096), M: int = 300_000,
+                 seed: int = 1700):
+    """Models of mixed sizes on two shared uv sets (log-uniform radius over
+    the C43-5 baselines): n Gaussian-ring profiles, Nxy drawn from ``sizes``,
+    Nr in [512, 4096], the pixel set per size so that the coverage fills 0.8
+    of the valid radius, random PA, inclination and offsets.  Returns the two
+    uv sets (u, v, noise_re, noise_im, w) and n dicts {set, N, dxy, I, Rmin,
+    dR, inc, PA, dRA, dDec}."""
+    rng = np.random.default_rng(seed)
+    rho_lo, rho_hi = 14.6 / 1.3e-3, 1397.9 / 1.3e-3
+    sets = []
+    for s_ in range(2):
+        u, v = uv_log_uniform(M, rho_lo, rho_hi, seed=seed + 1 + s_)
+        nre, nim, w = noise(M, 1e-3, seed=seed + 3 + s_)
+        sets.append((u, v, nre, nim, w))
+    models = []
+    for i in range(n):
+        N = int(rng.choice(sizes))
+        dxy = 0.8 * (N / 2 - 1) / (N * rho_hi)
+        Nr = int(rng.integers(512, 4097))
+        Rmax = 0.7 * N * dxy
+        Rmin = 0.0
+        dR = (Rmax - Rmin) / (Nr - 1)
+        r = Rmin + dR * np.arange(Nr)
+        r0, wd = rng.uniform(0.1, 0.3) * N * dxy, rng.uniform(0.02, 0.06) * N * dxy
+        I = (np.exp(-((r - r0) / wd) ** 2) + 0.3 * np.exp(-(r / (0.1 * N * dxy)) ** 2)) / dxy ** 2
+        models.append(dict(set=int(i % 2), N=N, dxy=dxy, I=I, Rmin=Rmin, dR=dR,
+                           inc=rng.uniform(0.0, 60 * DEG), PA=rng.uniform(0.0, math.pi),
+                           dRA=rng.normal(0.0, 2 * dxy), dDec=rng.normal(0.0, 2 * dxy)))
+    return sets, models
+
+
 def field_of_copies(c: Workload, n: int, seed: int) -> list:
     """A field of n copies of the profile workload ``c``: the first at c's own
     geometry, the others (sharing its spectrum) at random PA and offsets of up
