@@ -167,6 +167,72 @@ def _kernel_times(gal, fn, steps, torch):
     return {k: {"avg_us": 1e3 * ms / n, "launches": n} for k, (ms, n) in times.items()}
 
 
+def cube_bench(gal, torch, np, dev, steps, warmup):
+    """The batched configuration: a 64-channel FP32 cube at 1024^2 (ragged M
+    2e5..1e6, frequency-scaled uv sets) plus 32 FP32 models of 512^2..4096^2
+    on two datasets, as one planned batch replayed from a HIP graph, against
+    the same 96 evaluations made one call at a time."""
+    import workloads as wl
+
+    f32 = lambda a: torch.as_tensor(np.ascontiguousarray(a, dtype=np.float32), device=dev)
+    jobs, keep, calls = [], [], []
+    for c in wl.spectral_cube(64, 1024):
+        ds = gal.Dataset(f32(c.u), f32(c.v), f32(c.noise_re), f32(c.noise_im), f32(c.w))
+        img = f32(c.image)
+        geo = torch.tensor([0.0, 1.0, c.inc, c.PA, c.dRA, c.dDec], dtype=torch.float64, device=dev)
+        jobs.append({"ds": ds, "kind": gal.JOB_IMAGE, "Nxy": c.N, "dxy": c.dxy, "model": img,
+                     "geo": geo})
+        calls.append(lambda ds=ds, img=img, c=c: ds.chi2Image(img, c.dxy, c.PA, c.dRA, c.dDec,
+                                                              c.inc))
+        keep.append((ds, img, geo))
+    sets, models = wl.mixed_models(32)
+    dsets = [gal.Dataset(*(f32(a) for a in st)) for st in sets]
+    for m in models:
+        I = f32(m["I"])
+        geo = torch.tensor([m["Rmin"], m["dR"], m["inc"], m["PA"], m["dRA"], m["dDec"]],
+                           dtype=torch.float64, device=dev)
+        ds = dsets[m["set"]]
+        jobs.append({"ds": ds, "kind": gal.JOB_PROFILE, "Nxy": m["N"], "dxy": m["dxy"],
+                     "model": I, "geo": geo})
+        calls.append(lambda ds=ds, I=I, m=m: ds.chi2Profile(I, m["Rmin"], m["dR"], m["N"],
+                                                            m["dxy"], m["inc"], m["PA"],
+                                                            m["dRA"], m["dDec"]))
+        keep.append((I, geo))
+    b = gal.Batch(jobs)
+    tuned = gal.autotune_batch(b, 1024, torch.float32)
+    side = torch.cuda.Stream(device=dev)
+    side.wait_stream(torch.cuda.current_stream(dev))
+    with torch.cuda.stream(side):
+        b.chi2()
+    torch.cuda.current_stream(dev).wait_stream(side)
+    torch.cuda.synchronize()
+    graph = torch.cuda.CUDAGraph()
+    with torch.cuda.graph(graph):
+        b.chi2()
+    ms_graph = _timed(graph.replay, steps, warmup, torch)
+    eager = b.chi2().clone()
+    graph.replay()
+    torch.cuda.synchronize()
+    same = bool(torch.equal(eager, b.out))
+    ms_plain = _timed(lambda: [f() for f in calls], max(steps // 4, 10), 2, torch)
+    n = len(jobs)
+    info = b.info()
+    b.close()
+    for ds, *_ in keep[:64]:
+        ds.close()
+    for ds in dsets:
+        ds.close()
+    return {"jobs": n, "fft_groups": info["fft_groups"], "sample_groups": info["sample_groups"],
+            "batched": {"value": round(n * 1e3 / ms_graph, 1), "unit": "chi2 evals/s",
+                        "ms_per_batch": round(ms_graph, 4), "form": "one HIP-graph replay"},
+            "plain": {"value": round(n * 1e3 / ms_plain, 1), "unit": "chi2 evals/s",
+                      "ms_per_96_calls": round(ms_plain, 4)},
+            "batched_vs_plain": round(ms_plain / ms_graph, 3), "fft_variants_1024": tuned,
+            "graph_replay_matches_eager": same,
+            "workload": "64 channels at 1024^2 FP32 (frequency-scaled uv, M 2e5..1e6) + 32 FP32 "
+                        "profiles at 512^2..4096^2 on two 3e5-point datasets"}
+
+
 def serve_bench(gal, torch, np, dev, rates, n_req, warm, grad_frac, n_datasets, max_M):
     """Poisson stream of chi2Profile (+ gradient) requests against resident
     datasets, served by the continuous-batching loop; latency and throughput
@@ -231,6 +297,8 @@ def main():
     ap.add_argument("--plain-steps", type=int, default=2000)
     ap.add_argument("--latency-samples", type=int, default=300)
     ap.add_argument("--grad-steps", type=int, default=300, help="timed plain gradient calls")
+    ap.add_argument("--no-cube", action="store_true",
+                    help="skip the batched cube + mixed-models section")
     ap.add_argument("--field-sources", type=int, default=16,
                     help="sources in the field section (copies of the profile)")
     ap.add_argument("--no-cpu-baseline", action="store_true")
@@ -350,6 +418,10 @@ def main():
                            args.warmup, torch)
     fb_shared.close()
     fb_own.close()
+
+    # ---- the batched configuration: cube + mixed models in one graph ------
+    cube = None if args.no_cube else cube_bench(gal, torch, np, dev, max(args.steps // 4, 20),
+                                                args.warmup)
 
     # ---- batched: K walkers (different profiles and geometry) per step ----
     K = args.batch
@@ -515,6 +587,7 @@ def main():
                  "geometry_plain": {"value": round(1e3 / ms_geo, 1),
                                     "unit": "chi2 + d/d(PA, dRA, dDec, inc) evals/s",
                                     "ms_per_eval": round(ms_geo, 5)}},
+        "cube": cube,
         "field": {"sources": S,
                   "shared_spectrum": {"value": round(1e3 / ms_field, 1), "unit": "field chi2 evals/s",
                                       "ms_per_eval": round(ms_field, 5),
