@@ -217,15 +217,15 @@ __device__ __forceinline__ void block_scatter(T *__restrict__ A, int CS, const P
 }
 
 // The residual R_k = Vobs_k - V_k of one sampled point as node additions.
-// Real spectrum (swept profile): hv = w cinc Re(conj(R) e^{i theta}); the
-// stencil's rows lo and lo + 1 carry p~0 + 1 and p~0 when swapped.
+// Real spectrum (swept profile): hv = w cinc Re(conj(R) e^{i theta}) on the
+// even-form stencil (stored rows i and i + 1 with weights 1 - t and t).
 template <typename T>
-__device__ __forceinline__ PointAdd<1> point_add_real(const StencilR<T> &st, double h) {
+__device__ __forceinline__ PointAdd<1> point_add_real(const StencilE<T> &st, double h) {
     PointAdd<1> r;
     r.q = st.q;
     r.i = st.i;
     r.hv[0] = h;
-    r.a = st.swap ? 1.0 - st.t : st.t;
+    r.a = st.t;
     r.s = st.s;
     return r;
 }
@@ -280,16 +280,13 @@ __global__ __launch_bounds__(SAMPLE_NT) void k_sample_scatter(
         const double uu = u[kk], vv = v[kk];
         const double ov = re[kk], oi = im[kk], wk = w[kk];
         double sn, cs;
-        sincospi_tab(2.0 * (uu * a.dRA + vv * a.dDec), sn, cs);
+        phase_of(a, uu, vv, sn, cs);
         if constexpr (REAL) {
             // an off-grid stencil points at valid nodes; its value is discarded
-            const StencilR<T> st = locate_r<T>(S, g, a, uu, vv);
-            const T x0 = st.c0[0], x1 = st.c0[1], y0 = st.c0[g.CS], y1 = st.c0[g.CS + 1];
-            const double a00 = st.swap ? x1 : x0, a10 = st.swap ? x0 : x1;
-            const double a01 = st.swap ? y1 : y0, a11 = st.swap ? y0 : y1;
-            const double s = st.s, t = st.t;
-            const double b = (1.0 - t) * ((1.0 - s) * a00 + s * a01) +
-                             t * ((1.0 - s) * a10 + s * a11);
+            const StencilE<T> st = locate_e<T>(S, g, a, uu, vv);
+            double x0, x1, y0, y1;
+            nodes_e<T>(S, st, g.CS, x0, x1, y0, y1);
+            const double b = bilerp(x0, y0, x1, y1, st.s, st.t);
             const double Vre = b * cs, Vim = b * sn;  // cos(inc) = 1 on real spectra
             const double rr = ov - Vre, ri = oi - Vim;
             bad |= in && !st.ok;

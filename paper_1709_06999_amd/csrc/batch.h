@@ -99,6 +99,8 @@ __device__ __forceinline__ SampleArgs sample_from_job(const JobDesc &j, int64_t 
     a.spa_du = j.spa_du;
     a.dRA = j.dRA;
     a.dDec = j.dDec;
+    a.ph_u = 256.0 * j.dRA;
+    a.ph_v = 256.0 * j.dDec;
     a.jmax = min(j.Q - 2, j.N / 2 - 1);
     a.imin = -min(j.P, j.N / 2);
     a.imax = min(j.P - 1, j.N / 2 - 2);
@@ -151,7 +153,7 @@ __global__ __launch_bounds__(Cfg::NT) void kb_cols_sym(const JobDesc *__restrict
 // images) times the phase of its offset, plus the stencil for a scatter.
 template <typename T, bool REAL>
 struct JobPoint {
-    std::conditional_t<REAL, StencilR<T>, Stencil<T>> st;
+    std::conditional_t<REAL, StencilE<T>, Stencil<T>> st;
     double Vre, Vim, sn, cs;
 };
 
@@ -161,19 +163,17 @@ __device__ __forceinline__ JobPoint<T, REAL> job_point(const JobDesc &J, const S
                                                        double v) {
     JobPoint<T, REAL> r;
     // exp(i theta), theta = 2 pi (u dRA + v dDec)
-    sincospi_tab(2.0 * (u * a.dRA + v * a.dDec), r.sn, r.cs);
+    phase_of(a, u, v, r.sn, r.cs);
     // an off-grid stencil points at valid nodes; its value is discarded
     if constexpr (REAL) {
-        r.st = locate_r<T>((const T *)(ws + J.spec_off), g, a, u, v);
-        const StencilR<T> &st = r.st;
-        const T x0 = st.c0[0], x1 = st.c0[1], y0 = st.c0[g.CS], y1 = st.c0[g.CS + 1];
-        const double a00 = st.swap ? x1 : x0, a10 = st.swap ? x0 : x1;
-        const double a01 = st.swap ? y1 : y0, a11 = st.swap ? y0 : y1;
-        const double s = st.s, t = st.t;
-        const double b = (1.0 - t) * ((1.0 - s) * a00 + s * a01) +
-                         t * ((1.0 - s) * a10 + s * a11);  // cos(inc) = 1 on real spectra
-        r.Vre = st.ok ? b * r.cs : __builtin_nan("");
-        r.Vim = st.ok ? b * r.sn : __builtin_nan("");
+        r.st = locate_e<T>((const T *)(ws + J.spec_off), g, a, u, v);
+        const StencilE<T> &st = r.st;
+        double x0, x1, y0, y1;
+        nodes_e<T>((const T *)(ws + J.spec_off), st, g.CS, x0, x1, y0, y1);
+        double b = bilerp(x0, y0, x1, y1, st.s, st.t);  // cos(inc) = 1 on real spectra
+        b = st.ok ? b : __builtin_nan("");
+        r.Vre = b * r.cs;
+        r.Vim = b * r.sn;
     } else {
         r.st = locate<T>((const c2<T> *)(ws + J.spec_off), g, a, u, v);
         const Stencil<T> &st = r.st;
@@ -339,22 +339,20 @@ __global__ __launch_bounds__(SAMPLE_NT) void kb_sample_chi2(const JobDesc *__res
             pa[p].q = -1;
             // exp(i theta), theta = 2 pi (u dRA + v dDec)
             double sn, cs;
-            sincospi_tab(2.0 * (uu[p] * a.dRA + vv[p] * a.dDec), sn, cs);
+            phase_of(a, uu[p], vv[p], sn, cs);
             double Vre, Vim;
             bool ok;
             // an off-grid stencil points at valid nodes; its value is discarded
             if constexpr (REAL) {
                 const T *S = (const T *)(ws + J.spec_off);
-                const StencilR<T> st = locate_r<T>(S, g, a, uu[p], vv[p]);
+                const StencilE<T> st = locate_e<T>(S, g, a, uu[p], vv[p]);
                 ok = st.ok;
-                const T x0 = st.c0[0], x1 = st.c0[1], y0 = st.c0[g.CS], y1 = st.c0[g.CS + 1];
-                const double a00 = st.swap ? x1 : x0, a10 = st.swap ? x0 : x1;
-                const double a01 = st.swap ? y1 : y0, a11 = st.swap ? y0 : y1;
-                const double s = st.s, t = st.t;
-                const double b = (1.0 - t) * ((1.0 - s) * a00 + s * a01) +
-                                 t * ((1.0 - s) * a10 + s * a11);  // cos(inc) = 1 on real spectra
-                Vre = ok ? b * cs : __builtin_nan("");
-                Vim = ok ? b * sn : __builtin_nan("");
+                double x0, x1, y0, y1;
+                nodes_e<T>(S, st, g.CS, x0, x1, y0, y1);
+                double b = bilerp(x0, y0, x1, y1, st.s, st.t);  // cos(inc) = 1 on real spectra
+                b = ok ? b : __builtin_nan("");
+                Vre = b * cs;
+                Vim = b * sn;
                 if (GRAD && J.grad && in && ok) {
                     // Re(conj(R) e^{i theta}) on the real spectrum
                     const double R0 = rr[p] - Vre, R1 = ii[p] - Vim;

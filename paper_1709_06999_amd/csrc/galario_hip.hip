@@ -504,6 +504,8 @@ static SampleArgs make_sample(const Geom &g, int64_t M, double dxy, double PA, d
     a.spa_du = a.spa * a.inv_du;
     a.dRA = dRA;
     a.dDec = dDec;
+    a.ph_u = 256.0 * dRA;
+    a.ph_v = 256.0 * dDec;
     a.jmax = min_c(g.Q - 2, g.N / 2 - 1);
     a.imin = -min_c(g.P, g.N / 2);
     a.imax = min_c(g.P - 1, g.N / 2 - 2);

@@ -41,7 +41,7 @@ __global__ __launch_bounds__(SAMPLE_NT) void k_sample_geo(
         if (k >= a.M) continue;
         const double uu = u[k], vv = v[k];
         double sn, cs;
-        sincospi_tab(2.0 * (uu * a.dRA + vv * a.dDec), sn, cs);
+        phase_of(a, uu, vv, sn, cs);
         const double up = uu * a.cpa - vv * a.spa, vp = uu * a.spa + vv * a.cpa;
         double Br, Bi = 0.0, Bsr, Bsi = 0.0, Btr, Bti = 0.0, Ir, Ii = 0.0;
         double s, t;

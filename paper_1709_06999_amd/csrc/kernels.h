@@ -38,23 +38,22 @@ __device__ __forceinline__ gptr<T> as_global(const void *p) {
     return (gptr<T>)p;
 }
 
-// sin(pi x) and cos(pi x) for the phase factor of a uv point, by table and
-// series: x = n/128 + r with n = rint(128 x) and |r| <= 1/256 (r exact);
-// (cos, -sin)(pi n / 128) is entry n mod 256 of the length-256 twiddle row
-// (exp(-2 pi i m / 256), stored at [256, 512)); sin and cos of y = pi r by
-// their Taylor series through y^5 and y^6 (|y| <= pi/256: truncation below
-// 1e-17); then the angle-addition formulas.  About 20 FP64 operations and one
-// cached 16-byte load; abs. error a few 1e-16.
-__device__ __forceinline__ void sincospi_tab(double x, double &sn, double &cs) {
-    const double n = rint(x * 128.0);
-    const double r = fma(n, -1.0 / 128.0, x);
+// sin(pi x) and cos(pi x) of x = y / 128 for the phase factor of a uv point,
+// by table and series: n = rint(y) and r = (y - n) / 128, |r| <= 1/256 (y - n
+// is exact); (cos, -sin)(pi n / 128) is entry n mod 256 of the length-256
+// twiddle row (exp(-2 pi i m / 256), stored at [256, 512)); sin and cos of
+// z = pi r by their Taylor series through z^5 and z^6 (|z| <= pi/256:
+// truncation below 1e-17); then the angle-addition formulas.  About 18 FP64
+// operations and one cached 16-byte load; abs. error a few 1e-16.
+__device__ __forceinline__ void sincospi_tab(double y, double &sn, double &cs) {
+    const double n = rint(y);
     const double m = fma(-256.0, floor(n * (1.0 / 256.0)), n);  // n mod 256
-    const int idx = (int)fmin(fmax(m, 0.0), 255.0);               // NaN -> 0
-    const c2<double> t = g_tw_d[256 + idx];
-    const double y = r * 3.141592653589793;
-    const double y2 = y * y;
-    const double sb = fma(y * y2, fma(y2, 1.0 / 120.0, -1.0 / 6.0), y);
-    const double cb = fma(y2, fma(y2, fma(y2, -1.0 / 720.0, 1.0 / 24.0), -0.5), 1.0);
+    const uint32_t idx = (uint32_t)(int)fmin(fmax(m, 0.0), 255.0);  // NaN -> 0
+    const c2<double> t = *(const c2<double> *)((const char *)(g_tw_d + 256) + idx * 16u);
+    const double z = (y - n) * (3.141592653589793 / 128.0);
+    const double z2 = z * z;
+    const double sb = fma(z * z2, fma(z2, 1.0 / 120.0, -1.0 / 6.0), z);
+    const double cb = fma(z2, fma(z2, fma(z2, -1.0 / 720.0, 1.0 / 24.0), -0.5), 1.0);
     sn = fma(-t.y, cb, t.x * sb);
     cs = fma(t.x, cb, t.y * sb);
 }
@@ -514,8 +513,15 @@ struct SampleArgs {
     double cpa, spa, cinc;     // cos PA, sin PA, cos inc
     double cpa_du, spa_du;     // cos PA, sin PA times N dxy (= 1 / du)
     double dRA, dDec;
+    double ph_u, ph_v;         // 256 dRA, 256 dDec: 128 x 2 (u dRA + v dDec), exactly
     int jmax, imin, imax;      // valid stencil corners: j0 <= jmax, imin <= i0 <= imax
 };
+
+// exp(i theta) of a uv point, theta = 2 pi (u dRA + v dDec)
+__device__ __forceinline__ void phase_of(const SampleArgs &a, double u, double v, double &sn,
+                                         double &cs) {
+    sincospi_tab(fma(u, a.ph_u, v * a.ph_v), sn, cs);
+}
 
 constexpr int SAMPLE_NT = 256;
 constexpr int SAMPLE_PPT = 4;
@@ -579,9 +585,9 @@ __device__ __forceinline__ void finish(const Stencil<T> &st, c2<T> a00, c2<T> a1
     if (st.mirror) bi = -bi;
     br *= a.cinc;
     bi *= a.cinc;
-    // exp(i theta), theta = 2 pi (u dRA + v dDec) = pi * x
+    // exp(i theta), theta = 2 pi (u dRA + v dDec)
     double sn, cs;
-    sincospi_tab(2.0 * (u * a.dRA + v * a.dDec), sn, cs);
+    phase_of(a, u, v, sn, cs);
     Vre = br * cs - bi * sn;
     Vim = br * sn + bi * cs;
 }
@@ -644,7 +650,8 @@ __global__ __launch_bounds__(REDUCE_NT) void k_reduce(const double *__restrict__
 
 // Sampling of the real, p-even spectrum of a swept profile: node (q, p~)
 // holds SR[q * CS + |p~|], so the two rows of a stencil are the adjacent
-// pair starting at min(|p~0|, |p~0 + 1|).
+// pair starting at min(|p~0|, |p~0 + 1|).  Signed form, kept for the
+// geometry gradient, whose derivatives follow the mirrored orientation.
 template <typename T>
 struct StencilR {
     const T *c0;       // SR + q * CS + lo; row lo and lo + 1
@@ -680,6 +687,69 @@ __device__ __forceinline__ StencilR<T> locate_r(const T *__restrict__ S, const G
     return st;
 }
 
+// Even form, for the chi^2 samplers and the adjoint scatter.  The spectrum of
+// a swept profile is real and even in u' and in v' separately (the disc
+// before rotation is symmetric about both axes), and the piecewise-linear
+// interpolant of an even node sequence is itself even: the bilinear value at
+// (u', v') is the one at (|u'|, |v'|), read from the stored rows |p~| with
+// neither mirror nor row swap.  Validity is the decision locate_r takes on
+// the mirrored point (for integer bounds, floor(x) >= lo iff x >= lo and
+// floor(x) <= hi iff x < hi + 1); an invalid point gets a clamped stencil
+// inside the stored spectrum, whose value the caller discards.
+template <typename T>
+struct StencilE {
+    uint32_t off;      // byte offset of node (q, i) from SR: (q * CS + i) sizeof(T), below
+                       // 2^32 for N <= 8192; rows i and i + 1 are adjacent, column q + 1
+                       // is CS elements further
+    double s, t;       // weights of column q + 1 and of row i + 1
+    bool ok;
+    int q, i;
+};
+
+// The four node values of an even-form stencil: (q, i), (q, i+1), (q+1, i),
+// (q+1, i+1).  A uniform base plus a 32-bit offset per lane.
+template <typename T>
+__device__ __forceinline__ void nodes_e(const T *__restrict__ S, const StencilE<T> &st, int CS,
+                                        double &x0, double &x1, double &y0, double &y1) {
+    const char *b = (const char *)S;
+    const T *c = (const T *)(b + st.off);
+    const T *d = (const T *)(b + (st.off + (uint32_t)CS * (uint32_t)sizeof(T)));
+    x0 = c[0];
+    x1 = c[1];
+    y0 = d[0];
+    y1 = d[1];
+}
+
+template <typename T>
+__device__ __forceinline__ StencilE<T> locate_e(const T *__restrict__ S, const Geom &g,
+                                                const SampleArgs &a, double u, double v) {
+    StencilE<T> st;
+    const double fu = u * a.cpa_du - v * a.spa_du;
+    const double fv = u * a.spa_du + v * a.cpa_du;
+    const double fvm = fu < 0.0 ? -fv : fv;  // v' of the mirrored point
+    const double au = fabs(fu), av = fabs(fv);
+    st.ok = (au < (double)a.jmax + 1.0) && (fvm >= (double)a.imin) &&
+            (fvm < (double)a.imax + 1.0);
+    // lower nodes clamped to the last valid ones (NaN -> the clamp): rows up
+    // to -imin = min(P, N/2) and columns up to jmax + 1 are stored
+    const double qf = fmin(floor(au), (double)a.jmax);
+    const double i0 = fmin(floor(av), (double)(-a.imin - 1));
+    st.s = au - qf;
+    st.t = av - i0;
+    st.q = (int)qf;
+    st.i = (int)i0;
+    st.off = ((uint32_t)st.q * (uint32_t)g.CS + (uint32_t)st.i) * (uint32_t)sizeof(T);
+    return st;
+}
+
+// Bilinear value from the four nodes (row i: a00, a01; row i + 1: a10, a11;
+// second index the column).
+__device__ __forceinline__ double bilerp(double a00, double a01, double a10, double a11, double s,
+                                         double t) {
+    const double b0 = fma(s, a01 - a00, a00), b1 = fma(s, a11 - a10, a10);
+    return fma(t, b1 - b0, b0);
+}
+
 template <typename T, bool CHI2>
 __global__ __launch_bounds__(SAMPLE_NT) void k_sample_sym(
     const T *__restrict__ S, Geom g, SampleArgs a, const T *__restrict__ u,
@@ -705,46 +775,32 @@ __global__ __launch_bounds__(SAMPLE_NT) void k_sample_sym(
             ww[p] = in ? (double)w[k] : 0.0;
         }
     }
-    StencilR<T> st[PPT];
-    c2<T> lo0[PPT], lo1[PPT];
+    StencilE<T> st[PPT];
+    double x0[PPT], x1[PPT], y0[PPT], y1[PPT];
 #pragma unroll
     for (int p = 0; p < PPT; ++p) {
-        st[p] = locate_r<T>(S, g, a, uu[p], vv[p]);
-        lo0[p] = c2<T>{st[p].c0[0], st[p].c0[1]};
-        lo1[p] = c2<T>{st[p].c0[g.CS], st[p].c0[g.CS + 1]};
+        st[p] = locate_e<T>(S, g, a, uu[p], vv[p]);
+        nodes_e<T>(S, st[p], g.CS, x0[p], x1[p], y0[p], y1[p]);
     }
     double acc = 0.0;
     bool bad = false;
 #pragma unroll
     for (int p = 0; p < PPT; ++p) {
         const int64_t k = base + p * SAMPLE_NT;
-        if (k < a.M) {
-            double Vre, Vim;
-            if (!st[p].ok) {
-                Vre = __builtin_nan("");
-                Vim = __builtin_nan("");
-                bad = true;
-            } else {
-                // a(q, p~0), a(q, p~0+1), a(q+1, p~0), a(q+1, p~0+1)
-                const double a00 = st[p].swap ? lo0[p].y : lo0[p].x;
-                const double a10 = st[p].swap ? lo0[p].x : lo0[p].y;
-                const double a01 = st[p].swap ? lo1[p].y : lo1[p].x;
-                const double a11 = st[p].swap ? lo1[p].x : lo1[p].y;
-                const double s = st[p].s, t = st[p].t;
-                const double b = (1.0 - t) * ((1.0 - s) * a00 + s * a01) +
-                                 t * ((1.0 - s) * a10 + s * a11);
-                double sn, cs;
-                sincospi_tab(2.0 * (uu[p] * a.dRA + vv[p] * a.dDec), sn, cs);
-                Vre = b * cs;  // cos(inc) = 1 on real spectra
-                Vim = b * sn;
-            }
-            if constexpr (CHI2) {
-                const double dr = Vre - rr[p];
-                const double di = Vim - ii[p];
-                acc += ww[p] * (dr * dr + di * di);
-            } else {
-                vis[perm ? (int64_t)perm[k] : k] = c2<T>{(T)Vre, (T)Vim};
-            }
+        const bool in = k < a.M;
+        double sn, cs;
+        phase_of(a, uu[p], vv[p], sn, cs);
+        double b = bilerp(x0[p], y0[p], x1[p], y1[p], st[p].s, st[p].t);
+        b = st[p].ok ? b : __builtin_nan("");
+        bad |= in && !st[p].ok;
+        const double Vre = b * cs, Vim = b * sn;  // cos(inc) = 1 on real spectra
+        if constexpr (CHI2) {
+            // no branch on `in`: a point past M has w = 0 and a valid stencil
+            const double dr = Vre - rr[p];
+            const double di = Vim - ii[p];
+            acc += ww[p] * (dr * dr + di * di);
+        } else {
+            if (in) vis[perm ? (int64_t)perm[k] : k] = c2<T>{(T)Vre, (T)Vim};
         }
     }
     if (bad) ctl->flag = 1;
