@@ -540,17 +540,16 @@ __device__ __forceinline__ void adj_rows_sym_body(const Geom &g, const T *__rest
         const double mult = ((r == 0 || r == N / 2) ? 1.0 : 2.0) * ((c == 0 || c == N / 2) ? 1.0 : 2.0);
         const double gw = gpix * mult * sw.pix_area;
         if (r == N / 2 && c == N / 2) {
-            atomicAdd(&hist[0], gw * (1.0 + sw.Rmin * sw.inv_dR));
-            atomicAdd(&hist[1], gw * (-sw.Rmin * sw.inv_dR));
+            atomicAdd(&hist[0], gw * (1.0 - sw.t0));
+            atomicAdd(&hist[1], gw * sw.t0);
             jlo = 0;
             jhi = jhi > 1 ? jhi : 1;
             continue;
         }
-        const double x = (double)(N / 2 - c) * sw.dxy;
+        const double xs = (double)(N / 2 - c) * sw.dxs;  // as sweep_pixel
         const double y = (double)(N / 2 - r) * sw.dxy;
-        const double xs = x * sw.inv_cos;
-        const double rho = sqrt_pos(xs * xs + y * y);
-        const double tt = (rho - sw.Rmin) * sw.inv_dR;
+        const double rho = sqrt_pos(fma(xs, xs, y * y));
+        const double tt = sweep_t(rho, sw);
         if (tt >= 0.0 && tt <= sw.tmax) {
             int j = (int)tt;
             j = j < sw.Nr - 2 ? j : sw.Nr - 2;

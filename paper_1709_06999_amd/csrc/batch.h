@@ -85,6 +85,8 @@ __device__ __forceinline__ SweepArgs sweep_of(const JobDesc &j) {
     a.inv_cos = j.inv_cos;
     a.pix_area = j.dxy * j.dxy;
     a.tmax = (double)(j.Nr - 1);
+    a.dxs = j.dxy * j.inv_cos;
+    a.t0 = -j.Rmin * j.inv_dR;
     return a;
 }
 

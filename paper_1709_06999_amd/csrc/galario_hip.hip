@@ -476,6 +476,8 @@ static SweepArgs make_sweep(int Nr, double Rmin, double dR, double dxy, double i
     a.pix_area = dxy * dxy;
     a.tmax = (double)(Nr - 1);
     a.tan_inc = std::tan(inc);
+    a.dxs = dxy * a.inv_cos;
+    a.t0 = -Rmin * a.inv_dR;
     return a;
 }
 

@@ -81,22 +81,28 @@ struct SweepArgs {
     int Nr;
     double Rmin, inv_dR, dxy, inv_cos, pix_area, tmax;
     double tan_inc;  // used by the inclination derivative of the sweep only
+    double dxs, t0;  // dxy / cos(inc); -Rmin / dR
 };
+
+// Profile coordinate of a pixel radius, t = (rho - Rmin) / dR, in one
+// rounding step (the forward sweep and its transpose use the same t).
+__device__ __forceinline__ double sweep_t(double rho, const SweepArgs &a) {
+    return fma(rho, a.inv_dR, a.t0);
+}
 
 // Square root of a squared pixel radius: x is a normal number well above
 // 2^-767 (pixel sizes are >= 1e-100 rad, checked on the host), so the
-// hardware reciprocal square root needs none of the general routine's
-// range scaling; one Goldschmidt step and two Newton corrections give the
-// correctly rounded root in practice (checked on 2e7 arguments).
+// hardware reciprocal square root (relative error about 5e-8) needs none of
+// the general routine's range scaling; one Goldschmidt step and one Newton
+// correction bring it within an ulp of the root (largest relative error
+// 1.1e-16 over 4e6 arguments from 1e-40 to 1e5, measured on this chip).
 __device__ __forceinline__ double sqrt_pos(double x) {
     const double y = __builtin_amdgcn_rsq(x);
     double g = x * y, h = 0.5 * y;
     const double r = fma(-g, h, 0.5);
     g = fma(g, r, g);
     h = fma(h, r, h);
-    double d = fma(-g, g, x);
-    g = fma(d, h, g);
-    d = fma(-g, g, x);
+    const double d = fma(-g, g, x);
     return fma(d, h, g);
 }
 
@@ -111,17 +117,18 @@ __device__ __forceinline__ double sqrt_pos(double x) {
 template <typename PI>
 __device__ __forceinline__ double sweep_pixel(PI I, int N, int r, int c, const SweepArgs &a) {
     const bool centre = (r == N / 2) && (c == N / 2);
-    const double x = (double)(N / 2 - c) * a.dxy;
+    const double xs = (double)(N / 2 - c) * a.dxs;  // x / cos(inc)
     const double y = (double)(N / 2 - r) * a.dxy;
-    const double xs = x * a.inv_cos;
-    const double rho = sqrt_pos(fmax(xs * xs + y * y, 1e-300));
-    const double t = (rho - a.Rmin) * a.inv_dR;
-    const int j = (int)fmin(fmax(t, 0.0), (double)(a.Nr - 2));
+    const double rho = sqrt_pos(fmax(fma(xs, xs, y * y), 1e-300));
+    const double t = sweep_t(rho, a);
+    const uint32_t j = (uint32_t)(int)fmin(fmax(t, 0.0), (double)(a.Nr - 2));
     const double f = t - (double)j;
     // a multiply by 0 or 1 rather than a select, which the compiler would
     // turn back into a branch around the loads' use
     const double m = (centre || (t >= 0.0 && t <= a.tmax)) ? a.pix_area : 0.0;
-    return ((1.0 - f) * (double)I[j] + f * (double)I[j + 1]) * m;
+    const auto Ij = I + j;  // I[j], I[j + 1]: one 16-byte load
+    const double I0 = (double)Ij[0], I1 = (double)Ij[1];
+    return fma(f, I1 - I0, I0) * m;
 }
 
 // d pixel / d inc of the sweep (not in the paper): on the segment that
@@ -131,12 +138,11 @@ __device__ __forceinline__ double sweep_pixel(PI I, int N, int r, int c, const S
 template <typename PI>
 __device__ __forceinline__ double sweep_pixel_dinc(PI I, int N, int r, int c, const SweepArgs &a) {
     const bool centre = (r == N / 2) && (c == N / 2);
-    const double x = (double)(N / 2 - c) * a.dxy;
+    const double xs = (double)(N / 2 - c) * a.dxs;  // as sweep_pixel
     const double y = (double)(N / 2 - r) * a.dxy;
-    const double xs = x * a.inv_cos;
-    const double rho = sqrt_pos(fmax(xs * xs + y * y, 1e-300));  // as sweep_pixel
-    const double t = (rho - a.Rmin) * a.inv_dR;
-    const int j = (int)fmin(fmax(t, 0.0), (double)(a.Nr - 2));
+    const double rho = sqrt_pos(fmax(fma(xs, xs, y * y), 1e-300));
+    const double t = sweep_t(rho, a);
+    const uint32_t j = (uint32_t)(int)fmin(fmax(t, 0.0), (double)(a.Nr - 2));
     const double v = ((double)I[j + 1] - (double)I[j]) * a.inv_dR *
                      (xs * xs * a.tan_inc / rho) * a.pix_area;
     return (!centre && t >= 0.0 && t <= a.tmax) ? v : 0.0;
