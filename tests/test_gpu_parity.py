@@ -244,6 +244,80 @@ def test_off_grid_points_are_flagged_nan():
     assert gal.read_status() == 0
 
 
+# (u', v') in grid units and whether the stencil lies inside the spectrum
+# (App. D: lower v' node in [-N/2, N/2 - 2] on the mirrored point, lower u'
+# node <= N/2 - 1), for N = 32
+PROFILE_EDGE_POINTS = [
+    ((0.0, -1.0), True), ((0.0, -3.0), True), ((2.5, -15.0), True), ((1.0, -16.0), True),
+    ((0.0, 14.5), True), ((-3.0, 2.0), True), ((-3.0, 16.0), True), ((15.5, 0.0), True),
+    ((0.0, 0.0), True), ((-2.25, -7.0), True),
+    ((3.0, -16.5), False), ((3.0, 15.0), False), ((-3.0, -15.0), False), ((16.0, 0.0), False),
+    ((-16.0, 1.0), False),
+]
+
+
+@pytest.mark.parametrize("dtype", DTYPES)
+def test_profile_edge_points_match_oracle(dtype):
+    # swept profiles are sampled from their real, even spectrum; points on node
+    # lines, on the validity limits and on both sides of the mirror, at exact
+    # grid coordinates (N dxy = 2^-20, PA = 0), against the oracle's App. D
+    # rule and values
+    dev = device()
+    gal = _gal()
+    import torch
+
+    # the status flag lives in the workspace of the call's precision
+    tdt = torch.float64 if dtype == np.float64 else torch.float32
+    status = lambda: gal.read_status(tdt)
+    N, dxy = 32, 2.0 ** -25
+    du = 1.0 / (N * dxy)
+    pts = np.array([p for p, _ in PROFILE_EDGE_POINTS])
+    ok = np.array([k for _, k in PROFILE_EDGE_POINTS])
+    u, v = pts[:, 0] * du, pts[:, 1] * du
+    r = np.linspace(0.0, 1.0, 64)
+    I = rounded((1.0 + 3.0 * np.exp(-(r / 0.3) ** 2)) / dxy ** 2, dtype)
+    Rmin, dR, inc = 0.0, 1.2 * N * dxy / 63, 0.4
+    Vo = oracle.sampleProfile(I, Rmin, dR, N, dxy, u, v, inc)
+    assert np.array_equal(np.isfinite(Vo), ok)
+    assert status() == 0
+    Vg = gal.sampleProfile(t(I, dtype, dev), Rmin, dR, N, dxy, t(u, dtype, dev), t(v, dtype, dev),
+                           inc).cpu().numpy()
+    assert np.array_equal(np.isfinite(Vg), ok)
+    assert_vis_close(Vg[ok], Vo[ok], dtype, "profile edge points")
+    assert status() == 1
+    # chi^2 over the valid points, then with the invalid ones: NaN and flagged
+    rng = np.random.default_rng(11)
+    re, im, w = rng.normal(size=u.size), rng.normal(size=u.size), rng.uniform(0.5, 1.5, u.size)
+    args = [t(a[ok], dtype, dev) for a in (u, v, re, im, w)]
+    c2g = float(gal.chi2Profile(t(I, dtype, dev), Rmin, dR, N, dxy, *args, inc))
+    c2o = oracle.chi2(Vo[ok], *(rounded(a[ok], dtype) for a in (re, im, w)))
+    dV = np.abs(Vg[ok] - Vo[ok]) + np.abs(Vo[ok]) * np.finfo(dtype).eps
+    assert abs(c2g - c2o) <= chi2_bound(c2o, dV, rounded(w[ok], dtype)), (c2g, c2o)
+    assert status() == 0
+    c2n = float(gal.chi2Profile(t(I, dtype, dev), Rmin, dR, N, dxy,
+                                *(t(a, dtype, dev) for a in (u, v, re, im, w)), inc))
+    assert np.isnan(c2n)
+    assert status() == 1
+    # the valid points within the radius a dataset accepts (rho <= (N/2 - 1) du,
+    # checked on the host) as a resident dataset: its own call and a one-job batch
+    inr = ok & (np.hypot(u, v) <= (N / 2 - 1) * du)
+    assert inr.sum() >= 5
+    ds = gal.Dataset(*(t(a[inr], dtype, dev) for a in (u, v, re, im, w)))
+    It = t(I, dtype, dev)
+    c2o = oracle.chi2(Vo[inr], *(rounded(a[inr], dtype) for a in (re, im, w)))
+    dV = np.abs(Vg[inr] - Vo[inr]) + np.abs(Vo[inr]) * np.finfo(dtype).eps
+    c2d = float(ds.chi2Profile(It, Rmin, dR, N, dxy, inc, 0.0, 0.0, 0.0))
+    geo = torch.tensor([Rmin, dR, inc, 0.0, 0.0, 0.0], dtype=torch.float64, device=dev)
+    b = gal.Batch([{"ds": ds, "kind": gal.JOB_PROFILE, "Nxy": N, "dxy": dxy, "model": It,
+                    "geo": geo}])
+    c2b = float(b.chi2().cpu()[0])
+    b.close()
+    ds.close()
+    for c in (c2d, c2b):
+        assert abs(c - c2o) <= chi2_bound(c2o, dV, rounded(w[inr], dtype)), (c, c2o)
+    assert status() == 0
+
+
 def test_host_side_errors():
     dev = device()
     gal = _gal()
