@@ -323,6 +323,30 @@ def test_sweep_symmetry_and_profile_visibilities_are_real():
     del N
 
 
+def test_swept_profile_visibilities_are_even_in_u_and_v():
+    # the swept disc before rotation is symmetric about both axes, so its grid
+    # spectrum is real and even in u and in v separately, and so is the
+    # bilinear interpolant of it (Sec. 3.4; App. D's mirror included): at
+    # PA = 0 and zero offsets V(u, v) = V(-u, v) = V(u, -v) = V(-u, -v), also
+    # between nodes and across the v = 0 line.  A mirror that reads the wrong
+    # node, or a row index off by one (0.8 of max|V| for one row), breaks it.
+    case = wl.random_case(64, 10, seed=121, kind="profile")
+    N, dxy = case.N, case.dxy
+    du = 1.0 / (N * dxy)
+    rng = np.random.default_rng(5)
+    u = np.concatenate([rng.uniform(0.0, N / 2 - 1.5, 300), [0.3, 2.7, 0.0]]) * du
+    v = np.concatenate([rng.uniform(-(N / 2 - 1.5), N / 2 - 1.5, 300), [-0.3, 0.4, -3.5]]) * du
+
+    def V(uu, vv):
+        return oracle.sampleProfile(case.I, case.Rmin, case.dR, N, dxy, uu, vv, inc=case.inc)
+
+    V0 = V(u, v)
+    scale = np.max(np.abs(V0))
+    for W in (V(-u, v), V(u, -v), V(-u, -v)):
+        assert np.max(np.abs(W - V0)) <= 1e-13 * scale
+    assert np.max(np.abs(V0.imag)) <= 1e-14 * scale
+
+
 def test_profile_path_is_image_path_of_sweep():
     case = wl.random_case(64, 300, seed=111, kind="profile")
     kw = dict(PA=case.PA, dRA=case.dRA, dDec=case.dDec)
