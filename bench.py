@@ -39,6 +39,11 @@ TRAFFIC_FILE = os.path.join(ROOT, "profiles", "hbm_traffic__chi2Profile_2048_M1e
 METRIC = "χ² evals/s at 2048², 1M uv (FP64), batched/served vs plain; p50/p99 latency"
 
 
+def progress(what):
+    """One line on stderr per section (the JSON result goes to stdout)."""
+    print(f"bench: {what}", file=sys.stderr, flush=True)
+
+
 def _ensure_built():
     from paper_1709_06999_amd import _native
 
@@ -108,6 +113,63 @@ def sample_flops(M, K=1):
     return {"kb_sample_sym_chi2": float(K) * M * SAMPLE_FLOPS_PER_POINT}
 
 
+SAMPLE_IMG_FLOPS_PER_POINT = 48  # per image job and point: rotation + deprojection 7, fractions
+                                 # 2, weights 5, complex bilinear 14, mirror and flux 2, phase
+                                 # argument 3, sin + cos 2, V 6, chi^2 term 7
+RIDGE = FP64_PEAK_TFLOPS * 1e12 / (HBM_PEAK_GBS * 1e9)   # flop per byte
+
+
+def image_alg(N, M, Q, P, p=8):
+    """Algorithmic bytes and flops of the three kernels of one chi2Image on a
+    dataset (columns [0, Q), rows [-P, P] of the complex half spectrum).  Row
+    pass: each real row of length N as a complex FFT of length N/2 (5 L log2 L)
+    and the split into Q outputs (12 flops each); column pass: Q complex FFTs
+    of length N."""
+    inter = N * Q * 2 * p
+    spec = Q * (2 * P + 1) * 2 * p
+    h = N // 2
+    lg = 5.0 * N * math.log2(N)
+    ab = {"k_rows_image": N * N * p + inter, "k_cols": inter + spec,
+          "k_sample_chi2": 5 * p * M + spec, "k_reduce": 8 * ((M + 1023) // 1024) + 8,
+          # gradient: the scatter grid written once, transposed passes (columns:
+          # grid -> N x Q intermediate; rows: intermediate -> N^2 gradient)
+          "k_sample_scatter": 5 * p * M + 2 * spec, "k_adj_cols": spec + inter,
+          "k_adj_rows": inter + N * N * p}
+    fl = {"k_rows_image": N * (5.0 * h * math.log2(h) + 12.0 * Q), "k_cols": Q * lg,
+          "k_sample_chi2": float(M) * SAMPLE_IMG_FLOPS_PER_POINT,
+          "k_sample_scatter": float(M) * (SAMPLE_IMG_FLOPS_PER_POINT + 24),
+          "k_adj_cols": Q * lg, "k_adj_rows": (N // 2) * lg}
+    return ab, fl
+
+
+def kernel_roofline(kern, alg_bytes, alg_flops):
+    """Annotate per-kernel times with algorithmic GB/s and TFLOP/s and return
+    the roofline of the kernel with the largest share of the time: bound by
+    HBM when its arithmetic intensity is below the FP64 ridge, else by the
+    FP64 vector ALUs."""
+    for k, x in kern.items():
+        t = x["avg_us"] * 1e-6
+        if k in alg_bytes:
+            x["alg_bytes"] = alg_bytes[k]
+            x["alg_GBps"] = alg_bytes[k] / t / 1e9
+        if k in alg_flops:
+            x["alg_flops"] = alg_flops[k]
+            x["alg_TFLOPs"] = alg_flops[k] / t / 1e12
+    dom = max((k for k in kern if k in alg_bytes), key=lambda k: kern[k]["avg_us"])
+    x = kern[dom]
+    fl = alg_flops.get(dom, 0.0)
+    if fl / alg_bytes[dom] >= RIDGE:
+        r = {"bound": "alu", "kernel": dom, "achieved": round(x["alg_TFLOPs"], 3),
+             "peak": FP64_PEAK_TFLOPS, "unit": "TFLOP/s",
+             "frac": round(x["alg_TFLOPs"] / FP64_PEAK_TFLOPS, 4)}
+    else:
+        r = {"bound": "hbm", "kernel": dom, "achieved": round(x["alg_GBps"], 1),
+             "peak": HBM_PEAK_GBS, "unit": "GB/s", "frac": round(x["alg_GBps"] / HBM_PEAK_GBS, 4)}
+    r.update({"alg_bytes_per_launch": alg_bytes[dom], "alg_flops_per_launch": fl,
+              "avg_us": round(x["avg_us"], 3)})
+    return r
+
+
 def source_digest():
     """SHA-256 over the HIP sources (file names and contents, sorted): ties
     stored counter readings to the kernels they were taken from."""
@@ -167,16 +229,69 @@ def _kernel_times(gal, fn, steps, torch):
     return {k: {"avg_us": 1e3 * ms / n, "launches": n} for k, (ms, n) in times.items()}
 
 
+def image_bench(gal, torch, np, dev, case, dtype, steps, warmup, grad=False, raw=False):
+    """Plain chi2Image calls (one evaluation per call) on a case: evals/s,
+    p50/p99 latency, per-kernel times and the dominant kernel's roofline; on
+    a device-resident dataset, or with raw arrays (raw=True: the full
+    spectrum, uv range checked per point).  grad: chi2Image + gradient."""
+    p = 8 if dtype == torch.float64 else 4
+    arr = lambda a: torch.as_tensor(np.ascontiguousarray(a), dtype=dtype, device=dev)
+    img = arr(case.image)
+    u, v = arr(case.u), arr(case.v)
+    kw = dict(PA=case.PA, dRA=case.dRA, dDec=case.dDec, inc=case.inc)
+    model = gal.sampleImage(img, case.dxy, u, v, **kw)
+    re = (model.real + arr(case.noise_re)).contiguous()
+    im = (model.imag + arr(case.noise_im)).contiguous()
+    w = arr(case.w)
+    out = torch.empty((), dtype=torch.float64, device=dev)
+    ds = None
+    if raw:
+        Q, P = case.N // 2 + 1, case.N // 2
+        call = lambda: gal.chi2Image(img, case.dxy, u, v, re, im, w, out=out, **kw)
+    else:
+        ds = gal.Dataset(u, v, re, im, w)
+        Q, P = ds.geometry(case.N, case.dxy)
+        if grad:
+            call = lambda: ds.chi2Image_grad(img, case.dxy, **kw)
+        else:
+            call = lambda: ds.chi2Image(img, case.dxy, out=out, **kw)
+    ms = _timed(call, steps, warmup, torch)
+    kern = _kernel_times(gal, call, max(steps // 4, 10), torch)
+    lat = []
+    for _ in range(min(steps, 200)):
+        a = time.perf_counter()
+        call()
+        torch.cuda.synchronize()
+        lat.append((time.perf_counter() - a) * 1e3)
+    ab, fl = image_alg(case.N, case.M, Q, P, p)
+    roof = kernel_roofline(kern, ab, fl)
+    if ds is not None:
+        ds.close()
+    rnd = {k: {kk: (round(vv, 3) if isinstance(vv, float) else vv) for kk, vv in x.items()}
+           for k, x in kern.items()}
+    return {"value": round(1e3 / ms, 1),
+            "unit": "chi2+grad evals/s" if grad else "chi2 evals/s",
+            "ms_per_eval": round(ms, 5),
+            "latency_ms": {"p50": round(float(np.percentile(lat, 50)), 4),
+                           "p99": round(float(np.percentile(lat, 99)), 4)},
+            "dtype": "f64" if p == 8 else "f32", "Nxy": case.N, "M": case.M,
+            "spectrum_cols_Q": Q, "spectrum_rows_P": P,
+            "form": "raw arrays (full spectrum)" if raw else "device-resident dataset",
+            "kernels": rnd, "roofline": roof}
+
+
 def cube_bench(gal, torch, np, dev, steps, warmup):
     """The batched configuration: a 64-channel FP32 cube at 1024^2 (ragged M
-    2e5..1e6, frequency-scaled uv sets) plus 32 FP32 models of 512^2..4096^2
-    on two datasets, as one planned batch replayed from a HIP graph, against
-    the same 96 evaluations made one call at a time."""
+    2e5..1e6, frequency-scaled uv sets) plus 32 FP32 chi2Image models of
+    512^2..4096^2 (20 blobs each, each on its own observation, M 1e5..2e6), as
+    one planned batch replayed from a HIP graph, against the same 96
+    evaluations made one call at a time."""
     import workloads as wl
 
     f32 = lambda a: torch.as_tensor(np.ascontiguousarray(a, dtype=np.float32), device=dev)
-    jobs, keep, calls = [], [], []
-    for c in wl.spectral_cube(64, 1024):
+    jobs, calls = [], []
+    sizes = {}
+    for c in list(wl.spectral_cube(64, 1024)) + list(wl.mixed_models(32)):
         ds = gal.Dataset(f32(c.u), f32(c.v), f32(c.noise_re), f32(c.noise_im), f32(c.w))
         img = f32(c.image)
         geo = torch.tensor([0.0, 1.0, c.inc, c.PA, c.dRA, c.dDec], dtype=torch.float64, device=dev)
@@ -184,22 +299,9 @@ def cube_bench(gal, torch, np, dev, steps, warmup):
                      "geo": geo})
         calls.append(lambda ds=ds, img=img, c=c: ds.chi2Image(img, c.dxy, c.PA, c.dRA, c.dDec,
                                                               c.inc))
-        keep.append((ds, img, geo))
-    sets, models = wl.mixed_models(32)
-    dsets = [gal.Dataset(*(f32(a) for a in st)) for st in sets]
-    for m in models:
-        I = f32(m["I"])
-        geo = torch.tensor([m["Rmin"], m["dR"], m["inc"], m["PA"], m["dRA"], m["dDec"]],
-                           dtype=torch.float64, device=dev)
-        ds = dsets[m["set"]]
-        jobs.append({"ds": ds, "kind": gal.JOB_PROFILE, "Nxy": m["N"], "dxy": m["dxy"],
-                     "model": I, "geo": geo})
-        calls.append(lambda ds=ds, I=I, m=m: ds.chi2Profile(I, m["Rmin"], m["dR"], m["N"],
-                                                            m["dxy"], m["inc"], m["PA"],
-                                                            m["dRA"], m["dDec"]))
-        keep.append((I, geo))
+        sizes[c.N] = sizes.get(c.N, 0) + 1
     b = gal.Batch(jobs)
-    tuned = gal.autotune_batch(b, 1024, torch.float32)
+    tuned = {N: gal.autotune_batch(b, N, torch.float32) for N in sorted(sizes)}
     side = torch.cuda.Stream(device=dev)
     side.wait_stream(torch.cuda.current_stream(dev))
     with torch.cuda.stream(side):
@@ -214,29 +316,65 @@ def cube_bench(gal, torch, np, dev, steps, warmup):
     graph.replay()
     torch.cuda.synchronize()
     same = bool(torch.equal(eager, b.out))
+    kern = _kernel_times(gal, b.chi2, max(steps // 4, 10), torch)
     ms_plain = _timed(lambda: [f() for f in calls], max(steps // 4, 10), 2, torch)
     n = len(jobs)
     info = b.info()
+    M_tot = sum(j["ds"].M for j in jobs)
     b.close()
-    for ds, *_ in keep[:64]:
-        ds.close()
-    for ds in dsets:
-        ds.close()
+    for j in jobs:
+        j["ds"].close()
+    rnd = {k: {kk: (round(vv, 3) if isinstance(vv, float) else vv) for kk, vv in x.items()}
+           for k, x in kern.items()}
     return {"jobs": n, "fft_groups": info["fft_groups"], "sample_groups": info["sample_groups"],
             "batched": {"value": round(n * 1e3 / ms_graph, 1), "unit": "chi2 evals/s",
-                        "ms_per_batch": round(ms_graph, 4), "form": "one HIP-graph replay"},
+                        "ms_per_batch": round(ms_graph, 4), "form": "one HIP-graph replay",
+                        "kernels": rnd},
             "plain": {"value": round(n * 1e3 / ms_plain, 1), "unit": "chi2 evals/s",
                       "ms_per_96_calls": round(ms_plain, 4)},
-            "batched_vs_plain": round(ms_plain / ms_graph, 3), "fft_variants_1024": tuned,
-            "graph_replay_matches_eager": same,
+            "batched_vs_plain": round(ms_plain / ms_graph, 3), "fft_variants": tuned,
+            "graph_replay_matches_eager": same, "models_per_size": sizes, "uv_points": M_tot,
             "workload": "64 channels at 1024^2 FP32 (frequency-scaled uv, M 2e5..1e6) + 32 FP32 "
-                        "profiles at 512^2..4096^2 on two 3e5-point datasets"}
+                        "chi2Image models of 20 blobs at 512^2..4096^2, each on its own "
+                        "observation (M 1e5..2e6)"}
 
 
-def serve_bench(gal, torch, np, dev, rates, n_req, warm, grad_frac, n_datasets, max_M):
+def _serve_rate(Server, Request, ex, params, rate, n_req, warm, grad_frac, rng):
+    """Poisson arrivals at `rate` of warm + n_req requests; statistics of the
+    last n_req (the warm-up requests complete before the counters start)."""
+    srv = Server(ex, max_batch=16, max_inflight=4).start()
+    gaps = rng.exponential(1.0 / rate, n_req + warm)
+    t_next = time.perf_counter()
+    futs = []
+    for i, prm in enumerate(params):
+        t_next += gaps[i]
+        while True:   # pace by sleeping: a spinning client would hold the GIL
+            dt = t_next - time.perf_counter()
+            if dt <= 0:
+                break
+            time.sleep(dt if dt > 2e-4 else 0)
+        futs.append(srv.submit(Request(grad=bool(rng.random() < grad_frac), **prm)))
+        if i == warm - 1:
+            for f in futs:
+                f.result(timeout=120)
+            srv.reset_stats()
+    for f in futs:
+        f.result(timeout=300)
+    srv.stop()
+    st = srv.stats()
+    return {"offered_req_per_s": rate,
+            "evals_per_s": round(st["evals_per_s"], 1) if st["evals_per_s"] else None,
+            "p50_ms": round(st["p50_ms"], 3), "p99_ms": round(st["p99_ms"], 3),
+            "requests": st["completed"], "micro_batches": st["batches"],
+            "host_launch_ms_per_batch": round(st["host_launch_ms_per_batch"], 3),
+            "peak_hbm_MB": round(st["peak_hbm_bytes"] / 1e6, 1)}
+
+
+def serve_bench(gal, torch, np, dev, rates, sat_rates, n_req, warm, grad_frac, n_datasets, max_M):
     """Poisson stream of chi2Profile (+ gradient) requests against resident
     datasets, served by the continuous-batching loop; latency and throughput
-    per arrival rate."""
+    per arrival rate, then offered rates raised until the served rate falls
+    behind (the loop's capacity)."""
     import workloads as wl
     from paper_1709_06999_amd.serve import GpuExecutor, Request, Server
 
@@ -256,36 +394,62 @@ def serve_bench(gal, torch, np, dev, rates, n_req, warm, grad_frac, n_datasets, 
     out = {}
     for rate in rates:
         params = wl.serve_requests(n_req + warm, seed=int(1551 + rate))
-        srv = Server(ex, max_batch=16, max_inflight=4).start()
-        gaps = rng.exponential(1.0 / rate, n_req + warm)
-        t_next = time.perf_counter()
-        futs = []
-        for i, prm in enumerate(params):
-            t_next += gaps[i]
-            while True:   # pace by sleeping: a spinning client would hold the GIL
-                dt = t_next - time.perf_counter()
-                if dt <= 0:
-                    break
-                time.sleep(dt if dt > 2e-4 else 0)
-            futs.append(srv.submit(Request(grad=bool(rng.random() < grad_frac), **prm)))
-            if i == warm - 1:
-                for f in futs:
-                    f.result(timeout=120)
-                srv.reset_stats()
-        for f in futs:
-            f.result(timeout=300)
-        srv.stop()
-        st = srv.stats()
-        out[str(rate)] = {"offered_req_per_s": rate,
-                          "evals_per_s": round(st["evals_per_s"], 1) if st["evals_per_s"] else None,
-                          "p50_ms": round(st["p50_ms"], 3), "p99_ms": round(st["p99_ms"], 3),
-                          "requests": st["completed"], "micro_batches": st["batches"],
-                          "host_launch_ms_per_batch": round(st["host_launch_ms_per_batch"], 3),
-                          "peak_hbm_MB": round(st["peak_hbm_bytes"] / 1e6, 1)}
+        out[str(rate)] = _serve_rate(Server, Request, ex, params, rate, n_req, warm, grad_frac, rng)
+    sat = {}
+    for rate in sat_rates:
+        params = wl.serve_requests(n_req + warm, seed=int(1551 + rate))
+        r = _serve_rate(Server, Request, ex, params, rate, n_req, warm, grad_frac, rng)
+        sat[str(rate)] = r
+        if r["evals_per_s"] is None or r["evals_per_s"] < 0.95 * rate:
+            break
+    allr = list(out.values()) + list(sat.values())
+    best = max(allr, key=lambda r: r["evals_per_s"] or 0.0)
+    for d in ex.datasets.values():
+        d.close()
     return {"workload": f"{n_datasets} resident datasets (M log-uniform in [1e5, {max_M:.0e}]), "
                         "requests: chi2Profile with Nxy in {512, 1024, 2048}, Nr in [512, 4096], "
                         f"{int(100 * grad_frac)}% with the adjoint gradient, Poisson arrivals",
-            "per_rate": out}
+            "per_rate": out, "saturation": sat,
+            "capacity": {"evals_per_s": best["evals_per_s"], "at_offered": best["offered_req_per_s"],
+                         "p50_ms": best["p50_ms"], "p99_ms": best["p99_ms"]}}
+
+
+def served_headline(gal, torch, np, dev, case, n_req, warm):
+    """The served form at the headline workload: chi^2 requests of perturbed
+    profiles (walkers) on the 2048^2, M = 1e6 dataset, all submitted at once
+    (a closed batch, as an ensemble sampler's step), so that the loop runs at
+    its capacity; evals/s and p50/p99 latency, to set beside the plain and
+    batched forms of the same evaluation."""
+    from paper_1709_06999_amd.serve import GpuExecutor, Request, Server
+
+    ex = GpuExecutor(dev, torch.float64, max_batch=16, max_inflight=4)
+    f64 = lambda a: torch.as_tensor(np.ascontiguousarray(a, dtype=np.float64), device=dev)
+    u, v = f64(case.u), f64(case.v)
+    Vm = gal.sampleProfile(f64(case.I), case.Rmin, case.dR, case.N, case.dxy, u, v, case.inc,
+                           case.PA, case.dRA, case.dDec)
+    ex.add_dataset("p2048", case.u, case.v, Vm.real.cpu().numpy() + case.noise_re,
+                   Vm.imag.cpu().numpy() + case.noise_im, case.w)
+    rng = np.random.default_rng(1104)
+    Ib = [case.I * (1.0 + 0.05 * rng.standard_normal(case.I.size)) for _ in range(64)]
+    mk = lambda k: Request("p2048", Ib[k % 64], case.Rmin, case.dR, case.N, case.dxy,
+                           inc=case.inc, PA=case.PA, dRA=case.dRA, dDec=case.dDec)
+    srv = Server(ex, max_batch=16, max_inflight=4).start()
+    for f in [srv.submit(mk(k)) for k in range(warm)]:
+        f.result(timeout=120)
+    srv.reset_stats()
+    futs = [srv.submit(mk(k)) for k in range(n_req)]
+    for f in futs:
+        f.result(timeout=300)
+    srv.stop()
+    st = srv.stats()
+    ex.datasets["p2048"].close()
+    return {"value": round(st["evals_per_s"], 1), "unit": "chi2 evals/s",
+            "p50_ms": round(st["p50_ms"], 3), "p99_ms": round(st["p99_ms"], 3),
+            "requests": st["completed"], "micro_batches": st["batches"],
+            "host_launch_ms_per_batch": round(st["host_launch_ms_per_batch"], 3),
+            "form": f"{n_req} chi2Profile requests (perturbed profiles) submitted at once to the "
+                    "continuous-batching loop (micro-batches of up to 16, 4 in flight), "
+                    "2048^2, Nr=4096, M=1e6, FP64"}
 
 
 def main():
@@ -316,9 +480,15 @@ def main():
     ap.add_argument("--no-serve", action="store_true", help="skip the served-load section")
     ap.add_argument("--serve-only", action="store_true",
                     help="run only the served-load section and print its JSON (profiling aid)")
-    ap.add_argument("--serve-rates", default="500,2000,5000",
+    ap.add_argument("--serve-rates", default="100,200,500,1000,2000,5000",
                     help="Poisson arrival rates (requests/s) of the served-load section")
-    ap.add_argument("--serve-requests", type=int, default=1000, help="timed requests per rate")
+    ap.add_argument("--serve-requests", type=int, default=2000, help="timed requests per rate")
+    ap.add_argument("--saturation-rates", default="10000,20000,50000,100000",
+                    help="offered rates above the sweep, raised until the served rate falls "
+                         "behind the offered one")
+    ap.add_argument("--no-images", action="store_true",
+                    help="skip the chi2Image sections (256^2, 2048^2 with gradient, 4096^2 "
+                         "FP64 / FP32)")
     ap.add_argument("--kind", choices=["profile", "image"], default="profile",
                     help="plain path: chi2Profile (default) or chi2Image of the swept image")
     args = ap.parse_args()
@@ -337,9 +507,11 @@ def main():
     dev = torch.device("cuda", 0)
     torch.cuda.set_device(dev)
     gal.init(0)
+    rates = [int(r) for r in args.serve_rates.split(",")]
+    sat_rates = [int(r) for r in args.saturation_rates.split(",")] if args.saturation_rates else []
     if args.serve_only:
-        served = serve_bench(gal, torch, np, dev, [int(r) for r in args.serve_rates.split(",")],
-                             args.serve_requests, 200, 0.5, 8, 2_000_000)
+        served = serve_bench(gal, torch, np, dev, rates, sat_rates, args.serve_requests, 200, 0.5,
+                             8, 2_000_000)
         print(json.dumps({"served": served}), flush=True)
         return
     case = wl.profile_2048()
@@ -370,6 +542,7 @@ def main():
         torch.cuda.synchronize()
         del a, b
 
+    progress("plain chi2Profile")
     # ---- plain: one evaluation per call --------------------------------
     out = torch.empty((), dtype=torch.float64, device=dev)
     if args.kind == "profile":
@@ -388,6 +561,7 @@ def main():
         lat.append((time.perf_counter() - a) * 1e3)
     lat = np.sort(np.array(lat))
 
+    progress("plain gradient")
     # ---- plain gradient: chi^2 and d chi^2 / d I per call ------------------
     grad_call = lambda: ds.chi2Profile_grad(I, case.Rmin, case.dR, N, case.dxy, **geo)
     ms_grad = _timed(grad_call, args.grad_steps, args.warmup, torch)
@@ -397,6 +571,7 @@ def main():
     geo_call = lambda: ds.chi2Profile_geograd(I, case.Rmin, case.dR, N, case.dxy, **geo)
     ms_geo = _timed(geo_call, args.grad_steps, args.warmup, torch)
 
+    progress("field of sources")
     # ---- a field of several sources (Sec. 3.2): copies of the profile at
     # other offsets and orientations, one scene; with the copies reading the
     # first one's spectrum, and with a transform per copy --------------------
@@ -419,10 +594,12 @@ def main():
     fb_shared.close()
     fb_own.close()
 
+    progress("cube + mixed models")
     # ---- the batched configuration: cube + mixed models in one graph ------
     cube = None if args.no_cube else cube_bench(gal, torch, np, dev, max(args.steps // 4, 20),
                                                 args.warmup)
 
+    progress("batched walkers (headline)")
     # ---- batched: K walkers (different profiles and geometry) per step ----
     K = args.batch
     rng = np.random.default_rng(1102)
@@ -461,6 +638,7 @@ def main():
     kern = _kernel_times(gal, batch.chi2, max(args.steps // 4, 20), torch)
     evals_per_s = K * 1e3 / ms_batch
 
+    progress("batched gradients")
     # ---- batched with gradients: the same K walkers, one batch_exec call ---
     gbuf = [torch.empty_like(Ib[k]) for k in range(K)]
     gjobs = batch.jobs
@@ -516,9 +694,11 @@ def main():
     roofline["step_hbm_frac"] = round(step_bytes / (ms_batch * 1e-3) / 1e9 / HBM_PEAK_GBS, 4)
 
     pb = path_bytes(N, Nr, M)
-    path_roofline = {
-        "definition": "evals/s x bytes per evaluation (full half spectrum, no pruning or "
-                      "batching credit) / 8 TB/s",
+    unpruned = {
+        "definition": "evals/s x the bytes of one evaluation counted without pruning, the "
+                      "even form or batching (full half spectrum written and read twice, "
+                      "every observation read per evaluation), over 8 TB/s.  Not a roofline "
+                      "fraction: the kernels do not move these bytes (see roofline)",
         "bytes_per_eval": pb,
         "plain": round(1e3 / ms_plain * pb["chi2"] / 1e9 / HBM_PEAK_GBS, 4),
         "batched": round(evals_per_s * pb["chi2"] / 1e9 / HBM_PEAK_GBS, 4),
@@ -526,11 +706,36 @@ def main():
         "batched_grad": round(K * 1e3 / ms_bgrad * pb["chi2_grad"] / 1e9 / HBM_PEAK_GBS, 4),
     }
 
+    progress("served load")
     served = None
     if not args.no_serve:
-        served = serve_bench(gal, torch, np, dev, [int(r) for r in args.serve_rates.split(",")],
-                             args.serve_requests, 200, 0.5, 8, 2_000_000)
+        served = serve_bench(gal, torch, np, dev, rates, sat_rates, args.serve_requests, 200, 0.5,
+                             8, 2_000_000)
+        served["headline"] = served_headline(gal, torch, np, dev, case, 8000, 500)
+        served["headline"]["served_vs_plain"] = round(served["headline"]["value"] /
+                                                      (1e3 / ms_plain), 3)
 
+    progress("chi2Image sections")
+    images = None
+    if not args.no_images:
+        isteps = max(args.grad_steps // 2, 50)
+        images = {
+            "gaussian_256_M1e4": image_bench(gal, torch, np, dev, wl.gaussian_image_256(),
+                                             torch.float64, isteps, args.warmup),
+            "blobs_2048_M1e6": image_bench(gal, torch, np, dev, wl.image_2048(), torch.float64,
+                                           isteps, args.warmup),
+            "blobs_2048_M1e6_grad": image_bench(gal, torch, np, dev, wl.image_2048(),
+                                                torch.float64, isteps // 2, args.warmup,
+                                                grad=True),
+        }
+        b4 = wl.blobs_4096()
+        images["blobs_4096_M5e6_f64"] = image_bench(gal, torch, np, dev, b4, torch.float64,
+                                                    isteps // 2, args.warmup)
+        images["blobs_4096_M5e6_f32"] = image_bench(gal, torch, np, dev, b4, torch.float32,
+                                                    isteps // 2, args.warmup)
+        del b4
+
+    progress("oracle baseline")
     cpu = None
     if not args.no_cpu_baseline:
         import oracle
@@ -543,10 +748,31 @@ def main():
             oracle.chi2Profile(case.I, case.Rmin, case.dR, N, case.dxy, case.u, case.v, nre, nim,
                                case.w, case.inc, case.PA, case.dRA, case.dDec)
             t_runs.append(time.perf_counter() - a)
+        cores = oracle.num_threads()
         cpu = {"value": round(1.0 / float(np.median(t_runs)), 5), "unit": "chi2 evals/s",
-               "cores": oracle.num_threads(), "kind": "oracle",
+               "cores": cores, "kind": "oracle",
                "sample": f"{len(t_runs)} full evaluation(s) of this workload by the FP64 "
-                         "direct-DFT oracle (O(N^3)), median time"}
+                         "direct-DFT oracle (O(N^3)), median time",
+               "nproc": os.cpu_count(),
+               "omp_num_threads": os.environ.get("OMP_NUM_THREADS")}
+        # one thread: the 256^2 chi2Image workload (median of 3) and this one (one run)
+        c0 = wl.gaussian_image_256()
+        oracle.set_num_threads(1)
+        try:
+            t0 = []
+            for _ in range(3):
+                a = time.perf_counter()
+                oracle.chi2Image(c0.image, c0.dxy, c0.u, c0.v, c0.noise_re, c0.noise_im, c0.w,
+                                 c0.PA, c0.dRA, c0.dDec, c0.inc)
+                t0.append(time.perf_counter() - a)
+            a = time.perf_counter()
+            oracle.chi2Profile(case.I, case.Rmin, case.dR, N, case.dxy, case.u, case.v, nre, nim,
+                               case.w, case.inc, case.PA, case.dRA, case.dDec)
+            t1 = time.perf_counter() - a
+        finally:
+            oracle.set_num_threads(cores)
+        cpu["one_thread"] = {"chi2Image_256_M1e4_evals_per_s": round(1.0 / float(np.median(t0)), 4),
+                             "chi2Profile_2048_M1e6_evals_per_s": round(1.0 / t1, 5)}
 
     rnd = lambda d: {k: {kk: (round(vv, 3) if isinstance(vv, float) else vv)
                          for kk, vv in x.items()} for k, x in d.items()}
@@ -600,8 +826,9 @@ def main():
                   "same_chi2": field_match,
                   "form": f"{S} copies of the 2048^2 profile (one scene) on the M=1e6 dataset; "
                           "persistent plan, one gal_batch_chi2 per evaluation"},
-        "path_roofline": path_roofline,
+        "evals_vs_unpruned_bytes": unpruned,
         "served": served,
+        "images": images,
         "kernels": rnd(kern),
         "roofline": roofline,
         "cpu_baseline": cpu,

@@ -87,7 +87,8 @@ size_t gal_workspace_bytes_f(int Nxy, int64_t M);
 /* Zero the control block (first 256 bytes) of a workspace, on `stream`. */
 int gal_workspace_init(void *ws, size_t ws_bytes, void *stream);
 /* Synchronise `stream`, return the workspace status flag in *status
- * (0 = fine, 1 = some uv point fell outside the half spectrum) and clear it. */
+ * (0 = fine; bit 1: some uv point fell outside the half spectrum; bit 2: a
+ * batch job's geometry row failed its checks) and clear it. */
 int gal_read_status(void *ws, void *stream, int *status);
 
 /* ---- the paper's calls (Sec. 2.2) on raw device arrays ---------------- */
@@ -317,9 +318,13 @@ int gal_dataset_image_size(const gal_dataset *ds, double f_min, double f_max, do
  * kernels read the current model arrays and geometry from the device pointers
  * in the jobs, so a plan -- and a HIP graph captured from gal_batch_chi2 -- is
  * reused while the caller rewrites those buffers between executions.  The
- * geometry is not checked at execution: cos(inc) <= 0 or dR <= 0 give a NaN
- * chi^2 for that job.  Creation checks everything else (like the dataset
- * calls), allocates the batch's device table and synchronises the device.
+ * geometry rows are checked on the device at every execution, as the single
+ * calls check them on the host (finite PA, inc, dRA, dDec, cos(inc) > 0;
+ * profiles: finite Rmin >= 0, dR > 0): a job that fails gets a NaN chi^2
+ * (that of its whole scene) and a NaN gradient, and the workspace status
+ * flag gets bit 2 (gal_read_status).  Creation checks everything else (like
+ * the dataset calls), allocates the batch's device table and synchronises
+ * the device.
  *
  * Scenes (Sec. 3.2: a field of several sources is the sum of the sources'
  * visibilities, each placed by its own phase shift).  Jobs with the same
@@ -368,7 +373,11 @@ int gal_batch_destroy(gal_batch *b);
  * (nullable) holds one gradient output per job (device, dataset precision:
  * image [Nxy*Nxy] or profile [Nr]; NULL = chi^2 only); gradient jobs run the
  * adjoint path of the gradient calls above.  Workspace:
- * gal_batch_exec_workspace_bytes (first 256 bytes zeroed once; 0 on error). */
+ * gal_batch_exec_workspace_bytes (first 256 bytes zeroed once; 0 on error).
+ * The host table is copied from pageable memory, which HIP stages before the
+ * call returns; because the plan is made at the call, a stream that is being
+ * captured into a graph is refused (GAL_ERR_UNSUPPORTED): capture
+ * gal_batch_chi2 of a created batch instead. */
 size_t gal_batch_exec_workspace_bytes(const gal_job *jobs, int n, void *const *grads);
 int gal_batch_exec(const gal_job *jobs, int n, double *chi2, void *const *grads, void *ws,
                    size_t ws_bytes, void *stream);

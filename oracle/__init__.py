@@ -62,6 +62,8 @@ def _load():
         build()
     lib = ctypes.CDLL(_SO)
     lib.orc_num_threads.restype = ctypes.c_int
+    lib.orc_set_num_threads.argtypes = [ctypes.c_int]
+    lib.orc_set_num_threads.restype = None
     lib.orc_sweep.argtypes = [_D, _I64, ctypes.c_double, ctypes.c_double, _I64,
                               ctypes.c_double, ctypes.c_double, _D]
     lib.orc_sweep.restype = ctypes.c_int
@@ -104,6 +106,11 @@ def _p(a: np.ndarray):
 def num_threads() -> int:
     """OpenMP threads the oracle uses (OMP_NUM_THREADS or all cores)."""
     return int(_load().orc_num_threads())
+
+
+def set_num_threads(n: int) -> None:
+    """Threads for later oracle calls (n < 1: all cores); timing only."""
+    _load().orc_set_num_threads(int(n))
 
 
 def sweep(I, Rmin, dR, N, dxy, inc=0.0) -> np.ndarray:

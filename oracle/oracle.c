@@ -34,6 +34,17 @@
 #define TWO_PI 6.283185307179586476925286766559
 #define TWO_PI_L 6.283185307179586476925286766559L
 
+/* Threads for the following calls (n < 1: all cores).  Timing only: the
+ * results do not depend on it. */
+void orc_set_num_threads(int n)
+{
+#ifdef _OPENMP
+    omp_set_num_threads(n >= 1 ? n : omp_get_num_procs());
+#else
+    (void)n;
+#endif
+}
+
 int orc_num_threads(void)
 {
 #ifdef _OPENMP

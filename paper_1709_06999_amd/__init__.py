@@ -34,7 +34,7 @@ __all__ = [
     "sample_spectrum", "Dataset", "Workspace", "read_status", "timing", "GalarioError",
     "version", "init", "autotune", "autotune_batch", "tune_get", "tune_set", "Batch", "profile_batch",
     "JOB_IMAGE", "JOB_PROFILE", "batch_exec", "chi2Image_grad", "chi2Profile_grad", "chi2_profile", "chi2_image",
-    "get_image_size",
+    "get_image_size", "STATUS_UV", "STATUS_GEO", "batch_exec_status", "exec_workspace_bytes",
 ]
 
 JOB_IMAGE = 0
@@ -132,17 +132,26 @@ def _ws(device: torch.device, dtype: torch.dtype, ws: Workspace | None) -> Works
     return _default_ws[key]
 
 
+STATUS_UV = 1    # a uv point fell outside the half spectrum (its samples are NaN)
+STATUS_GEO = 2   # a batch job's geometry row failed its checks (its chi^2 is NaN)
+
+
+def _read_status_buf(buf: torch.Tensor, dev: torch.device) -> int:
+    st = ctypes.c_int(0)
+    with torch.cuda.device(dev):
+        check(_lib().gal_read_status(_ptr(buf), _stream(dev), ctypes.byref(st)), "gal_read_status")
+    return int(st.value)
+
+
 def read_status(dtype: torch.dtype = torch.float64, device=None, ws: Workspace | None = None) -> int:
-    """1 if a uv point of a raw-array call fell outside the half spectrum since
-    the last read (its samples are NaN), else 0.  Synchronises the stream."""
+    """Status bits of the calls on this workspace since the last read, then
+    cleared: STATUS_UV if a uv point of a raw-array call fell outside the half
+    spectrum (its samples are NaN), else 0.  Synchronises the stream."""
     dev = torch.device("cuda", torch.cuda.current_device()) if device is None else torch.device(device)
     w = _ws(dev, dtype, ws)
     if w.buf.numel() == 0:
         return 0
-    st = ctypes.c_int(0)
-    with torch.cuda.device(dev):
-        check(_lib().gal_read_status(_ptr(w.buf), _stream(dev), ctypes.byref(st)), "gal_read_status")
-    return int(st.value)
+    return _read_status_buf(w.buf, dev)
 
 
 # ----------------------------------------------------------------------------
@@ -639,6 +648,12 @@ class Batch:
                                         _stream(self.device)), "Batch.chi2")
         return res
 
+    def status(self) -> int:
+        """Status bits of the executions since the last read, then cleared
+        (synchronises the current stream): STATUS_GEO if a job's geometry row
+        failed its checks (that job's chi^2 is NaN)."""
+        return _read_status_buf(self.ws, self.device)
+
     def close(self):
         if getattr(self, "_h", None) and self._h.value:
             with torch.cuda.device(self.device):
@@ -704,6 +719,39 @@ def batch_exec(jobs, grads=None, out: torch.Tensor | None = None,
         check(_lib().gal_batch_exec(arr, len(jobs), _ptr(res), gp, _ptr(buf), buf.numel(),
                                     _stream(dev)), "batch_exec")
     return res
+
+
+def batch_exec_status(device=None, ws: Workspace | None = None) -> int:
+    """Status bits of the batch_exec calls on this workspace (the default one
+    of the device if None) since the last read, then cleared."""
+    dev = torch.device("cuda", torch.cuda.current_device()) if device is None else torch.device(device)
+    if ws is None:
+        key = dev.index if dev.index is not None else torch.cuda.current_device()
+        ws = _exec_ws.get(key)
+    if ws is None or ws.buf.numel() == 0:
+        return 0
+    return _read_status_buf(ws.buf, dev)
+
+
+def exec_workspace_bytes(specs) -> int:
+    """Workspace bytes batch_exec needs for a job list, from the library's
+    planner on the host (no device work).  ``specs`` holds one tuple per job:
+    (dataset, kind, Nxy, dxy, Nr, grad) with Nr the profile length (0 for
+    images) and grad whether the job has a gradient output."""
+    n = len(specs)
+    arr = (_native.GalJob * n)()
+    gp = (ctypes.c_void_p * n)()
+    any_grad = False
+    for i, (ds, kind, Nxy, dxy, Nr, grad) in enumerate(specs):
+        # the planner reads no model or geometry value: any non-NULL address
+        arr[i] = _native.GalJob(ds._h.value, int(kind), int(Nxy), float(dxy), int(Nr), 256, 256,
+                                0, 0, None)
+        gp[i] = 256 if grad else None
+        any_grad = any_grad or bool(grad)
+    need = _lib().gal_batch_exec_workspace_bytes(arr, n, gp if any_grad else None)
+    if need == 0:
+        raise GalarioError(_native.GAL_ERR_SIZE, "exec_workspace_bytes")
+    return int(need)
 
 
 # ----------------------------------------------------------------------------

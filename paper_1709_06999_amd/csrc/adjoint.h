@@ -312,7 +312,7 @@ __global__ __launch_bounds__(SAMPLE_NT) void k_sample_scatter(
             if (in && st.ok) pa[p] = point_add_cplx<T>(st, wk * a.cinc, rr, ri, sn, cs);
         }
     }
-    if (bad) ctl->flag = 1;
+    if (bad) atomicOr(&ctl->flag, STATUS_UV);
     block_scatter<T, NV, SAMPLE_PPT>(A, g.CS, pa, tile, box);
     const double bs = block_sum(acc, red);
     if (threadIdx.x == 0) partials[blk] = bs;
@@ -373,7 +373,7 @@ __global__ __launch_bounds__(Cfg::NT) void k_adj_cols(Geom g, c2<T> *__restrict_
 // z = x_{2m} + i x_{2m+1}; grad[r][c] = -2 Re / Im of FFT(z)[c].
 template <typename T, typename Cfg>
 __device__ __forceinline__ void adj_rows_body(const Geom &g, const c2<T> *__restrict__ H,
-                                              T *__restrict__ grad, int blk) {
+                                              T *__restrict__ grad, int blk, bool nan_out = false) {
     constexpr int L = Cfg::L, B = Cfg::B, NT = Cfg::NT, E = Cfg::E;
     constexpr int N = L;
     constexpr int R0 = pass_radix(L, 1, Cfg::RMAX);
@@ -416,7 +416,8 @@ __device__ __forceinline__ void adj_rows_body(const Geom &g, const c2<T> *__rest
         const int r = 2 * m0 + rb;
         if (r >= N) continue;
         const c2<T> z = lds[Cfg::at(rb >> 1, c)];
-        grad[(size_t)r * N + c] = T(-2) * ((rb & 1) ? z.y : z.x);
+        const T gv = T(-2) * ((rb & 1) ? z.y : z.x);
+        grad[(size_t)r * N + c] = nan_out ? T(__builtin_nan("")) : gv;
     }
 }
 

@@ -43,11 +43,17 @@ struct JobDesc {
     double cpa, spa, cinc, dRA, dDec;  // sampling
     double cpa_du, spa_du;             // cos PA, sin PA times N dxy
     double Rmin, inv_dR, inv_cos;      // sweep (profiles)
+    int bad;                           // the geometry row failed its checks
+    int shared;                        // reads another job's spectrum (share > 0)
 };
 
 // one thread per job: the trigonometry and divisions every later block of
-// the job would otherwise repeat
-__global__ __launch_bounds__(64) void kb_prepare(JobDesc *__restrict__ jobs, int n) {
+// the job would otherwise repeat, and the checks the single calls make on the
+// host (finite PA, inc, offsets, cos(inc) > 0; for profiles finite dR > 0 and
+// Rmin >= 0).  A job that fails them is marked: its chi^2 (that of its scene)
+// and its gradient come out NaN, and the status flag gets STATUS_GEO.
+__global__ __launch_bounds__(64) void kb_prepare(JobDesc *__restrict__ jobs, int n,
+                                                 Control *ctl) {
     const int i = blockIdx.x * 64 + threadIdx.x;
     if (i >= n) return;
     JobDesc &j = jobs[i];
@@ -55,6 +61,14 @@ __global__ __launch_bounds__(64) void kb_prepare(JobDesc *__restrict__ jobs, int
     double sn, cs;
     sincos(geo[3], &sn, &cs);
     const double ci = cos(geo[2]);
+    // (a profile that reads another job's spectrum takes Rmin, dR and inc
+    // from that job: its own are not used)
+    const bool own_sweep = j.kind == 1 && !j.shared;
+    bool ok = isfinite(geo[3]) && isfinite(geo[4]) && isfinite(geo[5]);
+    if (j.kind == 0 || own_sweep) ok = ok && isfinite(geo[2]) && ci > 0.0;
+    if (own_sweep) ok = ok && isfinite(geo[0]) && geo[0] >= 0.0 && isfinite(geo[1]) && geo[1] > 0.0;
+    j.bad = ok ? 0 : 1;
+    if (!ok) atomicOr(&ctl->flag, STATUS_GEO);
     j.cpa = cs;
     j.spa = sn;
     j.cpa_du = cs * ((double)j.N * j.dxy);
@@ -393,7 +407,7 @@ __global__ __launch_bounds__(SAMPLE_NT) void kb_sample_chi2(const JobDesc *__res
         if ((threadIdx.x & 63) == 0)
             ((double *)(ws + J.part_off))[chunk * WAVES + (threadIdx.x >> 6)] = wsum;
     }
-    if (bad) ctl->flag = 1;
+    if (bad) atomicOr(&ctl->flag, STATUS_UV);
 }
 
 // KC: the kinds of the class's jobs -- 0 images, 1 profiles, 2 both (the kind
@@ -511,21 +525,27 @@ __global__ __launch_bounds__(SAMPLE_NT) void kb_sample_scene(const JobDesc *__re
         if ((threadIdx.x & 63) == 0)
             ((double *)(ws + L.part_off))[chunk * WAVES + (threadIdx.x >> 6)] = wsum;
     }
-    if (bad) ctl->flag = 1;
+    if (bad) atomicOr(&ctl->flag, STATUS_UV);
 }
 
 // chi2[j] = sum of the partials of job j's scene in a fixed order (one block
-// per job, as k_reduce).  Bitwise repeatable.
-__global__ __launch_bounds__(REDUCE_NT) void kb_reduce(const JobDesc *__restrict__ jobs,
+// per job, as k_reduce).  Bitwise repeatable.  NaN when a job of the scene
+// (the jobs sharing its partials) failed the geometry checks of kb_prepare.
+__global__ __launch_bounds__(REDUCE_NT) void kb_reduce(const JobDesc *__restrict__ jobs, int njobs,
                                                        const SGroup *__restrict__ groups,
                                                        const int *__restrict__ job_group,
                                                        const char *ws, double *__restrict__ chi2) {
     __shared__ double red[REDUCE_NT / 64];
+    __shared__ int any_bad;
     const int j = blockIdx.x;
     const JobDesc &J = jobs[j];
+    if (threadIdx.x == 0) any_bad = 0;
+    __syncthreads();
+    for (int k = threadIdx.x; k < njobs; k += REDUCE_NT)
+        if (jobs[k].bad && jobs[k].part_off == J.part_off) any_bad = 1;
     const int n = groups[job_group[j]].nblk * WAVES;
     const double tot = block_sum(strided_sum((const double *)(ws + J.part_off), n), red);
-    if (threadIdx.x == 0) chi2[j] = tot;
+    if (threadIdx.x == 0) chi2[j] = any_bad ? __builtin_nan("") : tot;
 }
 
 // ---- adjoint passes of gradient jobs: blockIdx.y selects the job ------------
@@ -540,7 +560,8 @@ template <typename T, typename Cfg>
 __global__ __launch_bounds__(Cfg::NT) void kb_adj_rows(const JobDesc *__restrict__ jobs,
                                                        const int *__restrict__ list, char *ws) {
     const JobDesc &j = jobs[list[blockIdx.y]];
-    adj_rows_body<T, Cfg>(geom_of(j), (const c2<T> *)(ws + j.a_off), (T *)j.grad, blockIdx.x);
+    adj_rows_body<T, Cfg>(geom_of(j), (const c2<T> *)(ws + j.a_off), (T *)j.grad, blockIdx.x,
+                          j.bad != 0);
 }
 
 template <typename T, typename Cfg>
@@ -568,7 +589,10 @@ __global__ __launch_bounds__(256) void kb_grad_out(const JobDesc *__restrict__ j
                                                    const int *__restrict__ list, const char *ws) {
     const JobDesc &j = jobs[list[blockIdx.y]];
     const int i = blockIdx.x * 256 + threadIdx.x;
-    if (i < j.Nr) sum_bins<T>((const double *)(ws + j.gi_off), j.Nr, (T *)j.grad, i);
+    if (i < j.Nr) {
+        sum_bins<T>((const double *)(ws + j.gi_off), j.Nr, (T *)j.grad, i);
+        if (j.bad) ((T *)j.grad)[i] = T(__builtin_nan(""));
+    }
 }
 
 }  // namespace gal

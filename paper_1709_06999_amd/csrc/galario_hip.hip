@@ -566,6 +566,17 @@ static int sample(bool real_spec, const void *S, const Geom &gs, const SampleArg
 }
 
 template <typename T>
+static int run_carved(const T *src, bool profile, const SweepArgs &sw, const Geom &g, double dxy,
+                      const Obs<T> &o, double PA, double dRA, double dDec, double inc, T *vis,
+                      double *chi2, const WS &w, hipStream_t s) {
+    Geom gs;
+    int rc = transform<T>(src, profile, sw, g, w.xt, s, gs);
+    if (rc) return rc;
+    const SampleArgs sa = make_sample(g, o.M, dxy, PA, dRA, dDec, inc);
+    return sample<T>(profile, w.xt, gs, sa, o, vis, chi2, w, s);
+}
+
+template <typename T>
 static int run_path(const T *src, bool profile, const SweepArgs &sw, const Geom &g, double dxy,
                     const Obs<T> &o, double PA, double dRA, double dDec, double inc, T *vis,
                     double *chi2, void *ws, size_t ws_bytes_, hipStream_t s) {
@@ -574,11 +585,7 @@ static int run_path(const T *src, bool profile, const SweepArgs &sw, const Geom 
     WS w;
     rc = carve<T>(ws, ws_bytes_, g.N, o.M, w);
     if (rc) return rc;
-    Geom gs;
-    rc = transform<T>(src, profile, sw, g, w.xt, s, gs);
-    if (rc) return rc;
-    const SampleArgs sa = make_sample(g, o.M, dxy, PA, dRA, dDec, inc);
-    return sample<T>(profile, w.xt, gs, sa, o, vis, chi2, w, s);
+    return run_carved<T>(src, profile, sw, g, dxy, o, PA, dRA, dDec, inc, vis, chi2, w, s);
 }
 
 // ---------------------------------------------------------------------------
@@ -1823,6 +1830,7 @@ static int plan_batch(const gal_job *jobs, int n, void *const *grads, size_t bas
     for (int i = 0; i < n; ++i) {
         if (!jobs[i].share) continue;
         JobDesc d = P.jobs[jobs[i].share - 1];
+        d.shared = 1;
         d.geo = jobs[i].geo;
         d.vis = jobs[i].vis;
         d.part_off = P.jobs[i].part_off;
@@ -1950,7 +1958,8 @@ static int batch_sample_any(const BatchPlan::SClass &c, bool grads, const BatchT
 }
 
 static int exec_plan(const BatchPlan &P, const BatchTables &t, char *ws, double *chi2, hipStream_t s) {
-    int rc = launch("kb_prepare", kb_prepare, dim3((P.n + 63) / 64), dim3(64), s, t.jobs, P.n);
+    int rc = launch("kb_prepare", kb_prepare, dim3((P.n + 63) / 64), dim3(64), s, t.jobs, P.n,
+                    (Control *)ws);
     if (rc) return rc;
     if (P.zero_end > P.zero_begin) {
         const int64_t zb = (int64_t)(P.zero_end - P.zero_begin);
@@ -1967,8 +1976,8 @@ static int exec_plan(const BatchPlan &P, const BatchTables &t, char *ws, double 
                          : batch_sample_any<float>(c, P.grads, t, ws, s);
         if (rc) return rc;
     }
-    rc = launch("kb_reduce", kb_reduce, dim3(P.n), dim3(REDUCE_NT), s, t.jobs, t.groups, t.job_group,
-                ws, chi2);
+    rc = launch("kb_reduce", kb_reduce, dim3(P.n), dim3(REDUCE_NT), s, t.jobs, P.n, t.groups,
+                t.job_group, ws, chi2);
     if (rc) return rc;
     for (const auto &f : P.agroups) {
         rc = f.prec == 8 ? batch_adj<double>(f, t, ws, s) : batch_adj<float>(f, t, ws, s);
@@ -2062,8 +2071,17 @@ int gal_batch_exec(const gal_job *jobs, int n, double *chi2, void *const *grads,
     P.zero_begin += tab;
     P.zero_end += tab;
     hipStream_t s = (hipStream_t)stream;
+    // the table is copied from host memory that is freed on return: a copy
+    // captured into a graph would read it at every replay
+    hipStreamCaptureStatus cap = hipStreamCaptureStatusNone;
+    GAL_HIP(hipStreamIsCapturing(s, &cap));
+    if (cap != hipStreamCaptureStatusNone)
+        return fail(GAL_ERR_UNSUPPORTED,
+                    "gal_batch_exec cannot be captured into a graph (its plan is made at the "
+                    "call): capture gal_batch_chi2 of a gal_batch_create plan instead");
     char *w = (char *)ws;
     const std::vector<char> h = table_image(P);
+    // a copy from pageable memory: HIP stages the source before returning
     GAL_HIP(hipMemcpyAsync(w + 256, h.data(), h.size(), hipMemcpyHostToDevice, s));
     return exec_plan(P, tables_at(P, w + 256), w, chi2, s);
 }

@@ -115,7 +115,7 @@ __global__ __launch_bounds__(SAMPLE_NT) void k_sample_geo(
         acc[3] += 2.0 * ww * two_pi * vv * imRV;
         acc[4] += -2.0 * ww * (Rr * Ir2 + Ri * Ii2);
     }
-    if (bad) ctl->flag = 1;
+    if (bad) atomicOr(&ctl->flag, STATUS_UV);
 #pragma unroll
     for (int q = 0; q < GEO_N; ++q) {
         const double bs = block_sum(acc[q], red);

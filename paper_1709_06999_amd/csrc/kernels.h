@@ -131,6 +131,23 @@ __device__ __forceinline__ double sweep_pixel(PI I, int N, int r, int c, const S
     return fma(f, I1 - I0, I0) * m;
 }
 
+// A pixel other than the centre one, from its stretched abscissa xs = x /
+// cos(inc) and the square of its ordinate: rho^2 >= dxy^2 there.  The same
+// value as sweep_pixel with one clamp: tc is t clamped to the profile's
+// range, the pixel is inside exactly when tc == t (NaN included: it is not).
+template <typename PI>
+__device__ __forceinline__ double sweep_px(PI I, double xs, double y2, const SweepArgs &a) {
+    const double rho = sqrt_pos(fma(xs, xs, y2));
+    const double t = sweep_t(rho, a);
+    const double tc = fmin(fmax(t, 0.0), a.tmax);
+    const uint32_t j = min((uint32_t)(int)tc, (uint32_t)(a.Nr - 2));
+    const double f = tc - (double)j;
+    const double m = (tc == t) ? a.pix_area : 0.0;
+    const auto Ij = I + j;  // I[j], I[j + 1]: one 16-byte load
+    const double I0 = (double)Ij[0], I1 = (double)Ij[1];
+    return fma(f, I1 - I0, I0) * m;
+}
+
 // d pixel / d inc of the sweep (not in the paper): on the segment that
 // sweep_pixel interpolates, (I[j+1] - I[j]) / dR times d rho / d inc =
 // (x / cos inc)^2 tan(inc) / rho, times dxy^2; 0 outside the profile and at
@@ -278,17 +295,29 @@ __device__ __forceinline__ void rows_sym_body(PI I, const SweepArgs &sw, const G
     const int tid = threadIdx.x;
     const int m0 = blk * B;
 
-    // columns c and N - c hold the same pixel: sweep c in [0, N/2] into LDS
-    constexpr int NH = N / 2 + 1;
+    // columns c and N - c hold the same pixel: sweep c in [0, N/2) into LDS
+    // (no centre pixel there), then column N/2 with the centre pixel's rule
+    constexpr int NH = N / 2;
     for (int idx = tid; idx < B * NH; idx += NT) {
         const int b = idx / NH, c = idx % NH;
         const int r = 2 * (m0 + b);  // rows r, r + 1 (r + 1 < N)
-        if constexpr (TANGENT)
+        if constexpr (TANGENT) {
             lds[Cfg::at(b, c)] = c2<T>{(T)sweep_pixel_dinc(I, N, r, c, sw),
                                        (T)sweep_pixel_dinc(I, N, r + 1, c, sw)};
+        } else {
+            const double xs = (double)(N / 2 - c) * sw.dxs;
+            const double y0 = (double)(N / 2 - r) * sw.dxy, y1 = (double)(N / 2 - r - 1) * sw.dxy;
+            lds[Cfg::at(b, c)] = c2<T>{(T)sweep_px(I, xs, y0 * y0, sw), (T)sweep_px(I, xs, y1 * y1, sw)};
+        }
+    }
+    if (tid < B) {
+        const int r = 2 * (m0 + tid);
+        if constexpr (TANGENT)
+            lds[Cfg::at(tid, NH)] = c2<T>{(T)sweep_pixel_dinc(I, N, r, NH, sw),
+                                          (T)sweep_pixel_dinc(I, N, r + 1, NH, sw)};
         else
-            lds[Cfg::at(b, c)] = c2<T>{(T)sweep_pixel(I, N, r, c, sw),
-                                       (T)sweep_pixel(I, N, r + 1, c, sw)};
+            lds[Cfg::at(tid, NH)] = c2<T>{(T)sweep_pixel(I, N, r, NH, sw),
+                                          (T)sweep_pixel(I, N, r + 1, NH, sw)};
     }
     __syncthreads();
     c2<T> v[E];
@@ -366,17 +395,29 @@ __device__ __forceinline__ void rows_even_body(PI I, const SweepArgs &sw, const 
     const int tid = threadIdx.x;
     const int m0 = blk * B;
 
-    // sweep: columns c in [0, h] (c and N - c hold the same pixel)
-    for (int idx = tid; idx < B * (H + 1); idx += NT) {
-        const int b = idx / (H + 1), c = idx % (H + 1);
+    // sweep: columns c in [0, h) (c and N - c hold the same pixel; no centre
+    // pixel there), E per thread, then column h with the centre pixel's rule
+    static_assert(B * H == E * NT, "sweep: E pixel pairs per thread");
+#pragma unroll
+    for (int k = 0; k < E; ++k) {
+        const int idx = tid + k * NT;
+        const int b = idx / H, c = idx % H;
         const int r = 2 * (m0 + b);  // rows r, r + 1
-        c2<T> px;
+        if constexpr (TANGENT) {
+            lds[Cfg::at(b, c)] = c2<T>{(T)sweep_pixel_dinc(I, N, r, c, sw),
+                                       (T)sweep_pixel_dinc(I, N, r + 1, c, sw)};
+        } else {
+            const double xs = (double)(N / 2 - c) * sw.dxs;
+            const double y0 = (double)(N / 2 - r) * sw.dxy, y1 = (double)(N / 2 - r - 1) * sw.dxy;
+            lds[Cfg::at(b, c)] = c2<T>{(T)sweep_px(I, xs, y0 * y0, sw), (T)sweep_px(I, xs, y1 * y1, sw)};
+        }
+    }
+    if (tid < B) {
+        const int r = 2 * (m0 + tid);
         if constexpr (TANGENT)
-            px = c2<T>{(T)sweep_pixel_dinc(I, N, r, c, sw), (T)sweep_pixel_dinc(I, N, r + 1, c, sw)};
+            xh[tid] = c2<T>{(T)sweep_pixel_dinc(I, N, r, H, sw), (T)sweep_pixel_dinc(I, N, r + 1, H, sw)};
         else
-            px = c2<T>{(T)sweep_pixel(I, N, r, c, sw), (T)sweep_pixel(I, N, r + 1, c, sw)};
-        if (c < H) lds[Cfg::at(b, c)] = px;
-        else xh[b] = px;
+            xh[tid] = c2<T>{(T)sweep_pixel(I, N, r, H, sw), (T)sweep_pixel(I, N, r + 1, H, sw)};
     }
     __syncthreads();
     const c2<T> *tw = twiddles<T>();
@@ -534,8 +575,11 @@ constexpr int SAMPLE_PPT = 4;
 
 struct Control {
     unsigned int reserved;
-    int flag;              // 1 once a uv point fell outside the spectrum
+    int flag;              // status bits, set with atomicOr (see below)
 };
+// status bits of Control::flag
+constexpr int STATUS_UV = 1;   // a uv point fell outside the spectrum (its V is NaN)
+constexpr int STATUS_GEO = 2;  // a batch job's geometry row failed its checks (chi^2 NaN)
 
 // Bilinear sample of the stored spectrum at one uv point: rotation by PA,
 // deprojection, mirror of u' < 0 (conjugate), 4-node interpolation, flux
@@ -809,7 +853,7 @@ __global__ __launch_bounds__(SAMPLE_NT) void k_sample_sym(
             if (in) vis[perm ? (int64_t)perm[k] : k] = c2<T>{(T)Vre, (T)Vim};
         }
     }
-    if (bad) ctl->flag = 1;
+    if (bad) atomicOr(&ctl->flag, STATUS_UV);
     if constexpr (CHI2) chi2_block_end(acc, red, blk, partials);
 }
 
@@ -868,7 +912,7 @@ __global__ __launch_bounds__(SAMPLE_NT) void k_sample(
             }
         }
     }
-    if (bad) ctl->flag = 1;
+    if (bad) atomicOr(&ctl->flag, STATUS_UV);
     if constexpr (CHI2) chi2_block_end(acc, red, blk, partials);
 }
 

@@ -201,18 +201,30 @@ class Server:
                 else:
                     key = head.key()
                     group = [r for r in self._pending if r.key() == key][: self.max_batch]
-                fp_one = self.ex.footprint([head])
+                try:
+                    fp_one = self.ex.footprint([head])
+                except Exception as e:  # a request the executor cannot plan
+                    self._pending.popleft()
+                    _settle(head.future, exc=e)
+                    self.rejected += 1
+                    continue
                 if fp_one > self.budget:
                     self._pending.popleft()
                     _settle(head.future, exc=MemoryError(
                         f"request needs {fp_one} bytes of device memory, budget {self.budget}"))
                     self.rejected += 1
                     continue
-                while group and self.ex.footprint(group) > self.budget - self._used:
+                fp = None
+                while group:
+                    try:
+                        fp = self.ex.footprint(group)
+                    except Exception:  # a later member fails alone when it is the head
+                        fp = None
+                    if fp is not None and fp <= self.budget - self._used:
+                        break
                     group.pop()
                 if not group:
                     break              # wait for memory to free up
-                fp = self.ex.footprint(group)
                 ids = set(id(r) for r in group)
                 self._pending = collections.deque(r for r in self._pending if id(r) not in ids)
                 slot = self._free_slots.pop()
@@ -237,15 +249,17 @@ class Server:
                 self._wake.clear()
 
 
-class _Slot:
-    """Staging buffers of one in-flight slot: pinned host and device copies of
-    the packed models, geometry rows, chi^2 and gradient outputs, and the
-    slot's workspace.  A slot is reused only after its previous micro-batch
-    was collected, so the buffers are free whenever a launch fills them."""
+def _al(n: int) -> int:
+    return (int(n) + 255) & ~255
 
-    def __init__(self, torch, device, dtype, Workspace):
-        self.torch, self.device, self.dtype = torch, device, dtype
-        self.ws = Workspace(device, torch.float64)
+
+class _Slot:
+    """Pinned host staging of one in-flight slot (models, geometry rows, chi^2
+    and gradient outputs), grown on demand.  Host memory only: the device
+    buffers of a micro-batch are allocated per launch (see GpuExecutor)."""
+
+    def __init__(self, torch, dtype):
+        self.torch, self.dtype = torch, dtype
         self.cap = (0, 0, 0)
 
     def grow(self, K, n_model, n_grad):
@@ -257,36 +271,41 @@ class _Slot:
         n_grad = max(n_grad, self.cap[2], 1)
         pin = dict(pin_memory=True)
         self.h_model = torch.empty(n_model, dtype=self.dtype, **pin)
-        self.d_model = torch.empty(n_model, dtype=self.dtype, device=self.device)
         self.h_geo = torch.empty((K, 6), dtype=torch.float64, **pin)
-        self.d_geo = torch.empty((K, 6), dtype=torch.float64, device=self.device)
         self.h_chi2 = torch.empty(K, dtype=torch.float64, **pin)
-        self.d_chi2 = torch.empty(K, dtype=torch.float64, device=self.device)
         self.h_grad = torch.empty(n_grad, dtype=self.dtype, **pin)
-        self.d_grad = torch.empty(n_grad, dtype=self.dtype, device=self.device)
         self.cap = (K, n_model, n_grad)
 
 
 class GpuExecutor:
-    """HIP executor: datasets resident in HBM, one stream and one set of
-    staging buffers per in-flight slot, one batch_exec call per micro-batch
-    (any mix of requests, gradients included)."""
+    """HIP executor: datasets resident in HBM, one stream and pinned staging
+    per in-flight slot, one batch_exec call per micro-batch (any mix of
+    requests, gradients included).
+
+    Device memory: each micro-batch gets one buffer of exactly
+    ``footprint(reqs)`` bytes -- the batch_exec workspace that the library's
+    planner computes for its job list, then the models, geometry rows, chi^2
+    and gradient outputs -- taken on the slot's stream when it is launched and
+    released when its results are collected.  The scheduler's count of bytes
+    in flight is therefore the device memory the micro-batches hold."""
 
     mixed_batches = True
 
     def __init__(self, device=None, dtype=None, max_batch: int = 16, max_inflight: int = 4):
         import torch
 
-        from . import JOB_PROFILE, Dataset, Workspace, batch_exec
+        from . import JOB_PROFILE, Dataset, Workspace, batch_exec, exec_workspace_bytes
 
         self.torch = torch
         self._Dataset, self._batch_exec, self._JOB_PROFILE = Dataset, batch_exec, JOB_PROFILE
+        self._Workspace, self._ws_bytes = Workspace, exec_workspace_bytes
         self.device = torch.device("cuda", torch.cuda.current_device()) if device is None \
             else torch.device(device)
         self.dtype = torch.float64 if dtype is None else dtype
+        self.el = 8 if self.dtype == torch.float64 else 4
         self.max_batch = max_batch
         self.streams = [torch.cuda.Stream(device=self.device) for _ in range(max_inflight)]
-        self.slots = [_Slot(torch, self.device, self.dtype, Workspace) for _ in range(max_inflight)]
+        self.slots = [_Slot(torch, self.dtype) for _ in range(max_inflight)]
         self.datasets = {}
 
     def default_budget(self) -> int:
@@ -302,22 +321,27 @@ class GpuExecutor:
         self.datasets[name] = self._Dataset(t(u), t(v), t(re), t(im), t(w))
         return self.datasets[name]
 
+    def layout(self, reqs):
+        """Byte offsets of the parts of a micro-batch's device buffer:
+        (workspace bytes, model offset, geo offset, chi2 offset, grad offset,
+        total).  The workspace size is the planner's own figure for the
+        batch_exec call the launch makes."""
+        nr = [int(np.size(r.I)) for r in reqs]
+        specs = [(self.datasets[r.dataset], self._JOB_PROFILE, int(r.Nxy), float(r.dxy), n,
+                  bool(r.grad)) for r, n in zip(reqs, nr)]
+        ws = _al(self._ws_bytes(specs))
+        K, n_model = len(reqs), sum(nr)
+        n_grad = sum(n for n, r in zip(nr, reqs) if r.grad)
+        o_model = ws
+        o_geo = o_model + _al(self.el * n_model)
+        o_chi2 = o_geo + _al(48 * K)
+        o_grad = o_chi2 + _al(8 * K)
+        total = o_grad + _al(self.el * max(n_grad, 1))
+        return ws, o_model, o_geo, o_chi2, o_grad, total
+
     def footprint(self, reqs) -> int:
-        """Upper bound of the device bytes a micro-batch uses: per request its
-        pruned spectrum (at most (Nxy/2 + 2)^2 reals), chi^2 partials, model,
-        geometry and table entry; a gradient request adds its adjoint grid,
-        bin accumulator and gradient output."""
-        el = 8 if self.dtype == self.torch.float64 else 4
-        tot = 4096
-        for r in reqs:
-            N, Nr = int(r.Nxy), int(np.size(r.I))
-            M = int(self.datasets[r.dataset].M)
-            spec = (N // 2 + 2) ** 2 * el + 256
-            b = spec + 8 * ((M + 1023) // 1024) + 256 + el * Nr + 48 + 8 + 512
-            if r.grad:
-                b += spec + 8 * Nr + 256 + el * Nr
-            tot += b
-        return tot
+        """Device bytes a micro-batch holds while in flight (exact)."""
+        return self.layout(reqs)[-1]
 
     def launch(self, reqs, slot):
         torch = self.torch
@@ -332,36 +356,47 @@ class GpuExecutor:
             I = r.I.detach().cpu().numpy() if torch.is_tensor(r.I) else np.asarray(r.I)
             hm[mo[k]:mo[k + 1]] = I
             hg[k] = (r.Rmin, r.dR, r.inc, r.PA, r.dRA, r.dDec)
-        jobs, grads, goff = [], [], []
-        g0 = 0
-        for k, r in enumerate(reqs):
-            jobs.append({"ds": self.datasets[r.dataset], "kind": self._JOB_PROFILE,
-                         "Nxy": int(r.Nxy), "dxy": float(r.dxy),
-                         "model": S.d_model[mo[k]:mo[k + 1]], "geo": S.d_geo[k]})
-            if r.grad:
-                grads.append(S.d_grad[g0:g0 + nr[k]])
-                goff.append(g0)
-                g0 += nr[k]
-            else:
-                grads.append(None)
-                goff.append(-1)
+        ws_b, o_model, o_geo, o_chi2, o_grad, total = self.layout(reqs)
         with torch.cuda.stream(st):
-            S.d_model[:mo[-1]].copy_(S.h_model[:mo[-1]], non_blocking=True)
-            S.d_geo[:K].copy_(S.h_geo[:K], non_blocking=True)
-            self._batch_exec(jobs, grads if n_grad else None, out=S.d_chi2[:K], ws=S.ws)
-            S.h_chi2[:K].copy_(S.d_chi2[:K], non_blocking=True)
+            buf = torch.empty(total, dtype=torch.uint8, device=self.device)
+            view = lambda o, n, dt: buf[o:o + n * (8 if dt == torch.float64 else 4)].view(dt)
+            d_model = view(o_model, int(mo[-1]), self.dtype)
+            d_geo = view(o_geo, 6 * K, torch.float64).view(K, 6)
+            d_chi2 = view(o_chi2, K, torch.float64)
+            d_grad = view(o_grad, max(n_grad, 1), self.dtype)
+            ws = self._Workspace(self.device, torch.float64)
+            ws.buf = buf[:ws_b]
+            ws.buf[:256].zero_()   # the control block (status flag)
+            jobs, grads, goff = [], [], []
+            g0 = 0
+            for k, r in enumerate(reqs):
+                jobs.append({"ds": self.datasets[r.dataset], "kind": self._JOB_PROFILE,
+                             "Nxy": int(r.Nxy), "dxy": float(r.dxy),
+                             "model": d_model[mo[k]:mo[k + 1]], "geo": d_geo[k]})
+                if r.grad:
+                    grads.append(d_grad[g0:g0 + nr[k]])
+                    goff.append(g0)
+                    g0 += nr[k]
+                else:
+                    grads.append(None)
+                    goff.append(-1)
+            d_model.copy_(S.h_model[:mo[-1]], non_blocking=True)
+            d_geo.copy_(S.h_geo[:K], non_blocking=True)
+            self._batch_exec(jobs, grads if n_grad else None, out=d_chi2, ws=ws)
+            S.h_chi2[:K].copy_(d_chi2, non_blocking=True)
             if n_grad:
-                S.h_grad[:n_grad].copy_(S.d_grad[:n_grad], non_blocking=True)
+                S.h_grad[:n_grad].copy_(d_grad[:n_grad], non_blocking=True)
             ev = torch.cuda.Event()
             ev.record(st)
-        return (ev, S, nr, goff)
+        return [ev, S, nr, goff, buf]
 
     def done(self, handle) -> bool:
         return handle[0].query()
 
     def collect(self, handle):
-        ev, S, nr, goff = handle
+        ev, S, nr, goff = handle[:4]
         ev.synchronize()
+        handle[4] = None   # the micro-batch's device buffer goes back to the allocator
         c, g = S.h_chi2.numpy(), S.h_grad.numpy()
         return [(float(c[k]), None if goff[k] < 0 else g[goff[k]:goff[k] + nr[k]].copy())
                 for k in range(len(nr))]

@@ -211,3 +211,77 @@ def test_batch_exec_edge_cases():
             continue
         assert abs(c2[k] - c2s) <= (1e-6 if fp32 else 1e-12) * c2s, (k, c2[k], c2s)
         assert _rel(g.cpu().numpy().astype(np.float64), gs) <= (1e-4 if fp32 else 1e-10), k
+
+
+def test_bad_geometry_row_gives_nan_and_status_flag():
+    # the device checks of kb_prepare (as the host checks of the single calls):
+    # cos(inc) <= 0, dR <= 0, Rmin < 0, non-finite values mark the job, whose
+    # chi^2 (and gradient) come out NaN, and raise STATUS_GEO; the others are
+    # unaffected, and a corrected row is evaluated normally
+    dev = device()
+    gal = _gal()
+    import torch
+
+    d = np.float64
+    base = wl.random_case(128, 20000, seed=950, kind="profile", fill=0.7)
+    Vo = _obs(base, d)
+    re, im = Vo.real + base.noise_re, Vo.imag + base.noise_im
+    ds = gal.Dataset(*(t(a, d, dev) for a in (base.u, base.v, re, im, base.w)))
+    K = 4
+    It = t(np.stack([base.I] * K), d, dev)
+    good = _geo(base)
+    gt = torch.as_tensor(np.array([good] * K), device=dev)
+    b = gal.profile_batch(ds, It, gt, base.N, base.dxy)
+    ref = b.chi2().cpu().numpy()
+    assert np.all(np.isfinite(ref)) and b.status() == 0
+    bad_rows = {"cos(inc) <= 0": (2, 2.0), "dR <= 0": (1, -base.dR), "Rmin < 0": (0, -1e-9),
+                "NaN PA": (3, float("nan"))}
+    for what, (col, val) in bad_rows.items():
+        gt[2, col] = val
+        c2 = b.chi2().cpu().numpy()
+        st = b.status()
+        assert np.isnan(c2[2]), what
+        assert np.array_equal(c2[[0, 1, 3]], ref[[0, 1, 3]]), what
+        assert st & gal.STATUS_GEO, (what, st)
+        gt[2, col] = good[col]
+        c2 = b.chi2().cpu().numpy()
+        assert np.array_equal(c2, ref) and b.status() == 0, what
+    # the one-shot form with gradients: NaN gradient for the marked job only
+    gt[1, 2] = 1.7
+    jobs = [{"ds": ds, "kind": gal.JOB_PROFILE, "Nxy": base.N, "dxy": base.dxy, "model": It[k],
+             "geo": gt[k]} for k in range(K)]
+    grads = [torch.empty_like(It[k]) for k in range(K)]
+    c2 = gal.batch_exec(jobs, grads).cpu().numpy()
+    assert np.isnan(c2[1]) and np.all(np.isfinite(c2[[0, 2, 3]]))
+    assert torch.isnan(grads[1]).all() and all(torch.isfinite(grads[k]).all() for k in (0, 2, 3))
+    assert gal.batch_exec_status(dev) & gal.STATUS_GEO
+    assert gal.batch_exec_status(dev) == 0  # read clears
+    ds.close()
+
+
+def test_batch_exec_refuses_graph_capture():
+    # the one-shot call plans on the host at every call: a captured copy of
+    # its table would replay stale host memory, so capture is refused
+    dev = device()
+    gal = _gal()
+    import torch
+
+    d = np.float64
+    base = wl.random_case(64, 3000, seed=960, kind="profile", fill=0.7)
+    ds = gal.Dataset(*(t(a, d, dev) for a in (base.u, base.v, base.noise_re, base.noise_im,
+                                                base.w)))
+    I = t(base.I, d, dev)
+    geo = torch.as_tensor(_geo(base), device=dev)
+    jobs = [{"ds": ds, "kind": gal.JOB_PROFILE, "Nxy": base.N, "dxy": base.dxy, "model": I,
+             "geo": geo}]
+    out = torch.empty(1, dtype=torch.float64, device=dev)
+    gal.batch_exec(jobs, out=out)  # sizes the workspace outside the capture
+    torch.cuda.synchronize()
+    g = torch.cuda.CUDAGraph()
+    s = torch.cuda.Stream()
+    with torch.cuda.stream(s):
+        with pytest.raises(gal.GalarioError, match="captured"):
+            with torch.cuda.graph(g, stream=s):
+                gal.batch_exec(jobs, out=out)
+    torch.cuda.synchronize()
+    ds.close()

@@ -22,6 +22,18 @@ def _rel(a, b):
     return float(np.linalg.norm(a - b) / max(np.linalg.norm(b), 1e-300))
 
 
+def _assert_grad(g, go, tol=1e-8, what=""):
+    """Relative l2 error and the largest element error, both against the
+    oracle gradient's scale: a wrong small component (an outer profile bin,
+    the centre-pixel bins) cannot hide under the norm."""
+    g = np.asarray(g, dtype=np.float64)
+    rel = _rel(g, go)
+    el = float(np.max(np.abs(g - go)) / max(np.max(np.abs(go)), 1e-300))
+    assert rel <= tol, f"{what}: rel l2 {rel:.3e} > {tol:.1e}"
+    assert el <= tol, f"{what}: max|dg|/max|g| {el:.3e} > {tol:.1e}"
+    return rel, el
+
+
 def _obs(case, offset=0.05):
     # observations away from the model so that the residuals are not noise only
     if case.kind == "image":
@@ -52,7 +64,7 @@ def test_image_gradient_matches_oracle(N, M, path):
         ds = gal.Dataset(*args)
         c2g, gg = ds.chi2Image_grad(img, case.dxy, **kw)
     assert abs(float(c2g) - c2o) <= 1e-10 * c2o
-    assert _rel(gg.cpu().numpy(), go) <= 1e-8
+    _assert_grad(gg.cpu().numpy(), go, what=f"image N={N} {path}")
 
 
 @pytest.mark.parametrize("N,M,Nr", [(16, 400, 12), (64, 5001, 70), (256, 20003, 301)])
@@ -74,7 +86,7 @@ def test_profile_gradient_matches_oracle(N, M, Nr, path):
         ds = gal.Dataset(*args)
         c2g, gg = ds.chi2Profile_grad(I, case.Rmin, case.dR, N, case.dxy, **kw)
     assert abs(float(c2g) - c2o) <= 1e-10 * c2o
-    assert _rel(gg.cpu().numpy(), go) <= 1e-8, _rel(gg.cpu().numpy(), go)
+    _assert_grad(gg.cpu().numpy(), go, what=f"profile N={N} {path}")
 
 
 def test_profile_gradient_central_differences_on_gpu():
@@ -119,13 +131,13 @@ def test_autograd_through_profile_and_image():
     (gI,) = torch.autograd.grad(loss, I)
     _, go = oracle.grad_profile(case.I, case.Rmin, case.dR, 128, case.dxy, case.u, case.v, re, im,
                                 case.w, case.inc, case.PA, case.dRA, case.dDec)
-    assert _rel(gI.cpu().numpy(), 0.5 * go) <= 1e-8
+    _assert_grad(gI.cpu().numpy(), 0.5 * go, what="autograd profile")
     img = gal.sweep(I.detach(), case.Rmin, case.dR, 128, case.dxy, case.inc).requires_grad_(True)
     loss2 = gal.chi2_image(ds, img, case.dxy, case.PA, case.dRA, case.dDec)
     (gimg,) = torch.autograd.grad(loss2, img)
     _, gio = oracle.grad_image(img.detach().cpu().numpy(), case.dxy, case.u, case.v, re, im,
                                case.w, case.PA, case.dRA, case.dDec)
-    assert _rel(gimg.cpu().numpy(), gio) <= 1e-8
+    _assert_grad(gimg.cpu().numpy(), gio, what="autograd image")
 
 
 def test_fp32_gradients_close_to_fp64_oracle():
@@ -141,7 +153,7 @@ def test_fp32_gradients_close_to_fp64_oracle():
                                 rounded(case.u, f), rounded(case.v, f), rounded(re, f),
                                 rounded(im, f), rounded(case.w, f), case.inc, case.PA, case.dRA,
                                 case.dDec)
-    assert _rel(g.cpu().numpy().astype(np.float64), go) <= 1e-3
+    _assert_grad(g.cpu().numpy().astype(np.float64), go, tol=1e-3, what="FP32 profile")
 
 
 def test_profile_2048_gradient_full_size():
@@ -157,7 +169,28 @@ def test_profile_2048_gradient_full_size():
     ds = gal.Dataset(*(t(a, d, dev) for a in (c.u, c.v, re, im, c.w)))
     c2g, g = ds.chi2Profile_grad(t(c.I, d, dev), c.Rmin, c.dR, c.N, c.dxy, c.inc, c.PA, c.dRA,
                                  c.dDec)
-    err = _rel(g.cpu().numpy(), go)
-    print(f"profile 2048 gradient: rel l2 {err:.3e}, chi2 {float(c2g):.15g} vs {c2o:.15g}", flush=True)
+    rel, el = _assert_grad(g.cpu().numpy(), go, what="profile 2048")
+    print(f"profile 2048 gradient: rel l2 {rel:.3e}, max element {el:.3e}, chi2 {float(c2g):.15g} "
+          f"vs {c2o:.15g}", flush=True)
     assert abs(float(c2g) - c2o) <= 1e-10 * c2o
-    assert err <= 1e-8
+
+
+def test_image_2048_gradient_full_size():
+    # chi2Image + gradient at the headline size (2048^2, M = 1e6, FP64): every
+    # pixel of the gradient against the oracle's transposed map
+    dev = device()
+    gal = _gal()
+    d = np.float64
+    c = wl.image_2048()
+    kw = dict(PA=c.PA, dRA=c.dRA, dDec=c.dDec, inc=c.inc)
+    print("image 2048 gradient: oracle", flush=True)
+    Vo = oracle.sampleImage(c.image, c.dxy, c.u, c.v, **kw)
+    re, im = 1.02 * Vo.real + c.noise_re, 0.98 * Vo.imag + c.noise_im
+    c2o, go = oracle.grad_image(c.image, c.dxy, c.u, c.v, re, im, c.w, **kw)
+    ds = gal.Dataset(*(t(a, d, dev) for a in (c.u, c.v, re, im, c.w)))
+    c2g, g = ds.chi2Image_grad(t(c.image, d, dev), c.dxy, **kw)
+    rel, el = _assert_grad(g.cpu().numpy(), go, what="image 2048")
+    print(f"image 2048 gradient: rel l2 {rel:.3e}, max element {el:.3e}, chi2 {float(c2g):.15g} "
+          f"vs {c2o:.15g}", flush=True)
+    assert abs(float(c2g) - c2o) <= 1e-10 * c2o
+    ds.close()

@@ -121,3 +121,28 @@ def test_mixed_executor_takes_requests_in_arrival_order():
     assert order == [id(r) for r in reqs]                      # FIFO across keys
     assert any(len({reqs[[id(r) for r in reqs].index(i)].key() for i in b}) > 1
                for b in ex.launched)
+
+
+class PlanningStub(StubExecutor):
+    """footprint() raises for requests on dataset 'bad' (as the GPU executor
+    does for a request its planner refuses)."""
+
+    def footprint(self, reqs):
+        if any(r.dataset == "bad" for r in reqs):
+            raise ValueError("planner refused the request")
+        return super().footprint(reqs)
+
+
+def test_request_the_executor_cannot_plan_is_rejected_alone():
+    ex = PlanningStub(delay=0.01)
+    srv = Server(ex, max_batch=8, max_inflight=2).start()
+    futs = [srv.submit(_req(ds="bad" if i == 3 else "a", val=float(i))) for i in range(8)]
+    for i, f in enumerate(futs):
+        if i == 3:
+            with pytest.raises(ValueError, match="planner refused"):
+                f.result(timeout=5)
+        else:
+            assert f.result(timeout=5)[0] == 8.0 * i
+    srv.stop()
+    st = srv.stats()
+    assert st["rejected"] == 1 and st["completed"] == 7

@@ -199,61 +199,74 @@ def profile_2048(M: int = 1_000_000) -> Workload:
                     PA=120 * DEG, inc=45 * DEG, I=I, Rmin=Rmin, dR=dR)
 
 
+def ring_image(N: int, dxy: float, flux: float, r0: float, width: float, inc: float,
+               phi0: float, phi_sigma: float):
+    """Gaussian ring of radius r0 and Gaussian width ``width`` (rad), inclined
+    by ``inc`` (x stretched by 1 / cos inc before the radius is taken),
+    modulated in azimuth by exp(-(phi - phi0)^2 / (2 phi_sigma^2)) (phi the
+    position angle East of North of the deprojected point, the difference
+    wrapped into [-pi, pi)), pixel values summing to ``flux``."""
+    x, y = pixel_axes(N, dxy)
+    X = x[None, :] / math.cos(inc)
+    Y = y[:, None]
+    rho = np.hypot(X, Y)
+    phi = np.arctan2(X, Y)
+    dphi = (phi - phi0 + math.pi) % (2.0 * math.pi) - math.pi
+    img = np.exp(-0.5 * ((rho - r0) / width) ** 2 - 0.5 * (dphi / phi_sigma) ** 2)
+    return img * (flux / img.sum())
+
+
 def spectral_cube(n_chan: int = 64, N: int = 1024, M_range=(200_000, 1_000_000),
-                  seed: int = 1600):
-    """Channels of a spectral cube at N^2 (64 channels at 1024^2 by default).
-    One base uv set (log-uniform radius over the C43-5 baselines at 1.3 mm)
-    is scaled by each channel's frequency ratio, 1 to 1.05 across the band;
-    channel k keeps the first M_k points, M_k log-uniform in M_range (ragged).
-    The pixel keeps the widest channel inside 0.9 of the valid radius.  Each
-    channel's model is an elliptical Gaussian whose flux and position drift
-    across the band; noise sigma 1e-3 Jy.  Yields one Workload per channel."""
-    rng = np.random.default_rng(seed)
-    rho_lo, rho_hi = 14.6 / 1.3e-3, 1397.9 / 1.3e-3
-    u0, v0 = uv_log_uniform(M_range[1], rho_lo, rho_hi, seed=seed + 1)
-    dxy = 0.9 * (N / 2 - 1) / (N * 1.05 * rho_hi)
-    Ms = np.exp(rng.uniform(math.log(M_range[0]), math.log(M_range[1]), n_chan)).astype(int)
+                  seed: int = 1300):
+    """Channels of a spectral cube at N^2 FP32 (64 at 1024^2), dxy = 0.054''
+    (ALMA C43-4 row of the paper's table).  One base uv set of 10^6 points,
+    log-uniform radius over the C43-4 baselines at 1.3 mm; channel c scales it
+    by its frequency ratio s_c = 1 + 0.05 c / (n - 1) and keeps the first
+    M_c = round(M_lo + (M_hi - M_lo) U_c) points of its own permutation
+    (ragged).  Its image is a Gaussian ring (r0 = 2'', width 0.5'', inclined
+    40 deg) modulated in azimuth around 2 pi c / 64 (sigma 0.4 rad), 0.1 Jy;
+    noise sigma 1e-3 Jy.  Yields one Workload per channel."""
+    dxy = 0.054 * ARCSEC
+    rho_lo, rho_hi = 14.6 / 1.3e-3, 783.5 / 1.3e-3
+    u0, v0 = uv_log_uniform(M_range[1], rho_lo, rho_hi, seed=seed - 1)
     for k in range(n_chan):
+        rng = np.random.default_rng(seed + k)
         f = 1.0 + 0.05 * k / max(n_chan - 1, 1)
-        M = int(Ms[k])
-        nre, nim, w = noise(M, 1e-3, seed=seed + 10 + k)
-        x0 = (k / n_chan - 0.5) * 8.0 * dxy
-        img = gaussian_image(N, dxy, 1.0 + 0.5 * math.sin(2.0 * math.pi * k / n_chan),
-                             6.0 * dxy, 4.0 * dxy, x0, 0.5 * x0, 0.4)
-        yield Workload(f"cube_chan{k}_N{N}_M{M}", "image", N, dxy, u0[:M] * f, v0[:M] * f, nre,
+        M = int(round(M_range[0] + (M_range[1] - M_range[0]) * rng.random()))
+        sel = rng.permutation(u0.size)[:M]
+        nre, nim, w = noise(M, 1e-3, seed=seed + 100 + k)
+        img = ring_image(N, dxy, 0.1, 2.0 * ARCSEC, 0.5 * ARCSEC, 40 * DEG,
+                         2.0 * math.pi * k / 64.0, 0.4)
+        yield Workload(f"cube_chan{k}_N{N}_M{M}", "image", N, dxy, u0[sel] * f, v0[sel] * f, nre,
                        nim, w, PA=30 * DEG, inc=0.0, dRA=0.0, dDec=0.0, image=img)
 
 
-def mixed_models(n: int = 32, sizes=(512, 1024, 2048, 4096), M: int = 300_000,
-                 seed: int = 1700):
-    """Models of mixed sizes on two shared uv sets (log-uniform radius over
-    the C43-5 baselines): n Gaussian-ring profiles, Nxy drawn from ``sizes``,
-    Nr in [512, 4096], the pixel set per size so that the coverage fills 0.8
-    of the valid radius, random PA, inclination and offsets.  Returns the two
-    uv sets (u, v, noise_re, noise_im, w) and n dicts {set, N, dxy, I, Rmin,
-    dR, inc, PA, dRA, dDec}."""
-    rng = np.random.default_rng(seed)
-    rho_lo, rho_hi = 14.6 / 1.3e-3, 1397.9 / 1.3e-3
-    sets = []
-    for s_ in range(2):
-        u, v = uv_log_uniform(M, rho_lo, rho_hi, seed=seed + 1 + s_)
-        nre, nim, w = noise(M, 1e-3, seed=seed + 3 + s_)
-        sets.append((u, v, nre, nim, w))
-    models = []
+# pixel sizes of the paper's table (ALMA at 1.3 mm) for the image sizes it lists
+TABLE_DXY = {512: 0.108 * ARCSEC, 1024: 0.054 * ARCSEC, 2048: 0.027 * ARCSEC,
+             4096: 0.013 * ARCSEC}
+
+
+def mixed_models(n: int = 32, sizes=(512, 1024, 2048, 4096), M_range=(100_000, 2_000_000),
+                 seed: int = 1400):
+    """Models of mixed sizes, each on its own observation: model i draws Nxy
+    uniformly from ``sizes`` with the table's pixel size, an image of 20
+    Gaussian blobs (as blobs_4096), M_i log-uniform in M_range, uv radius
+    log-uniform in [rho_max / 100, rho_max] with rho_max = 1 / (5 dxy) (the
+    grid reaches f_max = 2.5 times it), uniform angle, noise sigma 1e-3 Jy,
+    random PA and offsets (seeds 1400 + i).  Yields one Workload per model."""
     for i in range(n):
+        rng = np.random.default_rng(seed + i)
         N = int(rng.choice(sizes))
-        dxy = 0.8 * (N / 2 - 1) / (N * rho_hi)
-        Nr = int(rng.integers(512, 4097))
-        Rmax = 0.7 * N * dxy
-        Rmin = 0.0
-        dR = (Rmax - Rmin) / (Nr - 1)
-        r = Rmin + dR * np.arange(Nr)
-        r0, wd = rng.uniform(0.1, 0.3) * N * dxy, rng.uniform(0.02, 0.06) * N * dxy
-        I = (np.exp(-((r - r0) / wd) ** 2) + 0.3 * np.exp(-(r / (0.1 * N * dxy)) ** 2)) / dxy ** 2
-        models.append(dict(set=int(i % 2), N=N, dxy=dxy, I=I, Rmin=Rmin, dR=dR,
-                           inc=rng.uniform(0.0, 60 * DEG), PA=rng.uniform(0.0, math.pi),
-                           dRA=rng.normal(0.0, 2 * dxy), dDec=rng.normal(0.0, 2 * dxy)))
-    return sets, models
+        dxy = TABLE_DXY[N]
+        M = int(round(math.exp(rng.uniform(math.log(M_range[0]), math.log(M_range[1])))))
+        rho_max = 1.0 / (5.0 * dxy)
+        u, v = uv_log_uniform(M, rho_max / 100.0, rho_max, seed=seed + 100 + i)
+        nre, nim, w = noise(M, 1e-3, seed=seed + 200 + i)
+        img = blob_image(N, dxy, 20, seed=seed + 300 + i)
+        yield Workload(f"mixed{i}_N{N}_M{M}", "image", N, dxy, u, v, nre, nim, w,
+                       PA=rng.uniform(0.0, math.pi), inc=0.0,
+                       dRA=float(rng.normal(0.0, 2 * dxy)), dDec=float(rng.normal(0.0, 2 * dxy)),
+                       image=img)
 
 
 def field_of_copies(c: Workload, n: int, seed: int) -> list:
@@ -268,6 +281,19 @@ def field_of_copies(c: Workload, n: int, seed: int) -> list:
                         PA=rng.uniform(0.0, math.pi),
                         dRA=rng.uniform(-1.0, 1.0) * ARCSEC, dDec=rng.uniform(-1.0, 1.0) * ARCSEC))
     return out
+
+
+def image_2048(M: int = 1_000_000) -> Workload:
+    """chi2Image at the headline size, 2048^2 FP64: 200 Gaussian blobs (as
+    blobs_4096) at dxy = 0.003'', on the uv set and noise of profile_2048
+    (M = 1e6, C43-10), PA = 120 deg, inc = 45 deg (deprojection of the uv),
+    offsets 0.01''."""
+    N, dxy = 2048, 0.003 * ARCSEC
+    img = blob_image(N, dxy, 200, seed=1250)
+    u, v = uv_log_uniform(M, 1.877e5, 1.2457e7, seed=1100)
+    nre, nim, w = noise(u.size, 1e-3, seed=1101)
+    return Workload("blobs_chi2Image_2048_M1e6", "image", N, dxy, u, v, nre, nim, w,
+                    PA=120 * DEG, inc=45 * DEG, dRA=0.01 * ARCSEC, dDec=0.01 * ARCSEC, image=img)
 
 
 def blobs_4096(M: int = 5_000_000) -> Workload:
@@ -332,17 +358,18 @@ def serve_datasets(n: int = 8, M_range=(100_000, 2_000_000), seed0: int = 1500):
     return out
 
 
-def serve_requests(n: int, seed: int, n_datasets: int = 8):
-    """Request parameters: dataset uniform, Nxy in {512, 1024, 2048}, Nr in
-    U{512..4096}, a gapped power-law profile with random gap positions and
-    depths, Rmin = 1e-4 N dxy, R_max = 1.05 (N/2) dxy sqrt(1/cos^2 i + 1),
-    inc ~ U[0, 70 deg], PA ~ U[0, 180 deg), offsets ~ N(0, (5 dxy)^2)."""
+def serve_requests(n: int, seed: int, n_datasets: int = 8, sizes=(512, 1024, 2048)):
+    """Request parameters: dataset uniform, Nxy uniform in ``sizes`` ({512,
+    1024, 2048}), Nr in U{512..4096}, a gapped power-law profile with random
+    gap positions and depths, Rmin = 1e-4 N dxy, R_max = 1.05 (N/2) dxy
+    sqrt(1/cos^2 i + 1), inc ~ U[0, 70 deg], PA ~ U[0, 180 deg), offsets
+    ~ N(0, (5 dxy)^2)."""
     rng = np.random.default_rng(seed)
     dxy = SERVE_DXY
     reqs = []
     for _ in range(n):
         d = int(rng.integers(0, n_datasets))
-        N = int(rng.choice([512, 1024, 2048]))
+        N = int(rng.choice(list(sizes)))
         Nr = int(rng.integers(512, 4097))
         inc = rng.uniform(0.0, 70.0) * DEG
         PA = rng.uniform(0.0, 180.0) * DEG
