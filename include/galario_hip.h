@@ -199,6 +199,24 @@ int gal_chi2Profile_ds_d(const gal_dataset *ds, const double *I, int Nr, double 
 int gal_chi2Profile_ds_f(const gal_dataset *ds, const float *I, int Nr, double Rmin,
                          double dR, int Nxy, double dxy, double inc, double PA, double dRA,
                          double dDec, double *chi2, void *ws, size_t ws_bytes, void *stream);
+
+/* chi2Profile on a dataset with the library's own scratch workspace: for
+ * callers that cannot allocate device memory (code under HIP graph capture,
+ * tight serving loops, harnesses that forbid hipMalloc).  The same result as
+ * gal_chi2Profile_ds_d; the call allocates nothing.  The workspace is a
+ * static device array of GAL_SCRATCH_BYTES on every device the library runs
+ * on, held until the process ends; a call needing more
+ * (gal_workspace_bytes_d(Nxy, M) > GAL_SCRATCH_BYTES: Nxy <= 2048 fits up to
+ * M of about 4e9 points, Nxy >= 4096 never fits) returns GAL_ERR_WORKSPACE
+ * with nothing enqueued.  Its set-up (twiddle tables, the scratch address, its
+ * status word cleared) runs in gal_init(device) or else on the first call on
+ * a device: call gal_init before capturing.  Every call on one device shares
+ * that device's scratch: calls on different streams that overlap race and
+ * must be ordered by the caller. */
+#define GAL_SCRATCH_BYTES (64u << 20)
+int gal_chi2Profile_ds_scratch_d(const gal_dataset *ds, const double *I, int Nr, double Rmin,
+                                 double dR, int Nxy, double dxy, double inc, double PA,
+                                 double dRA, double dDec, double *chi2, void *stream);
 int gal_sampleImage_ds_d(const gal_dataset *ds, const double *image, int Nxy, double dxy,
                          double PA, double dRA, double dDec, double inc, double *vis,
                          void *ws, size_t ws_bytes, void *stream);

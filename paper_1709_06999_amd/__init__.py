@@ -429,6 +429,23 @@ class Dataset:
                 _stream(self.device)), "Dataset.chi2Profile")
         return res
 
+    def chi2Profile_scratch(self, I, Rmin, dR, Nxy, dxy, inc=0.0, PA=0.0, dRA=0.0, dDec=0.0,
+                            out: torch.Tensor | None = None):
+        """chi2Profile with the library's static scratch workspace (FP64 datasets
+        only): the C call allocates nothing, for callers that cannot allocate
+        (pass `out` to allocate nothing here either).  Calls on one device share
+        the scratch, so calls on different streams must not overlap."""
+        if self.dtype != torch.float64:
+            raise TypeError("chi2Profile_scratch needs an FP64 dataset")
+        self._chk(I, "I")
+        res = torch.empty((), dtype=torch.float64, device=self.device) if out is None else out
+        with torch.cuda.device(self.device):
+            check(_lib().gal_chi2Profile_ds_scratch_d(
+                self._h, _ptr(I), I.numel(), float(Rmin), float(dR), int(Nxy), float(dxy),
+                float(inc), float(PA), float(dRA), float(dDec), _ptr(res), _stream(self.device)),
+                "Dataset.chi2Profile_scratch")
+        return res
+
     def chi2Image_grad(self, image, dxy, PA=0.0, dRA=0.0, dDec=0.0, inc=0.0,
                        ws: Workspace | None = None):
         """(chi^2 0-d tensor, d chi^2 / d image)."""

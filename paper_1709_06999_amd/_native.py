@@ -13,6 +13,8 @@ LIB_PATH = os.path.join(HERE, "libgalario_hip.so")
 
 GAL_OK = 0
 GAL_ERR_SIZE = -2
+GAL_ERR_WORKSPACE = -5
+GAL_SCRATCH_BYTES = 64 << 20  # the scratch workspace of gal_chi2Profile_ds_scratch_d
 ERRORS = {
     -1: "GAL_ERR_NULL",
     -2: "GAL_ERR_SIZE",
@@ -51,6 +53,7 @@ _SIG = {
     "gal_dataset_geometry": (I, [P, I, D, ctypes.POINTER(I), ctypes.POINTER(I)]),
     "gal_chi2Image_ds": (I, [P, P, I, D, D, D, D, D, P, P, SZ, P]),
     "gal_chi2Profile_ds": (I, [P, P, I, D, D, I, D, D, D, D, D, P, P, SZ, P]),
+    "gal_chi2Profile_ds_scratch_d": (I, [P, P, I, D, D, I, D, D, D, D, D, P, P]),
     "gal_sampleImage_ds": (I, [P, P, I, D, D, D, D, D, P, P, SZ, P]),
     "gal_sampleProfile_ds": (I, [P, P, I, D, D, I, D, D, D, D, D, P, P, SZ, P]),
     "gal_grad_workspace_bytes_d": (SZ, [I, I64, I]),

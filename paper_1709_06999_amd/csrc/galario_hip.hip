@@ -28,6 +28,11 @@ namespace gal {
 __device__ c2<double> g_tw_d[2 * TW_MAX];
 __device__ c2<float> g_tw_f[2 * TW_MAX];
 
+// Workspace of gal_chi2Profile_ds_scratch_d, for callers that cannot allocate.
+// Each device holds its own copy; host code uses only the per-device address
+// that hipGetSymbolAddress returns (g_scratch_ptr), never the array's name.
+__device__ __align__(256) char scratch[GAL_SCRATCH_BYTES];
+
 // ---------------------------------------------------------------------------
 // errors
 static thread_local std::string t_err;
@@ -53,6 +58,7 @@ static int fail(int code, const char *fmt, ...) {
 // twiddle tables: entries [M, 2M) hold exp(-2 pi i m / M) for every power of two M
 static std::mutex g_init_mu;
 static std::vector<char> g_init_done;
+static std::vector<void *> g_scratch_ptr;  // per device: device address of `scratch`
 
 static int init_device(int dev) {
     std::lock_guard<std::mutex> lk(g_init_mu);
@@ -76,6 +82,15 @@ static int init_device(int dev) {
     if (cur != dev) GAL_HIP(hipSetDevice(dev));
     GAL_HIP(hipMemcpyToSymbol(HIP_SYMBOL(g_tw_d), td.data(), sizeof(c2<double>) * td.size()));
     GAL_HIP(hipMemcpyToSymbol(HIP_SYMBOL(g_tw_f), tf.data(), sizeof(c2<float>) * tf.size()));
+    // the scratch workspace: its address on this device, and its control
+    // block (status flag) cleared once, as gal_workspace_init does for a
+    // caller's workspace
+    void *sp = nullptr;
+    GAL_HIP(hipGetSymbolAddress(&sp, HIP_SYMBOL(scratch)));
+    GAL_HIP(hipMemset(sp, 0, 256));
+    GAL_HIP(hipDeviceSynchronize());
+    if ((int)g_scratch_ptr.size() <= dev) g_scratch_ptr.resize(dev + 1, nullptr);
+    g_scratch_ptr[dev] = sp;
     if (cur != dev) GAL_HIP(hipSetDevice(cur));
     g_init_done[dev] = 1;
     return GAL_OK;
@@ -1397,6 +1412,30 @@ int gal_chi2Profile_ds_d(const gal_dataset *ds, const double *I, int Nr, double 
     if (!chi2) return fail(GAL_ERR_NULL, "NULL chi2");
     return ds_call<double>(ds, I, true, Nr, Rmin, dR, Nxy, dxy, inc, PA, dRA, dDec, nullptr, chi2,
                            ws, ws_bytes_, stream);
+}
+int gal_chi2Profile_ds_scratch_d(const gal_dataset *ds, const double *I, int Nr, double Rmin,
+                                 double dR, int Nxy, double dxy, double inc, double PA,
+                                 double dRA, double dDec, double *chi2, void *stream) {
+    if (!chi2 || !ds) return fail(GAL_ERR_NULL, "NULL argument");
+    if (!pow2_in_range(Nxy)) return fail(GAL_ERR_SIZE, "Nxy=%d: need a power of two in [16, 8192]", Nxy);
+    const size_t need = ws_bytes<double>(Nxy, ds->M);
+    if (need > (size_t)GAL_SCRATCH_BYTES)
+        return fail(GAL_ERR_WORKSPACE,
+                    "Nxy=%d, M=%lld needs %zu bytes of workspace; the scratch holds %zu "
+                    "(use gal_chi2Profile_ds_d with a caller's workspace)",
+                    Nxy, (long long)ds->M, need, (size_t)GAL_SCRATCH_BYTES);
+    int rc = ensure_init();
+    if (rc) return rc;
+    int dev = 0;
+    GAL_HIP(hipGetDevice(&dev));
+    void *sp = nullptr;
+    {
+        std::lock_guard<std::mutex> lk(g_init_mu);
+        if ((int)g_scratch_ptr.size() > dev) sp = g_scratch_ptr[dev];
+    }
+    if (!sp) return fail(GAL_ERR_HIP, "scratch workspace of device %d has no address", dev);
+    return ds_call<double>(ds, I, true, Nr, Rmin, dR, Nxy, dxy, inc, PA, dRA, dDec, nullptr, chi2,
+                           sp, (size_t)GAL_SCRATCH_BYTES, stream);
 }
 int gal_chi2Profile_ds_f(const gal_dataset *ds, const float *I, int Nr, double Rmin, double dR,
                          int Nxy, double dxy, double inc, double PA, double dRA, double dDec,
