@@ -75,17 +75,6 @@ struct PointAdd {
     double a, s;
 };
 
-__device__ __forceinline__ int wave_min(int x) {
-#pragma unroll
-    for (int o = 32; o >= 1; o >>= 1) x = min(x, __shfl_xor(x, o, 64));
-    return x;
-}
-__device__ __forceinline__ int wave_max(int x) {
-#pragma unroll
-    for (int o = 32; o >= 1; o >>= 1) x = max(x, __shfl_xor(x, o, 64));
-    return x;
-}
-
 // Called by every thread of the block (it synchronises); tile: SCAT_TILE
 // doubles of LDS, box: 4 * (blockDim.x / 64) ints of LDS.
 template <typename T, int NV, int NP>

@@ -403,7 +403,7 @@ __global__ __launch_bounds__(SAMPLE_NT) void kb_sample_chi2(const JobDesc *__res
         }
         if (GRAD && J.grad) block_scatter<T, NV, PPT>((T *)(ws + J.a_off), g.CS, pa, tile, box);
         // one partial per wave (no barrier between chi^2-only jobs); kb_reduce adds them
-        const double wsum = wave_sum(acc);
+        const double wsum = wave_sum_permute(acc);
         if ((threadIdx.x & 63) == 0)
             ((double *)(ws + J.part_off))[chunk * WAVES + (threadIdx.x >> 6)] = wsum;
     }
@@ -521,7 +521,7 @@ __global__ __launch_bounds__(SAMPLE_NT) void kb_sample_scene(const JobDesc *__re
         }
         // one partial per wave and scene (no barrier between chi^2-only
         // scenes); kb_reduce adds them
-        const double wsum = wave_sum(acc);
+        const double wsum = wave_sum_permute(acc);
         if ((threadIdx.x & 63) == 0)
             ((double *)(ws + L.part_off))[chunk * WAVES + (threadIdx.x >> 6)] = wsum;
     }

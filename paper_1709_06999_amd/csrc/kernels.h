@@ -15,6 +15,7 @@
 // so no data is moved for it.
 #pragma once
 #include "fft_block.h"
+#include "wave.h"
 
 namespace gal {
 
@@ -344,26 +345,6 @@ __device__ __forceinline__ void rows_sym_body(PI I, const SweepArgs &sw, const G
         else
             XR[(size_t)q * g.CS + r] = z.x;
     });
-}
-
-// sum over the 64 lanes of a wave (every lane gets it)
-__device__ __forceinline__ double wave_sum(double x) {
-#pragma unroll
-    for (int o = 32; o >= 1; o >>= 1) x += __shfl_xor(x, o, 64);
-    return x;
-}
-
-// exclusive prefix sum over the 64 lanes of a wave (lane order)
-__device__ __forceinline__ double wave_excl_scan(double x) {
-    const int lane = threadIdx.x & 63;
-    double incl = x;
-#pragma unroll
-    for (int o = 1; o < 64; o <<= 1) {
-        const double y = __shfl_up(incl, o, 64);
-        if (lane >= o) incl += y;
-    }
-    const double e = __shfl_up(incl, 1, 64);
-    return lane == 0 ? 0.0 : e;
 }
 
 // Row pass of a swept profile by half-length transforms.  A row x of the
