@@ -28,7 +28,14 @@
  *    *Image a non-zero inc deprojects the rotated u' <- u' cos(inc) and
  *    scales V by cos(inc), the transform of the image stretched the same way
  *    (extension; inc = 0 is the paper's *Image).
- *  - Nxy must be a power of two, 16 <= Nxy <= 8192.  A uv point is usable
+ *  - Nxy must be a power of two, 16 <= Nxy <= 16384 for sweep, sample*,
+ *    chi2* and the dataset calls (the sizes of the paper's timing tables,
+ *    Sec. 6.1 and App. B), 16 <= Nxy <= 8192 for gradients, geometry
+ *    gradients, batches, the autotuner and gal_spectrum_* /
+ *    gal_sample_spectrum_*.  At 16384 a full-length FP64 column does not fit
+ *    in one workgroup's LDS: swept profiles then use half-length transforms of
+ *    even sequences in both passes and images a two-launch column pass, whose
+ *    spectrum takes a second region of the workspace.  A uv point is usable
  *    when all four nodes of its bilinear stencil lie on the half spectrum:
  *    0 <= floor(|u'|/du) <= Nxy/2 - 1 and -Nxy/2 <= floor(v'/du) <= Nxy/2 - 2,
  *    du = 1/(Nxy dxy).  Calls on raw uv arrays check this per point on the
@@ -65,7 +72,7 @@ extern "C" {
 
 #define GAL_OK               0
 #define GAL_ERR_NULL        (-1)  /* a required pointer is NULL */
-#define GAL_ERR_SIZE        (-2)  /* Nxy not a power of two in [16, 8192], Nr < 2, M < 0 */
+#define GAL_ERR_SIZE        (-2)  /* Nxy outside the sizes above, Nr < 2, M < 0 */
 #define GAL_ERR_UV_RANGE    (-3)  /* dataset rho_max outside the half spectrum */
 #define GAL_ERR_SCALAR      (-4)  /* dxy < 1e-100, dR <= 0, Rmin < 0, cos(inc) <= 0, non-finite */
 #define GAL_ERR_WORKSPACE   (-5)  /* workspace too small / out of memory */
@@ -317,7 +324,7 @@ int gal_chi2Profile_geograd_ds_f(const gal_dataset *ds, const float *I, int Nr, 
  * the paper's table of ALMA and VLA configurations).  Errors: GAL_ERR_SCALAR
  * for f_max <= 2, f_min <= 1 or Gamma <= 0 with PB = 0, rho_min = 0 with PB = 0,
  * PB < 0, an empty or non-finite uv range; GAL_ERR_SIZE above 2^30.  The
- * result may exceed the largest image the other calls take (8192).
+ * result may exceed the largest image the other calls take (16384).
  * gal_uv_range_*: shortest and longest baseline of HOST arrays u, v [M]
  * (M >= 1).  gal_dataset_image_size: from a dataset's registered range. */
 int gal_image_size(double rho_min, double rho_max, double f_min, double f_max, double PB,

@@ -216,6 +216,7 @@ struct FftJob {
     int Qe;          // even column count (swept-profile passes)
     void *buf;       // intermediate / spectrum
     hipStream_t s;
+    void *buf2 = nullptr;  // spectrum of a column pass that cannot run in place
 };
 template <typename T>
 using FftFn = int (*)(const FftJob<T> &);
@@ -257,6 +258,44 @@ static int run_cols_sym(const FftJob<T> &j) {
     const int pairs = j.Qe / 2;
     return launch("k_cols_sym", k_cols_sym<T, C>, dim3((pairs + B - 1) / B), dim3(C::NT), j.s, j.g,
                   j.Qe, j.buf);
+}
+
+// 16384^2: one schedule per pass.  Rows of images at half length (E = 8);
+// swept profiles by the half-length transform of even sequences in both
+// passes; image columns in LDS in FP32, in two launches (four-step) in FP64,
+// whose column of 256 KB does not fit.
+constexpr int NXY_BIG = 16384;
+template <typename T>
+constexpr bool four_step(int N) { return N == NXY_BIG && sizeof(T) == 8; }
+
+template <typename T>
+static int run_cols_even_big(const FftJob<T> &j) {
+    using C = CfgE<T, NXY_BIG / 2, 1, 8>;
+    return launch("k_cols_even", k_cols_even<T, C>, dim3(j.Qe / 2), dim3(C::NT), j.s, j.g, j.Qe,
+                  j.buf);
+}
+template <typename T>
+static int run_cols4_big(const FftJob<T> &j) {
+    constexpr int N1 = 128, B = 16;
+    static_assert(N1 * N1 == NXY_BIG, "four-step factors");
+    using C = CfgE<T, N1, B, 8>;
+    if (!j.buf2) return fail(GAL_ERR_WORKSPACE, "no spectrum buffer for the 16384 column pass");
+    int rc = launch("k_cols4a", k_cols4a<T, C, NXY_BIG>, dim3(N1 / B, j.g.Q), dim3(C::NT), j.s,
+                    j.g, j.buf);
+    if (rc) return rc;
+    return launch("k_cols4b", k_cols4b<T, C, NXY_BIG>, dim3(N1 / B, j.g.Q), dim3(C::NT), j.s, j.g,
+                  j.buf, j.buf2, 2 * j.g.P + 1);
+}
+template <typename T>
+static FftFn<T> fft_fn_big(int kind) {
+    switch (kind) {
+        case K_ROWS_IMG: return run_rows_img<T, NXY_BIG, 1>;
+        case K_COLS:
+            if constexpr (four_step<T>(NXY_BIG)) return run_cols4_big<T>;
+            else return run_cols<T, NXY_BIG, 0>;
+        case K_ROWS_SYM: return run_rows_sym<T, NXY_BIG, 0>;
+        default: return run_cols_even_big<T>;
+    }
 }
 
 // variant table [log2 N - 4][kind][var]; small images compile one variant
@@ -334,6 +373,7 @@ static int chosen_var(int N, int kind) {
 
 template <typename T>
 static int run_fft(int kind, const FftJob<T> &j) {
+    if (j.g.N == NXY_BIG) return fft_fn_big<T>(kind)(j);
     FftFn<T> f = fft_fn<T>(j.g.N, kind, chosen_var<T>(j.g.N, kind));
     if (!f) return fail(GAL_ERR_SIZE, "Nxy=%d unsupported", j.g.N);
     return f(j);
@@ -432,17 +472,24 @@ static int64_t sample_blocks(int64_t M) {
     return n < 1 ? 1 : n;
 }
 
+// [control 256 B][partials][XT][spectrum of a four-step column pass]
+template <typename T>
+static size_t spec2_bytes(int N) {
+    return four_step<T>(N) ? align256((size_t)(N / 2 + 1) * (size_t)(N + 1) * sizeof(c2<T>)) : 0;
+}
+
 template <typename T>
 static size_t ws_bytes(int N, int64_t M) {
     const size_t partials = align256((size_t)sample_blocks(M) * sizeof(double));
     const size_t xt = align256((size_t)(N / 2 + 1) * (size_t)(N + 2) * sizeof(c2<T>));
-    return 256 + partials + xt;
+    return 256 + partials + xt + spec2_bytes<T>(N);
 }
 
 struct WS {
     Control *ctl;
     double *partials;
     void *xt;
+    void *spec2;  // four-step column pass output (NULL otherwise)
 };
 
 template <typename T>
@@ -455,18 +502,27 @@ static int carve(void *ws, size_t bytes, int N, int64_t M, WS &out) {
     out.ctl = (Control *)p;
     out.partials = (double *)(p + 256);
     out.xt = p + 256 + align256((size_t)sample_blocks(M) * sizeof(double));
+    out.spec2 = four_step<T>(N)
+                    ? (char *)out.xt + align256((size_t)(N / 2 + 1) * (size_t)(N + 2) * sizeof(c2<T>))
+                    : nullptr;
     return GAL_OK;
 }
 
 // ---------------------------------------------------------------------------
 // argument checks
-static bool pow2_in_range(int N) { return N >= 16 && N <= 8192 && (N & (N - 1)) == 0; }
+// image sizes: powers of two from 16 to NXY_BIG for the forward calls (sweep,
+// sample*, chi2*, datasets); up to 8192 for gradients, geometry gradients,
+// batches, the autotuner and the separate spectrum calls
+static bool pow2_upto(int N, int nmax) { return N >= 16 && N <= nmax && (N & (N - 1)) == 0; }
+static bool pow2_in_range(int N) { return pow2_upto(N, 8192); }
 // smallest pixel size: squared pixel radii stay far above the range where the
 // sweep's square root would need scaling
 constexpr double DXY_MIN = 1e-100;
 
-static int check_image_scalars(int N, double dxy, double PA, double dRA, double dDec, double inc) {
-    if (!pow2_in_range(N)) return fail(GAL_ERR_SIZE, "Nxy=%d: need a power of two in [16, 8192]", N);
+static int check_image_scalars(int N, double dxy, double PA, double dRA, double dDec, double inc,
+                               int nmax = 8192) {
+    if (!pow2_upto(N, nmax))
+        return fail(GAL_ERR_SIZE, "Nxy=%d: need a power of two in [16, %d]", N, nmax);
     if (!(dxy >= DXY_MIN) || !std::isfinite(dxy)) return fail(GAL_ERR_SCALAR, "dxy must be >= 1e-100");
     if (!std::isfinite(PA) || !std::isfinite(dRA) || !std::isfinite(dDec) || !std::isfinite(inc))
         return fail(GAL_ERR_SCALAR, "PA, dRA, dDec and inc must be finite");
@@ -541,10 +597,17 @@ struct Obs {
 // Transform: the general image -> complex spectrum in XT (column stride CS);
 // a swept profile -> real spectrum (column stride N/2 + 2).  Returns the
 // geometry the sampler must use.
+// buf2: the spectrum when the image column pass cannot run in place
+// (four_step); *spec receives where the spectrum is.
 template <typename T>
 static int transform(const T *src, bool profile, const SweepArgs &sw, const Geom &g, void *buf,
-                     hipStream_t s, Geom &gs) {
-    FftJob<T> j{src, sw, g, (g.Q + 1) & ~1, buf, s};
+                     hipStream_t s, Geom &gs, void *buf2 = nullptr, void **spec = nullptr) {
+    FftJob<T> j{src, sw, g, (g.Q + 1) & ~1, buf, s, buf2};
+    if (spec) *spec = buf;
+    if (!profile && four_step<T>(g.N)) {
+        if (!buf2 || !spec) return fail(GAL_ERR_SIZE, "Nxy=%d unsupported here", g.N);
+        *spec = buf2;
+    }
     if (profile) {
         j.g.CS = g.N / 2 + 2;
         gs = j.g;
@@ -553,6 +616,7 @@ static int transform(const T *src, bool profile, const SweepArgs &sw, const Geom
         return run_fft<T>(K_COLS_SYM, j);
     }
     gs = g;
+    if (four_step<T>(g.N)) gs.CS = 2 * g.P + 1;
     int rc = run_fft<T>(K_ROWS_IMG, j);
     if (rc) return rc;
     return run_fft<T>(K_COLS, j);
@@ -585,10 +649,11 @@ static int run_carved(const T *src, bool profile, const SweepArgs &sw, const Geo
                       const Obs<T> &o, double PA, double dRA, double dDec, double inc, T *vis,
                       double *chi2, const WS &w, hipStream_t s) {
     Geom gs;
-    int rc = transform<T>(src, profile, sw, g, w.xt, s, gs);
+    void *S = nullptr;
+    int rc = transform<T>(src, profile, sw, g, w.xt, s, gs, w.spec2, &S);
     if (rc) return rc;
     const SampleArgs sa = make_sample(g, o.M, dxy, PA, dRA, dDec, inc);
-    return sample<T>(profile, w.xt, gs, sa, o, vis, chi2, w, s);
+    return sample<T>(profile, S, gs, sa, o, vis, chi2, w, s);
 }
 
 template <typename T>
@@ -936,11 +1001,11 @@ int gal_init(int device) {
 }
 
 size_t gal_workspace_bytes_d(int Nxy, int64_t M) {
-    if (!pow2_in_range(Nxy) || M < 0) return 0;
+    if (!pow2_upto(Nxy, NXY_BIG) || M < 0) return 0;
     return ws_bytes<double>(Nxy, M);
 }
 size_t gal_workspace_bytes_f(int Nxy, int64_t M) {
-    if (!pow2_in_range(Nxy) || M < 0) return 0;
+    if (!pow2_upto(Nxy, NXY_BIG) || M < 0) return 0;
     return ws_bytes<float>(Nxy, M);
 }
 
@@ -973,7 +1038,7 @@ template <typename T>
 static int sweep_impl(const T *I, int Nr, double Rmin, double dR, int Nxy, double dxy, double inc,
                       T *image, void *stream) {
     if (!I || !image) return fail(GAL_ERR_NULL, "NULL array");
-    int rc = check_image_scalars(Nxy, dxy, 0.0, 0.0, 0.0, inc);
+    int rc = check_image_scalars(Nxy, dxy, 0.0, 0.0, 0.0, inc, NXY_BIG);
     if (rc) return rc;
     rc = check_profile(Nr, Rmin, dR);
     if (rc) return rc;
@@ -1001,7 +1066,7 @@ static int image_call(const T *image, int Nxy, double dxy, const T *u, const T *
     if (chi2 && M > 0 && (!re || !im || !w)) return fail(GAL_ERR_NULL, "NULL observation array");
     if (!chi2 && M > 0 && !vis) return fail(GAL_ERR_NULL, "NULL output");
     if (M < 0) return fail(GAL_ERR_SIZE, "M < 0");
-    int rc = check_image_scalars(Nxy, dxy, PA, dRA, dDec, inc);
+    int rc = check_image_scalars(Nxy, dxy, PA, dRA, dDec, inc, NXY_BIG);
     if (rc) return rc;
     const Geom g = geom_full(Nxy);
     return run_path<T>(image, false, SweepArgs{}, g, dxy, Obs<T>{u, v, re, im, w, M, nullptr}, PA, dRA, dDec,
@@ -1017,7 +1082,7 @@ static int profile_call(const T *I, int Nr, double Rmin, double dR, int Nxy, dou
     if (chi2 && M > 0 && (!re || !im || !w)) return fail(GAL_ERR_NULL, "NULL observation array");
     if (!chi2 && M > 0 && !vis) return fail(GAL_ERR_NULL, "NULL output");
     if (M < 0) return fail(GAL_ERR_SIZE, "M < 0");
-    int rc = check_image_scalars(Nxy, dxy, PA, dRA, dDec, inc);
+    int rc = check_image_scalars(Nxy, dxy, PA, dRA, dDec, inc, NXY_BIG);
     if (rc) return rc;
     rc = check_profile(Nr, Rmin, dR);
     if (rc) return rc;
@@ -1355,7 +1420,7 @@ int gal_dataset_image_size(const gal_dataset *ds, double f_min, double f_max, do
 
 int gal_dataset_geometry(const gal_dataset *ds, int Nxy, double dxy, int *Q, int *P) {
     if (!ds || !Q || !P) return fail(GAL_ERR_NULL, "NULL argument");
-    int rc = check_image_scalars(Nxy, dxy, 0.0, 0.0, 0.0, 0.0);
+    int rc = check_image_scalars(Nxy, dxy, 0.0, 0.0, 0.0, 0.0, NXY_BIG);
     if (rc) return rc;
     const Geom g = geom_pruned(Nxy, dxy, ds->rho_max);
     *Q = g.Q;
@@ -1372,7 +1437,7 @@ static int ds_call(const gal_dataset *ds, const T *src, bool profile, int Nr, do
         return fail(GAL_ERR_UNSUPPORTED, "dataset precision %d differs from the call", ds->precision);
     if (chi2 && !ds->re) return fail(GAL_ERR_UNSUPPORTED, "dataset holds no observations");
     if (!chi2 && ds->M > 0 && !vis) return fail(GAL_ERR_NULL, "NULL output");
-    int rc = check_image_scalars(Nxy, dxy, PA, dRA, dDec, inc);
+    int rc = check_image_scalars(Nxy, dxy, PA, dRA, dDec, inc, NXY_BIG);
     if (rc) return rc;
     if (profile) {
         rc = check_profile(Nr, Rmin, dR);

@@ -347,10 +347,10 @@ __device__ __forceinline__ void rows_sym_body(PI I, const SweepArgs &sw, const G
     });
 }
 
-// Row pass of a swept profile by half-length transforms.  A row x of the
-// (centred) swept image is real and even, x[n] = x[N - n], so its spectrum is
-// real and even as well, and X[k] for k <= N/2 follows from one real DFT of
-// length h = N/2 (the two rows of a pair share one complex transform).  With
+// Half-length transform of even sequences.  A real sequence x of length
+// N = 2h that is even about 0, x[n] = x[N - n], has a real and even DFT, and
+// X[k] for k <= h follows from one real DFT of length h (two sequences share
+// one complex transform as its real and imaginary parts).  With
 //   a[n] = x[n] + x[h - n],  b[n] = x[n] - x[h - n]   (n in [0, h)),
 // the even outputs are the (real) DFT of a, X[2m] = sum_n a[n] cos(2 pi n m / h),
 // and the odd ones X[2m+1] = sum_n b[n] cos(pi n (2m+1) / h) obey
@@ -359,9 +359,84 @@ __device__ __forceinline__ void rows_sym_body(PI I, const SweepArgs &sw, const G
 //   y[n] = a[n] + sin(pi n / h) b[n],  Y = DFT_h(y):
 //   X[2m] = Re Y[m],  X[2m+1] = X[1] + 2 sum_{j=1..m} Im Y[j],
 //   X[1] = sum_n b[n] cos(pi n / h).
-// Half the FFT work of the length-N transform of rows_sym_body; the odd
-// outputs come from a prefix sum (in FP64) over the kept columns.  Same
-// output as rows_sym_body: XR[q * CS + r] = (-1)^q X_r[q], q < Qe.
+// Half the FFT work of the length-N transform; the odd outputs come from a
+// prefix sum (in FP64) over the kept outputs.
+//
+// The block's B pairs hold x[n], n in [0, h), at lds[Cfg::at(b, n)] and x[h]
+// at xh[b] (one sequence in .x, the other in .y), staged by the caller and
+// followed by a barrier.  For every pair b with active(b) and m in [0, Mk),
+// out(b, m, ev, od) receives ev = X[2m] and od = -X[2m+1] of both sequences.
+template <typename T, typename Cfg, typename Active, typename Out>
+__device__ __forceinline__ void even_transform(c2<T> *lds, const c2<T> *xh, c2<double> *part,
+                                               int tid, int Mk, Active active, Out out) {
+    constexpr int L = Cfg::L, B = Cfg::B, NT = Cfg::NT, E = Cfg::E;
+    constexpr int H = L, N = 2 * L;
+    constexpr int R0 = pass_radix(L, 1, Cfg::RMAX);
+    constexpr int LR = L / R0;
+    constexpr int NW = NT >= 64 ? NT / 64 : 1;
+    const c2<T> *tw = twiddles<T>();
+    const c2<T> *wN = tw + N;  // exp(-2 pi i n / N) = (cos(pi n / h), -sin(pi n / h))
+    c2<T> v[E];
+#pragma unroll
+    for (int i = 0; i < E / R0; ++i) {
+        const int gi = tid + i * NT;  // butterfly gi = b * LR + j of the first pass
+        const int b = gi / LR, j = gi % LR;
+        double p1 = 0.0, p2 = 0.0;
+#pragma unroll
+        for (int t = 0; t < R0; ++t) {
+            const int n = j + t * LR;
+            const c2<T> xa = lds[Cfg::at(b, n)];
+            const c2<T> xb = n == 0 ? xh[b] : lds[Cfg::at(b, H - n)];
+            const c2<T> w = wN[n];
+            const T b1 = xa.x - xb.x, b2 = xa.y - xb.y;
+            v[i * R0 + t] = c2<T>{xa.x + xb.x - w.y * b1, xa.y + xb.y - w.y * b2};
+            p1 += (double)w.x * (double)b1;
+            p2 += (double)w.x * (double)b2;
+        }
+        part[gi] = c2<double>{p1, p2};
+    }
+    // (the first pass's barrier orders these LDS reads before its writes)
+    fft_passes<Cfg, 1>(v, lds, tw, tid);
+
+    // one wave per pair: X[1] in a fixed order, then the outputs with the
+    // prefix sum of the odd ones over contiguous runs of m per lane
+    const int wave = tid >> 6, lane = tid & 63;
+    const int ch = (Mk + 63) / 64;
+    const int mb = lane * ch, me = min(mb + ch, Mk);
+    for (int b = wave; b < B; b += NW) {
+        if (!active(b)) continue;
+        double x1 = 0.0, x2 = 0.0;
+        for (int k = lane; k < LR; k += 64) {
+            x1 += part[b * LR + k].x;
+            x2 += part[b * LR + k].y;
+        }
+        x1 = wave_sum(x1);
+        x2 = wave_sum(x2);
+        // 2 Im Y[m] of each sequence from Z[m], Z[h - m] (Y1 = (Z[m] + conj Z[h-m]) / 2,
+        // Y2 = (Z[m] - conj Z[h-m]) / 2i)
+        double t1 = 0.0, t2 = 0.0;
+        for (int m = mb; m < me; ++m) {
+            const c2<T> z = lds[Cfg::at(b, m)], zc = lds[Cfg::at(b, (H - m) & (H - 1))];
+            t1 += (double)z.y - (double)zc.y;
+            t2 += (double)zc.x - (double)z.x;
+        }
+        double a1 = x1 + wave_excl_scan(t1), a2 = x2 + wave_excl_scan(t2);
+        for (int m = mb; m < me; ++m) {
+            const c2<T> z = lds[Cfg::at(b, m)], zc = lds[Cfg::at(b, (H - m) & (H - 1))];
+            a1 += (double)z.y - (double)zc.y;
+            a2 += (double)zc.x - (double)z.x;
+            const c2<T> ev{(T)(0.5 * ((double)z.x + (double)zc.x)),
+                           (T)(0.5 * ((double)z.y + (double)zc.y))};  // X[2m]
+            const c2<T> od{(T)(-a1), (T)(-a2)};                       // -X[2m+1]
+            out(b, m, ev, od);
+        }
+    }
+}
+
+// Row pass of a swept profile by half-length transforms: every row of the
+// (centred) swept image is even, so even_transform applies to the row pairs.
+// Half the FFT work of rows_sym_body, same output:
+// XR[q * CS + r] = (-1)^q X_r[q], q < Qe.
 template <typename T, typename Cfg, typename PI, bool TANGENT = false>
 __device__ __forceinline__ void rows_even_body(PI I, const SweepArgs &sw, const Geom &g, int Qe,
                                                T *__restrict__ XR, int blk) {
@@ -369,7 +444,6 @@ __device__ __forceinline__ void rows_even_body(PI I, const SweepArgs &sw, const 
     constexpr int H = L, N = 2 * L;
     constexpr int R0 = pass_radix(L, 1, Cfg::RMAX);
     constexpr int LR = L / R0;
-    constexpr int NW = NT >= 64 ? NT / 64 : 1;
     __shared__ c2<T> lds[B * Cfg::LS];
     __shared__ c2<T> xh[B];               // x[h] of each row pair
     __shared__ c2<double> part[B * LR];   // per-butterfly parts of X[1]
@@ -401,72 +475,20 @@ __device__ __forceinline__ void rows_even_body(PI I, const SweepArgs &sw, const 
             xh[tid] = c2<T>{(T)sweep_pixel(I, N, r, H, sw), (T)sweep_pixel(I, N, r + 1, H, sw)};
     }
     __syncthreads();
-    const c2<T> *tw = twiddles<T>();
-    const c2<T> *wN = tw + N;  // exp(-2 pi i n / N) = (cos(pi n / h), -sin(pi n / h))
-    c2<T> v[E];
-#pragma unroll
-    for (int i = 0; i < E / R0; ++i) {
-        const int gi = tid + i * NT;  // butterfly gi = b * LR + j of the first pass
-        const int b = gi / LR, j = gi % LR;
-        double p1 = 0.0, p2 = 0.0;
-#pragma unroll
-        for (int t = 0; t < R0; ++t) {
-            const int n = j + t * LR;
-            const c2<T> xa = lds[Cfg::at(b, n)];
-            const c2<T> xb = n == 0 ? xh[b] : lds[Cfg::at(b, H - n)];
-            const c2<T> w = wN[n];
-            const T b1 = xa.x - xb.x, b2 = xa.y - xb.y;
-            v[i * R0 + t] = c2<T>{xa.x + xb.x - w.y * b1, xa.y + xb.y - w.y * b2};
-            p1 += (double)w.x * (double)b1;
-            p2 += (double)w.x * (double)b2;
-        }
-        part[gi] = c2<double>{p1, p2};
-    }
-    // (the first pass's barrier orders these LDS reads before its writes)
-    fft_passes<Cfg, 1>(v, lds, tw, tid);
-
-    // one wave per row pair: X[1] in a fixed order, then the outputs with the
-    // prefix sum of the odd ones over contiguous runs of m per lane
-    const int wave = tid >> 6, lane = tid & 63;
-    const int Mq = Qe / 2;  // m in [0, Mq): columns 2m and 2m + 1 < Qe (Qe even, <= h + 2)
-    const int ch = (Mq + 63) / 64;
-    const int mb = lane * ch, me = min(mb + ch, Mq);
-    for (int b = wave; b < B; b += NW) {
-        const int r = 2 * (m0 + b);
-        if (r > N / 2) continue;
-        double x1 = 0.0, x2 = 0.0;
-        for (int k = lane; k < LR; k += 64) {
-            x1 += part[b * LR + k].x;
-            x2 += part[b * LR + k].y;
-        }
-        x1 = wave_sum(x1);
-        x2 = wave_sum(x2);
-        // 2 Im Y[m] of each row from Z[m], Z[h - m] (Y1 = (Z[m] + conj Z[h-m]) / 2,
-        // Y2 = (Z[m] - conj Z[h-m]) / 2i)
-        double t1 = 0.0, t2 = 0.0;
-        for (int m = mb; m < me; ++m) {
-            const c2<T> z = lds[Cfg::at(b, m)], zc = lds[Cfg::at(b, (H - m) & (H - 1))];
-            t1 += (double)z.y - (double)zc.y;
-            t2 += (double)zc.x - (double)z.x;
-        }
-        double a1 = x1 + wave_excl_scan(t1), a2 = x2 + wave_excl_scan(t2);
-        for (int m = mb; m < me; ++m) {
-            const c2<T> z = lds[Cfg::at(b, m)], zc = lds[Cfg::at(b, (H - m) & (H - 1))];
-            a1 += (double)z.y - (double)zc.y;
-            a2 += (double)zc.x - (double)z.x;
-            const c2<T> ev{(T)(0.5 * ((double)z.x + (double)zc.x)),
-                           (T)(0.5 * ((double)z.y + (double)zc.y))};  // X[2m]
-            const c2<T> od{(T)(-a1), (T)(-a2)};                       // -X[2m+1]
+    // Qe even, <= h + 2: m in [0, Qe / 2) gives columns 2m and 2m + 1 < Qe
+    even_transform<T, Cfg>(
+        lds, xh, part, tid, Qe / 2, [&](int b) { return 2 * (m0 + b) <= N / 2; },
+        [&](int b, int m, c2<T> ev, c2<T> od) {
+            const int r = 2 * (m0 + b);
             T *dst = XR + (size_t)(2 * m) * g.CS + r;
             if (r + 1 <= N / 2) {
                 *reinterpret_cast<c2<T> *>(dst) = ev;
-                if (2 * m + 1 < Qe) *reinterpret_cast<c2<T> *>(dst + g.CS) = od;
+                *reinterpret_cast<c2<T> *>(dst + g.CS) = od;
             } else {
                 dst[0] = ev.x;
-                if (2 * m + 1 < Qe) dst[g.CS] = od.x;
+                dst[g.CS] = od.x;
             }
-        }
-    }
+        });
 }
 
 template <typename T, typename Cfg, bool TANGENT = false>
@@ -531,6 +553,129 @@ __device__ __forceinline__ void cols_sym_body(const Geom &g, int Qe, T *__restri
 template <typename T, typename Cfg>
 __global__ __launch_bounds__(Cfg::NT) void k_cols_sym(Geom g, int Qe, T *__restrict__ XR) {
     cols_sym_body<T, Cfg>(g, Qe, XR, blockIdx.x);
+}
+
+// Column pass of a swept profile by half-length transforms, for images whose
+// full-length column does not fit in LDS (16384^2 in FP64).  A column of the
+// row pass's output is even in r about 0 (stored half r in [0, N/2]), so
+// even_transform applies with x[n] read from XR.  Columns q = 2 (m0 + b) and
+// q + 1 are the two sequences of a pair.  In place, as cols_sym_body:
+// SR[q * CS + p] = (-1)^p G[p][q] for p in [0, P] (every read of the block's
+// columns happens before its first barrier).
+template <typename T, typename Cfg>
+__device__ __forceinline__ void cols_even_body(const Geom &g, int Qe, T *__restrict__ XR, int blk) {
+    constexpr int L = Cfg::L, B = Cfg::B, NT = Cfg::NT, E = Cfg::E;
+    constexpr int H = L;
+    constexpr int R0 = pass_radix(L, 1, Cfg::RMAX);
+    constexpr int LR = L / R0;
+    __shared__ c2<T> lds[B * Cfg::LS];
+    __shared__ c2<T> xh[B];
+    __shared__ c2<double> part[B * LR];
+    const int tid = threadIdx.x;
+    const int m0 = blk * B;
+    if (2 * m0 >= Qe) return;
+    static_assert(B * H == E * NT, "E values per thread");
+#pragma unroll
+    for (int k = 0; k < E; ++k) {
+        const int idx = tid + k * NT;
+        const int b = idx / H, n = idx % H;
+        const int q = 2 * (m0 + b);
+        lds[Cfg::at(b, n)] = q < Qe ? c2<T>{XR[(size_t)q * g.CS + n], XR[(size_t)(q + 1) * g.CS + n]}
+                                    : c2<T>{T(0), T(0)};
+    }
+    if (tid < B) {
+        const int q = 2 * (m0 + tid);
+        xh[tid] = q < Qe ? c2<T>{XR[(size_t)q * g.CS + H], XR[(size_t)(q + 1) * g.CS + H]}
+                         : c2<T>{T(0), T(0)};
+    }
+    __syncthreads();
+    // m in [0, P / 2 + 1): rows 2m <= P and 2m + 1 (kept when <= P)
+    even_transform<T, Cfg>(
+        lds, xh, part, tid, g.P / 2 + 1, [&](int b) { return 2 * (m0 + b) < Qe; },
+        [&](int b, int m, c2<T> ev, c2<T> od) {
+            T *dst = XR + (size_t)(2 * (m0 + b)) * g.CS + 2 * m;
+            dst[0] = ev.x;
+            dst[g.CS] = ev.y;
+            if (2 * m + 1 <= g.P) {
+                dst[1] = od.x;
+                dst[g.CS + 1] = od.y;
+            }
+        });
+}
+
+template <typename T, typename Cfg>
+__global__ __launch_bounds__(Cfg::NT) void k_cols_even(Geom g, int Qe, T *__restrict__ XR) {
+    cols_even_body<T, Cfg>(g, Qe, XR, blockIdx.x);
+}
+
+// Column pass of a general image whose column does not fit in LDS (16384^2
+// in FP64), in two launches by the four-step factorisation of the DFT: with
+// n = n1 + N1 n2 and p = k2 + N2 k1 (N = N1 N2),
+//   X[k2 + N2 k1] = sum_n1 W_N1^(n1 k1) [ W_N^(n1 k2) sum_n2 x[n1 + N1 n2] W_N2^(n2 k2) ],
+// W_M = exp(-2 pi i / M).  Step A, in place: for a group of B values n1, the
+// length-N2 DFTs over n2, times W_N^(n1 k2), stored at n1 + N1 k2.  Step B:
+// for a group of B values k2, the length-N1 DFTs over n1 (contiguous in
+// memory), whose outputs p~ in [-P, P] go to the separate spectrum
+// SP[q * CS2 + p~ + P] with the shift sign (-1)^p~ (cols_body's layout).
+// blockIdx.y = column q.  Cfg: B sequences of length N1 = N2.
+template <typename T, typename Cfg, int NTOT>
+__global__ __launch_bounds__(Cfg::NT) void k_cols4a(Geom g, c2<T> *__restrict__ XT) {
+    constexpr int L = Cfg::L, B = Cfg::B, NT = Cfg::NT, E = Cfg::E;
+    constexpr int N1 = NTOT / L;
+    static_assert(N1 == L, "square factorisation");
+    __shared__ c2<T> lds[B * Cfg::LS];
+    const int tid = threadIdx.x;
+    const int n10 = blockIdx.x * B;
+    c2<T> *col = XT + (size_t)blockIdx.y * g.CS;
+    // x[n1 + N1 n2], n1 fastest: runs of B contiguous values
+    for (int idx = tid; idx < B * L; idx += NT) {
+        const int b = idx % B, n2 = idx / B;
+        lds[Cfg::at(b, n2)] = col[n10 + b + (size_t)N1 * n2];
+    }
+    __syncthreads();
+    c2<T> v[E];
+    fft_gather<Cfg, 1>(v, lds, tid);
+    const c2<T> *tw = twiddles<T>();
+    fft_passes<Cfg, 1>(v, lds, tw, tid);
+    const c2<T> *wN = tw + NTOT;  // exp(-2 pi i m / N)
+    for (int idx = tid; idx < B * L; idx += NT) {
+        const int b = idx % B, k2 = idx / B;
+        const int n1 = n10 + b;
+        col[n1 + (size_t)N1 * k2] = cmul(lds[Cfg::at(b, k2)], wN[(n1 * k2) & (NTOT - 1)]);
+    }
+}
+
+template <typename T, typename Cfg, int NTOT>
+__global__ __launch_bounds__(Cfg::NT) void k_cols4b(Geom g, const c2<T> *__restrict__ XT,
+                                                    c2<T> *__restrict__ SP, int CS2) {
+    constexpr int L = Cfg::L, B = Cfg::B, NT = Cfg::NT, E = Cfg::E;
+    constexpr int N2 = NTOT / L;
+    constexpr int R0 = pass_radix(L, 1, Cfg::RMAX);
+    constexpr int LR = L / R0;
+    __shared__ c2<T> lds[B * Cfg::LS];
+    const int tid = threadIdx.x;
+    const int k20 = blockIdx.x * B;
+    const c2<T> *col = XT + (size_t)blockIdx.y * g.CS;
+    // first-pass inputs y[n1 + N1 k2] straight from memory (n1 contiguous)
+    c2<T> v[E];
+#pragma unroll
+    for (int i = 0; i < E / R0; ++i) {
+        const int gi = tid + i * NT;
+        const int b = gi / LR, j = gi % LR;
+#pragma unroll
+        for (int t = 0; t < R0; ++t) v[i * R0 + t] = col[j + t * LR + (size_t)L * (k20 + b)];
+    }
+    fft_passes<Cfg, 1>(v, lds, twiddles<T>(), tid);
+    c2<T> *out = SP + (size_t)blockIdx.y * CS2;
+    for (int idx = tid; idx < B * L; idx += NT) {
+        const int b = idx % B, k1 = idx / B;
+        const int p = k20 + b + N2 * k1;
+        const int pt = p < NTOT / 2 ? p : p - NTOT;
+        if (pt < -g.P || pt > g.P) continue;
+        c2<T> X = lds[Cfg::at(b, k1)];
+        if (pt & 1) X = c2<T>{-X.x, -X.y};
+        out[pt + g.P] = X;
+    }
 }
 
 // ---------------------------------------------------------------------------

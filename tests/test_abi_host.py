@@ -38,10 +38,14 @@ def test_workspace_sizes_are_host_computable():
         pytest.skip("HIP library not built")
     L = _native.lib()
     # control block + partials + (N/2+1)(N+2) complex values
-    for N, M in [(16, 0), (256, 10**4), (2048, 10**6), (8192, 5 * 10**6)]:
+    for N, M in [(16, 0), (256, 10**4), (2048, 10**6), (8192, 5 * 10**6), (16384, 10**6)]:
         d = L.gal_workspace_bytes_d(N, M)
         f = L.gal_workspace_bytes_f(N, M)
         assert d >= (N // 2 + 1) * (N + 2) * 16 and f >= (N // 2 + 1) * (N + 2) * 8
         assert d > f
     assert L.gal_workspace_bytes_d(48, 10) == 0      # not a power of two
-    assert L.gal_workspace_bytes_d(16384, 10) == 0   # above the supported range
+    assert L.gal_workspace_bytes_d(32768, 10) == 0   # above the supported range
+    # 16384^2 in FP64: the four-step column pass writes the spectrum apart
+    assert L.gal_workspace_bytes_d(16384, 10) >= 2 * 8193 * 16385 * 16
+    # gradients stop at 8192
+    assert L.gal_grad_workspace_bytes_d(16384, 10, 100) == 0
