@@ -333,6 +333,14 @@ int gal_uv_range_d(const double *u, const double *v, int64_t M, double *rho_min,
 int gal_uv_range_f(const float *u, const float *v, int64_t M, double *rho_min, double *rho_max);
 int gal_dataset_image_size(const gal_dataset *ds, double f_min, double f_max, double PB,
                            double Gamma, int *Nxy, double *dxy);
+/* As gal_image_size and gal_dataset_image_size, with Nxy the smallest even
+ * 2^a 3^b 5^c (not only powers of two) meeting criterion (i): the paper
+ * advises powers of two, these sizes run on the forward calls' mixed-radix
+ * path up to 8192 and are never larger than the power-of-two answer. */
+int gal_image_size_smooth(double rho_min, double rho_max, double f_min, double f_max, double PB,
+                          double Gamma, int *Nxy, double *dxy);
+int gal_dataset_image_size_smooth(const gal_dataset *ds, double f_min, double f_max, double PB,
+                                  double Gamma, int *Nxy, double *dxy);
 
 /* ---- batches: many chi^2 evaluations per launch --------------------------
  * A batch is a fixed list of jobs, planned once.  Jobs with the same

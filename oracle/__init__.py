@@ -341,7 +341,7 @@ def grad_sources(sources, u, v, re, im, w):
     return c2, grads
 
 
-def get_image_size(u, v, PB=0.0, f_min=5.0, f_max=2.5, Gamma=0.6):
+def get_image_size(u, v, PB=0.0, f_min=5.0, f_max=2.5, Gamma=0.6, smooth=False):
     """(N, dxy [rad]) for the uv points by the image-size criteria of Sec. 3.4.
 
     uv cell: criterion (iia), the image spans f_min times the largest
@@ -349,11 +349,23 @@ def get_image_size(u, v, PB=0.0, f_min=5.0, f_max=2.5, Gamma=0.6):
     primary-beam FWHM PB > 0, criterion (iib), the image spans the beam, du =
     1 / PB.  Size: criterion (i), the grid reaches f_max times the longest
     baseline, N du / 2 >= f_max rho_max, with N the smallest power of two that
-    does (the advice after the paper's table).  Pixel: dxy = 1 / (N du), so the
-    image keeps the field of (iia) or (iib) exactly."""
+    does (the advice after the paper's table); smooth: the smallest even
+    N = 2^a 3^b 5^c that does, found by trying every even N in turn.  Pixel:
+    dxy = 1 / (N du), so the image keeps the field of (iia) or (iib) exactly."""
     rho = np.hypot(np.asarray(u, dtype=np.float64), np.asarray(v, dtype=np.float64))
     rho_min, rho_max = float(rho.min()), float(rho.max())
     du = 1.0 / PB if PB > 0 else rho_min / (Gamma * f_min)
+    if smooth:
+        def five_smooth(n):
+            for f in (2, 3, 5):
+                while n % f == 0:
+                    n //= f
+            return n == 1
+
+        N = 2
+        while N * du / 2.0 < f_max * rho_max or not five_smooth(N):
+            N += 2
+        return N, 1.0 / (N * du)
     N = 2
     while N * du / 2.0 < f_max * rho_max:
         N *= 2

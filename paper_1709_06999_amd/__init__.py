@@ -320,12 +320,13 @@ def sample_spectrum(spec, dxy, u, v, PA=0.0, dRA=0.0, dDec=0.0, inc=0.0,
 
 # ----------------------------------------------------------------------------
 def get_image_size(u, v, PB: float = 0.0, f_min: float = 5.0, f_max: float = 2.5,
-                   Gamma: float = 0.6):
+                   Gamma: float = 0.6, smooth: bool = False):
     """(Nxy, dxy [rad]) for the uv points by the criteria of Sec. 3.4
     (gal_image_size): the image spans f_min times the largest recoverable scale
     Gamma / rho_min (or, with PB > 0, the primary beam of FWHM PB [rad]), the
-    grid reaches f_max times the longest baseline, Nxy a power of two.  u, v:
-    numpy arrays or tensors (read on the host)."""
+    grid reaches f_max times the longest baseline, Nxy a power of two (smooth:
+    the smallest even 2^a 3^b 5^c, gal_image_size_smooth).  u, v: numpy arrays
+    or tensors (read on the host)."""
     import numpy as np
 
     host = [np.ascontiguousarray(x.detach().cpu().numpy() if isinstance(x, torch.Tensor) else x)
@@ -340,8 +341,9 @@ def get_image_size(u, v, PB: float = 0.0, f_min: float = 5.0, f_max: float = 2.5
                                                 host[0].size, ctypes.byref(lo), ctypes.byref(hi)),
           "get_image_size")
     n, d = ctypes.c_int(0), ctypes.c_double(0)
-    check(_lib().gal_image_size(lo.value, hi.value, float(f_min), float(f_max), float(PB),
-                                float(Gamma), ctypes.byref(n), ctypes.byref(d)), "get_image_size")
+    fn = _lib().gal_image_size_smooth if smooth else _lib().gal_image_size
+    check(fn(lo.value, hi.value, float(f_min), float(f_max), float(PB), float(Gamma),
+             ctypes.byref(n), ctypes.byref(d)), "get_image_size")
     return int(n.value), float(d.value)
 
 
@@ -374,12 +376,12 @@ class Dataset:
         self.rho_max = float(rho.value)
 
     def image_size(self, PB: float = 0.0, f_min: float = 5.0, f_max: float = 2.5,
-                   Gamma: float = 0.6):
+                   Gamma: float = 0.6, smooth: bool = False):
         """(Nxy, dxy) for this dataset's uv range (as ``get_image_size``)."""
         n, d = ctypes.c_int(0), ctypes.c_double(0)
-        check(_lib().gal_dataset_image_size(self._h, float(f_min), float(f_max), float(PB),
-                                            float(Gamma), ctypes.byref(n), ctypes.byref(d)),
-              "Dataset.image_size")
+        fn = _lib().gal_dataset_image_size_smooth if smooth else _lib().gal_dataset_image_size
+        check(fn(self._h, float(f_min), float(f_max), float(PB), float(Gamma), ctypes.byref(n),
+                 ctypes.byref(d)), "Dataset.image_size")
         return int(n.value), float(d.value)
 
     def geometry(self, Nxy, dxy):

@@ -70,6 +70,9 @@ _SIG = {
     "gal_image_size": (I, [D, D, D, D, D, D, ctypes.POINTER(I), ctypes.POINTER(D)]),
     "gal_uv_range": (I, [P, P, I64, ctypes.POINTER(D), ctypes.POINTER(D)]),
     "gal_dataset_image_size": (I, [P, D, D, D, D, ctypes.POINTER(I), ctypes.POINTER(D)]),
+    "gal_image_size_smooth": (I, [D, D, D, D, D, D, ctypes.POINTER(I), ctypes.POINTER(D)]),
+    "gal_dataset_image_size_smooth": (I, [P, D, D, D, D, ctypes.POINTER(I),
+                                          ctypes.POINTER(D)]),
     "gal_batch_create": (I, [P, I, ctypes.POINTER(P)]),
     "gal_batch_workspace_bytes": (SZ, [P]),
     "gal_batch_info": (I, [P, ctypes.POINTER(I), ctypes.POINTER(I), ctypes.POINTER(I)]),

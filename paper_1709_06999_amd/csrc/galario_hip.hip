@@ -22,6 +22,7 @@
 #include "batch.h"
 #include "geograd.h"
 #include "kernels.h"
+#include "mixed_radix.h"
 
 namespace gal {
 
@@ -478,11 +479,18 @@ static size_t spec2_bytes(int N) {
     return four_step<T>(N) ? align256((size_t)(N / 2 + 1) * (size_t)(N + 1) * sizeof(c2<T>)) : 0;
 }
 
+// mixed-radix sizes: the twiddle table of N and the swept image of a profile
+template <typename T>
+static size_t mr_bytes(int N) {
+    if ((N & (N - 1)) == 0) return 0;
+    return align256((size_t)N * sizeof(c2<T>)) + align256((size_t)N * (size_t)N * sizeof(T));
+}
+
 template <typename T>
 static size_t ws_bytes(int N, int64_t M) {
     const size_t partials = align256((size_t)sample_blocks(M) * sizeof(double));
     const size_t xt = align256((size_t)(N / 2 + 1) * (size_t)(N + 2) * sizeof(c2<T>));
-    return 256 + partials + xt + spec2_bytes<T>(N);
+    return 256 + partials + xt + spec2_bytes<T>(N) + mr_bytes<T>(N);
 }
 
 struct WS {
@@ -490,6 +498,7 @@ struct WS {
     double *partials;
     void *xt;
     void *spec2;  // four-step column pass output (NULL otherwise)
+    void *mr;     // mixed-radix sizes: twiddle table, then the swept image (NULL otherwise)
 };
 
 template <typename T>
@@ -502,9 +511,9 @@ static int carve(void *ws, size_t bytes, int N, int64_t M, WS &out) {
     out.ctl = (Control *)p;
     out.partials = (double *)(p + 256);
     out.xt = p + 256 + align256((size_t)sample_blocks(M) * sizeof(double));
-    out.spec2 = four_step<T>(N)
-                    ? (char *)out.xt + align256((size_t)(N / 2 + 1) * (size_t)(N + 2) * sizeof(c2<T>))
-                    : nullptr;
+    char *after_xt = (char *)out.xt + align256((size_t)(N / 2 + 1) * (size_t)(N + 2) * sizeof(c2<T>));
+    out.spec2 = four_step<T>(N) ? after_xt : nullptr;
+    out.mr = mr_bytes<T>(N) ? after_xt + spec2_bytes<T>(N) : nullptr;
     return GAL_OK;
 }
 
@@ -515,14 +524,54 @@ static int carve(void *ws, size_t bytes, int N, int64_t M, WS &out) {
 // batches, the autotuner and the separate spectrum calls
 static bool pow2_upto(int N, int nmax) { return N >= 16 && N <= nmax && (N & (N - 1)) == 0; }
 static bool pow2_in_range(int N) { return pow2_upto(N, 8192); }
+// the forward calls also take even N = 2^a 3^b 5^c (not a power of two) in
+// [16, 8192], on the mixed-radix path
+static bool mr_size(int N) {
+    if (N < 16 || N > MR_LMAX || (N & 1) || (N & (N - 1)) == 0) return false;
+    int n = N;
+    for (int f : {2, 3, 5})
+        while (n % f == 0) n /= f;
+    return n == 1;
+}
+static bool fwd_size(int N) { return pow2_upto(N, NXY_BIG) || mr_size(N); }
+
+// radices of a length-L transform (4s, then a 2, 3s, 5s); false if some pass
+// would hold more than MR_BPT butterflies per thread of an NT-thread block
+static bool mr_plan(int L, int N, int NT, MrPlan &pl) {
+    pl.L = L;
+    pl.tstride = N / L;
+    pl.np = 0;
+    int n = L;
+    auto add = [&](int r) {
+        if (pl.np >= MR_MAXPASS || L / r > MR_BPT * NT) return false;
+        pl.radix[pl.np++] = r;
+        n /= r;
+        return true;
+    };
+    while (n % 4 == 0)
+        if (!add(4)) return false;
+    while (n % 2 == 0)
+        if (!add(2)) return false;
+    while (n % 3 == 0)
+        if (!add(3)) return false;
+    while (n % 5 == 0)
+        if (!add(5)) return false;
+    return n == 1;
+}
 // smallest pixel size: squared pixel radii stay far above the range where the
 // sweep's square root would need scaling
 constexpr double DXY_MIN = 1e-100;
 
+// forward: the paper's calls (powers of two to NXY_BIG, mixed-radix sizes);
+// otherwise powers of two to 8192
 static int check_image_scalars(int N, double dxy, double PA, double dRA, double dDec, double inc,
-                               int nmax = 8192) {
-    if (!pow2_upto(N, nmax))
-        return fail(GAL_ERR_SIZE, "Nxy=%d: need a power of two in [16, %d]", N, nmax);
+                               bool forward = false) {
+    if (forward && !fwd_size(N))
+        return fail(GAL_ERR_SIZE,
+                    "Nxy=%d: need a power of two in [16, %d] or an even 2^a 3^b 5^c in [16, %d]",
+                    N, NXY_BIG, MR_LMAX);
+    if (!forward && !pow2_in_range(N))
+        return fail(GAL_ERR_SIZE, "Nxy=%d: need a power of two in [16, 8192] here", N);
     if (!(dxy >= DXY_MIN) || !std::isfinite(dxy)) return fail(GAL_ERR_SCALAR, "dxy must be >= 1e-100");
     if (!std::isfinite(PA) || !std::isfinite(dRA) || !std::isfinite(dDec) || !std::isfinite(inc))
         return fail(GAL_ERR_SCALAR, "PA, dRA, dDec and inc must be finite");
@@ -644,16 +693,53 @@ static int sample(bool real_spec, const void *S, const Geom &gs, const SampleArg
     return launch("k_reduce", k_reduce, dim3(1), dim3(REDUCE_NT), s, w.partials, (int)grid.x, chi2);
 }
 
+// Mixed-radix sizes: the image (a profile swept into the workspace first)
+// through k_mr_rows and k_mr_cols into the complex spectrum layout of the
+// general path, with the twiddle table of N filled at the head of the call.
+template <typename T>
+static int transform_mr(const T *src, bool profile, const SweepArgs &sw, const Geom &g,
+                        const WS &w, hipStream_t s) {
+    const int N = g.N;
+    MrPlan prow, pcol;
+    if (!mr_plan(N / 2, N, MR_ROWS_NT, prow) || !mr_plan(N, N, MR_COLS_NT, pcol))
+        return fail(GAL_ERR_SIZE, "Nxy=%d: no mixed-radix schedule", N);
+    c2<T> *W = (c2<T> *)w.mr;
+    T *img = (T *)((char *)w.mr + align256((size_t)N * sizeof(c2<T>)));
+    int rc = launch("k_mr_twiddles", k_mr_twiddles<T>, dim3((N + 255) / 256), dim3(256), s, W, N);
+    if (rc) return rc;
+    if (profile) {
+        const int64_t n = (int64_t)N * N;
+        rc = launch("k_sweep", k_sweep<T>, dim3((unsigned)((n + 255) / 256)), dim3(256), s, src, sw,
+                    N, img);
+        if (rc) return rc;
+        src = img;
+    }
+    rc = launch("k_mr_rows", k_mr_rows<T>, dim3(N), dim3(MR_ROWS_NT), s, src, g, prow,
+                (const c2<T> *)W, w.xt);
+    if (rc) return rc;
+    return launch("k_mr_cols", k_mr_cols<T>, dim3(g.Q), dim3(MR_COLS_NT), s, g, pcol,
+                  (const c2<T> *)W, w.xt);
+}
+
 template <typename T>
 static int run_carved(const T *src, bool profile, const SweepArgs &sw, const Geom &g, double dxy,
                       const Obs<T> &o, double PA, double dRA, double dDec, double inc, T *vis,
                       double *chi2, const WS &w, hipStream_t s) {
     Geom gs;
     void *S = nullptr;
-    int rc = transform<T>(src, profile, sw, g, w.xt, s, gs, w.spec2, &S);
+    bool real_spec = profile;
+    int rc;
+    if (w.mr) {
+        rc = transform_mr<T>(src, profile, sw, g, w, s);
+        gs = g;
+        S = w.xt;
+        real_spec = false;
+    } else {
+        rc = transform<T>(src, profile, sw, g, w.xt, s, gs, w.spec2, &S);
+    }
     if (rc) return rc;
     const SampleArgs sa = make_sample(g, o.M, dxy, PA, dRA, dDec, inc);
-    return sample<T>(profile, S, gs, sa, o, vis, chi2, w, s);
+    return sample<T>(real_spec, S, gs, sa, o, vis, chi2, w, s);
 }
 
 template <typename T>
@@ -1001,11 +1087,11 @@ int gal_init(int device) {
 }
 
 size_t gal_workspace_bytes_d(int Nxy, int64_t M) {
-    if (!pow2_upto(Nxy, NXY_BIG) || M < 0) return 0;
+    if (!fwd_size(Nxy) || M < 0) return 0;
     return ws_bytes<double>(Nxy, M);
 }
 size_t gal_workspace_bytes_f(int Nxy, int64_t M) {
-    if (!pow2_upto(Nxy, NXY_BIG) || M < 0) return 0;
+    if (!fwd_size(Nxy) || M < 0) return 0;
     return ws_bytes<float>(Nxy, M);
 }
 
@@ -1038,7 +1124,7 @@ template <typename T>
 static int sweep_impl(const T *I, int Nr, double Rmin, double dR, int Nxy, double dxy, double inc,
                       T *image, void *stream) {
     if (!I || !image) return fail(GAL_ERR_NULL, "NULL array");
-    int rc = check_image_scalars(Nxy, dxy, 0.0, 0.0, 0.0, inc, NXY_BIG);
+    int rc = check_image_scalars(Nxy, dxy, 0.0, 0.0, 0.0, inc, true);
     if (rc) return rc;
     rc = check_profile(Nr, Rmin, dR);
     if (rc) return rc;
@@ -1066,7 +1152,7 @@ static int image_call(const T *image, int Nxy, double dxy, const T *u, const T *
     if (chi2 && M > 0 && (!re || !im || !w)) return fail(GAL_ERR_NULL, "NULL observation array");
     if (!chi2 && M > 0 && !vis) return fail(GAL_ERR_NULL, "NULL output");
     if (M < 0) return fail(GAL_ERR_SIZE, "M < 0");
-    int rc = check_image_scalars(Nxy, dxy, PA, dRA, dDec, inc, NXY_BIG);
+    int rc = check_image_scalars(Nxy, dxy, PA, dRA, dDec, inc, true);
     if (rc) return rc;
     const Geom g = geom_full(Nxy);
     return run_path<T>(image, false, SweepArgs{}, g, dxy, Obs<T>{u, v, re, im, w, M, nullptr}, PA, dRA, dDec,
@@ -1082,7 +1168,7 @@ static int profile_call(const T *I, int Nr, double Rmin, double dR, int Nxy, dou
     if (chi2 && M > 0 && (!re || !im || !w)) return fail(GAL_ERR_NULL, "NULL observation array");
     if (!chi2 && M > 0 && !vis) return fail(GAL_ERR_NULL, "NULL output");
     if (M < 0) return fail(GAL_ERR_SIZE, "M < 0");
-    int rc = check_image_scalars(Nxy, dxy, PA, dRA, dDec, inc, NXY_BIG);
+    int rc = check_image_scalars(Nxy, dxy, PA, dRA, dDec, inc, true);
     if (rc) return rc;
     rc = check_profile(Nr, Rmin, dR);
     if (rc) return rc;
@@ -1360,8 +1446,9 @@ int gal_dataset_info(const gal_dataset *ds, int64_t *M, double *rho_max, int *pr
 }
 
 // ---- image size (Sec. 3.4 criteria) ---------------------------------------
-int gal_image_size(double rho_min, double rho_max, double f_min, double f_max, double PB,
-                   double Gamma, int *Nxy, double *dxy) {
+// smooth: N the smallest even 2^a 3^b 5^c instead of the smallest power of two
+static int image_size(double rho_min, double rho_max, double f_min, double f_max, double PB,
+                      double Gamma, bool smooth, int *Nxy, double *dxy) {
     if (!Nxy || !dxy) return fail(GAL_ERR_NULL, "NULL output");
     if (!(f_max > 2.0) || !std::isfinite(f_max)) return fail(GAL_ERR_SCALAR, "f_max must be > 2");
     if (!(PB >= 0.0) || !std::isfinite(PB)) return fail(GAL_ERR_SCALAR, "PB must be >= 0");
@@ -1382,9 +1469,30 @@ int gal_image_size(double rho_min, double rho_max, double f_min, double f_max, d
         n *= 2;
         if (n > ((int64_t)1 << 30)) return fail(GAL_ERR_SIZE, "image size above 2^30");
     }
+    if (smooth) {
+        // the smallest even 2^a 3^b 5^c meeting (i): between n / 2 and n
+        for (int64_t m = n / 2 + (n / 2) % 2; m <= n; m += 2) {
+            if ((double)m * du / 2.0 < f_max * rho_max) continue;
+            int64_t r = m;
+            for (int f : {2, 3, 5})
+                while (r % f == 0) r /= f;
+            if (r == 1) {
+                n = m;
+                break;
+            }
+        }
+    }
     *Nxy = (int)n;
     *dxy = 1.0 / ((double)n * du);
     return GAL_OK;
+}
+int gal_image_size(double rho_min, double rho_max, double f_min, double f_max, double PB,
+                   double Gamma, int *Nxy, double *dxy) {
+    return image_size(rho_min, rho_max, f_min, f_max, PB, Gamma, false, Nxy, dxy);
+}
+int gal_image_size_smooth(double rho_min, double rho_max, double f_min, double f_max, double PB,
+                          double Gamma, int *Nxy, double *dxy) {
+    return image_size(rho_min, rho_max, f_min, f_max, PB, Gamma, true, Nxy, dxy);
 }
 
 template <typename T>
@@ -1417,10 +1525,16 @@ int gal_dataset_image_size(const gal_dataset *ds, double f_min, double f_max, do
     if (ds->M < 1) return fail(GAL_ERR_SIZE, "empty dataset");
     return gal_image_size(ds->rho_min, ds->rho_max, f_min, f_max, PB, Gamma, Nxy, dxy);
 }
+int gal_dataset_image_size_smooth(const gal_dataset *ds, double f_min, double f_max, double PB,
+                                  double Gamma, int *Nxy, double *dxy) {
+    if (!ds) return fail(GAL_ERR_NULL, "NULL dataset");
+    if (ds->M < 1) return fail(GAL_ERR_SIZE, "empty dataset");
+    return gal_image_size_smooth(ds->rho_min, ds->rho_max, f_min, f_max, PB, Gamma, Nxy, dxy);
+}
 
 int gal_dataset_geometry(const gal_dataset *ds, int Nxy, double dxy, int *Q, int *P) {
     if (!ds || !Q || !P) return fail(GAL_ERR_NULL, "NULL argument");
-    int rc = check_image_scalars(Nxy, dxy, 0.0, 0.0, 0.0, 0.0, NXY_BIG);
+    int rc = check_image_scalars(Nxy, dxy, 0.0, 0.0, 0.0, 0.0, true);
     if (rc) return rc;
     const Geom g = geom_pruned(Nxy, dxy, ds->rho_max);
     *Q = g.Q;
@@ -1437,7 +1551,7 @@ static int ds_call(const gal_dataset *ds, const T *src, bool profile, int Nr, do
         return fail(GAL_ERR_UNSUPPORTED, "dataset precision %d differs from the call", ds->precision);
     if (chi2 && !ds->re) return fail(GAL_ERR_UNSUPPORTED, "dataset holds no observations");
     if (!chi2 && ds->M > 0 && !vis) return fail(GAL_ERR_NULL, "NULL output");
-    int rc = check_image_scalars(Nxy, dxy, PA, dRA, dDec, inc, NXY_BIG);
+    int rc = check_image_scalars(Nxy, dxy, PA, dRA, dDec, inc, true);
     if (rc) return rc;
     if (profile) {
         rc = check_profile(Nr, Rmin, dR);

@@ -43,7 +43,10 @@ def test_workspace_sizes_are_host_computable():
         f = L.gal_workspace_bytes_f(N, M)
         assert d >= (N // 2 + 1) * (N + 2) * 16 and f >= (N // 2 + 1) * (N + 2) * 8
         assert d > f
-    assert L.gal_workspace_bytes_d(48, 10) == 0      # not a power of two
+    assert L.gal_workspace_bytes_d(56, 10) == 0      # 7 is not a factor the FFTs take
+    assert L.gal_workspace_bytes_d(47, 10) == 0      # odd
+    # 48 = 2^4 3: the mixed-radix path, with a twiddle table and a sweep buffer
+    assert L.gal_workspace_bytes_d(48, 10) >= 25 * 50 * 16 + 48 * 16 + 48 * 48 * 8
     assert L.gal_workspace_bytes_d(32768, 10) == 0   # above the supported range
     # 16384^2 in FP64: the four-step column pass writes the spectrum apart
     assert L.gal_workspace_bytes_d(16384, 10) >= 2 * 8193 * 16385 * 16

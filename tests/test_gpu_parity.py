@@ -323,10 +323,10 @@ def test_host_side_errors():
     gal = _gal()
     from paper_1709_06999_amd import GalarioError
 
-    img = t(np.zeros((48, 48)), np.float64, dev)
+    img = t(np.zeros((56, 56)), np.float64, dev)
     u = t(np.zeros(4), np.float64, dev)
     with pytest.raises(GalarioError, match="GAL_ERR_SIZE"):
-        gal.sampleImage(img, 1e-7, u, u)                         # 48 is not a power of two
+        gal.sampleImage(img, 1e-7, u, u)                         # 56 = 2^3 7
     img = t(np.zeros((64, 64)), np.float64, dev)
     with pytest.raises(GalarioError, match="GAL_ERR_SCALAR"):
         gal.sampleImage(img, -1e-7, u, u)                        # dxy <= 0

@@ -71,3 +71,28 @@ def test_argument_checks():
         gal.get_image_size(np.array([np.nan, 1.0]), np.array([0.0, 1.0]))
     with pytest.raises(gal.GalarioError):  # beyond 2^30
         gal.get_image_size(np.array([1.0, 1e12]), np.array([0.0, 0.0]))
+
+
+@pytest.mark.parametrize("dtype", [np.float64, np.float32])
+def test_smooth_sizes_match_oracle(dtype):
+    """Even 2^a 3^b 5^c sizes: the library's search against the oracle's
+    even-by-even search, never above the power of two, and minimal."""
+    gal = _gal()
+    rng = np.random.default_rng(3601)
+    seen = set()
+    for _ in range(60):
+        M = int(rng.integers(1, 500))
+        r = np.exp(rng.uniform(np.log(1e3), np.log(2e7), M))
+        a = rng.uniform(0, 2 * np.pi, M)
+        u, v = (r * np.cos(a)).astype(dtype), (r * np.sin(a)).astype(dtype)
+        kw = dict(f_min=rng.uniform(1.5, 8.0), f_max=rng.uniform(2.1, 4.0),
+                  Gamma=rng.uniform(0.4, 0.8))
+        N, d = gal.get_image_size(u, v, smooth=True, **kw)
+        No, do = oracle.get_image_size(u.astype(np.float64), v.astype(np.float64), smooth=True,
+                                       **kw)
+        assert N == No
+        assert abs(d - do) <= 1e-15 * do
+        N2, _ = gal.get_image_size(u, v, **kw)
+        assert N <= N2 and N % 2 == 0
+        seen.add(N != N2)
+    assert seen == {True, False}   # both kinds of answer occur

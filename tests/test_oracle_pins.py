@@ -629,3 +629,19 @@ def test_image_size_primary_beam_criterion():
         assert abs(N * dxy - PB) <= 1e-15 * PB
         du = 1.0 / PB
         assert N * du / 2 >= 2.5 * r.max() > (N // 2) * du / 2
+
+
+def test_image_size_smooth_hand_worked():
+    # with PB = 1 the uv cell is 1 and criterion (i) reads N >= 2 f_max rho_max;
+    # the smallest even 2^a 3^b 5^c at or above the bound, worked by hand:
+    # 47 -> 48 = 2^4 3, 98 -> 100 = 2^2 5^2, 61 -> 64 = 2^6, 121 -> 128
+    # (122 = 2 61, 124 = 4 31, 126 = 2 3^2 7), 17 -> 18 = 2 3^2
+    for bound, N_expect in ((47, 48), (98, 100), (61, 64), (121, 128), (17, 18)):
+        rho = (bound - 0.5) / 5.0   # 2 f_max rho = bound - 0.5 with f_max = 2.5
+        u, v = np.array([rho, 0.3 * rho]), np.array([0.0, 0.1 * rho])
+        N, dxy = oracle.get_image_size(u, v, PB=1.0, smooth=True)
+        assert N == N_expect, (bound, N)
+        assert dxy == 1.0 / N_expect
+        # the power-of-two rule on the same points
+        N2, _ = oracle.get_image_size(u, v, PB=1.0)
+        assert N2 == 1 << (N_expect - 1).bit_length()
