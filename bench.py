@@ -414,7 +414,7 @@ def serve_bench(gal, torch, np, dev, rates, sat_rates, n_req, warm, grad_frac, n
                          "p50_ms": best["p50_ms"], "p99_ms": best["p99_ms"]}}
 
 
-def served_headline(gal, torch, np, dev, case, n_req, warm):
+def served_headline(gal, torch, np, dev, case, n_req, warm, max_batch=64):
     """The served form at the headline workload: chi^2 requests of perturbed
     profiles (walkers) on the 2048^2, M = 1e6 dataset, all submitted at once
     (a closed batch, as an ensemble sampler's step), so that the loop runs at
@@ -422,7 +422,7 @@ def served_headline(gal, torch, np, dev, case, n_req, warm):
     batched forms of the same evaluation."""
     from paper_1709_06999_amd.serve import GpuExecutor, Request, Server
 
-    ex = GpuExecutor(dev, torch.float64, max_batch=16, max_inflight=4)
+    ex = GpuExecutor(dev, torch.float64, max_batch=max_batch, max_inflight=4)
     f64 = lambda a: torch.as_tensor(np.ascontiguousarray(a, dtype=np.float64), device=dev)
     u, v = f64(case.u), f64(case.v)
     Vm = gal.sampleProfile(f64(case.I), case.Rmin, case.dR, case.N, case.dxy, u, v, case.inc,
@@ -433,7 +433,7 @@ def served_headline(gal, torch, np, dev, case, n_req, warm):
     Ib = [case.I * (1.0 + 0.05 * rng.standard_normal(case.I.size)) for _ in range(64)]
     mk = lambda k: Request("p2048", Ib[k % 64], case.Rmin, case.dR, case.N, case.dxy,
                            inc=case.inc, PA=case.PA, dRA=case.dRA, dDec=case.dDec)
-    srv = Server(ex, max_batch=16, max_inflight=4).start()
+    srv = Server(ex, max_batch=max_batch, max_inflight=4).start()
     for f in [srv.submit(mk(k)) for k in range(warm)]:
         f.result(timeout=120)
     srv.reset_stats()
@@ -448,7 +448,7 @@ def served_headline(gal, torch, np, dev, case, n_req, warm):
             "requests": st["completed"], "micro_batches": st["batches"],
             "host_launch_ms_per_batch": round(st["host_launch_ms_per_batch"], 3),
             "form": f"{n_req} chi2Profile requests (perturbed profiles) submitted at once to the "
-                    "continuous-batching loop (micro-batches of up to 16, 4 in flight), "
+                    f"continuous-batching loop (micro-batches of up to {max_batch}, 4 in flight), "
                     "2048^2, Nr=4096, M=1e6, FP64"}
 
 
@@ -711,9 +711,9 @@ def main():
     if not args.no_serve:
         served = serve_bench(gal, torch, np, dev, rates, sat_rates, args.serve_requests, 200, 0.5,
                              8, 2_000_000)
-        served["headline"] = served_headline(gal, torch, np, dev, case, 8000, 500)
-        served["headline"]["served_vs_plain"] = round(served["headline"]["value"] /
-                                                      (1e3 / ms_plain), 3)
+        for key, mb in (("headline", 64), ("headline_mb16", 16)):
+            served[key] = served_headline(gal, torch, np, dev, case, 8000, 500, mb)
+            served[key]["served_vs_plain"] = round(served[key]["value"] / (1e3 / ms_plain), 3)
 
     progress("chi2Image sections")
     images = None

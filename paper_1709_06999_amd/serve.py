@@ -29,6 +29,7 @@ HIP one.
 from __future__ import annotations
 
 import collections
+import heapq
 import itertools
 import threading
 import time
@@ -55,6 +56,7 @@ class Request:
     deadline: float | None = None  # absolute time.perf_counter() value
     arrival: float = field(default=0.0)
     future: Future | None = field(default=None, repr=False)
+    queued: bool = field(default=False, repr=False)   # waiting in the scheduler's queue
 
     def key(self):
         return (self.dataset, int(self.Nxy), float(self.dxy), int(np.size(self.I)), bool(self.grad))
@@ -83,6 +85,8 @@ class Server:
         self.mixed = bool(getattr(executor, "mixed_batches", False))
         self.idle_wait = idle_wait
         self._in = collections.deque()
+        self._deadlines = []         # heap of (deadline, seq, request) of queued requests
+        self._seq = itertools.count()
         self._lock = threading.Lock()
         self._wake = threading.Event()
         self._pending = collections.deque()
@@ -105,6 +109,7 @@ class Server:
     def submit(self, req: Request) -> Future:
         req.arrival = time.perf_counter()
         req.future = Future()
+        req.queued = True
         with self._lock:
             self._in.append(req)
         self._wake.set()
@@ -157,24 +162,24 @@ class Server:
         bind = getattr(self.ex, "bind_thread", None)
         if bind is not None:
             bind()
+        live = lambda r: r.queued and not r.future.cancelled()
         while self._run:
             progressed = False
             with self._lock:
                 while self._in:
-                    self._pending.append(self._in.popleft())
+                    r = self._in.popleft()
+                    self._pending.append(r)
+                    if r.deadline is not None:
+                        heapq.heappush(self._deadlines, (r.deadline, next(self._seq), r))
             now = time.perf_counter()
-            # drop cancelled / expired requests before they take device memory
-            if self._pending:
-                keep = collections.deque()
-                for r in self._pending:
-                    if r.future.cancelled():
-                        continue
-                    if r.deadline is not None and now > r.deadline:
-                        _settle(r.future, exc=TimeoutError("deadline passed while queued"))
-                        self.expired += 1
-                        continue
-                    keep.append(r)
-                self._pending = keep
+            # queued requests whose deadline passed fail before they take device
+            # memory (a heap of deadlines: no pass over the whole queue)
+            while self._deadlines and self._deadlines[0][0] < now:
+                r = heapq.heappop(self._deadlines)[2]
+                if live(r):
+                    r.queued = False
+                    _settle(r.future, exc=TimeoutError("deadline passed while queued"))
+                    self.expired += 1
             # retire finished micro-batches
             still = []
             for item in self._inflight:
@@ -194,22 +199,28 @@ class Server:
                     still.append(item)
             self._inflight = still
             # admit new micro-batches while slots and memory allow
-            while self._pending and self._free_slots:
+            while self._free_slots:
+                while self._pending and not live(self._pending[0]):
+                    self._pending.popleft().queued = False   # cancelled or expired
+                if not self._pending:
+                    break
                 head = self._pending[0]
                 if self.mixed:
-                    group = list(itertools.islice(self._pending, self.max_batch))
+                    group = list(itertools.islice((r for r in self._pending if live(r)),
+                                                  self.max_batch))
                 else:
                     key = head.key()
-                    group = [r for r in self._pending if r.key() == key][: self.max_batch]
+                    group = list(itertools.islice(
+                        (r for r in self._pending if live(r) and r.key() == key), self.max_batch))
                 try:
                     fp_one = self.ex.footprint([head])
                 except Exception as e:  # a request the executor cannot plan
-                    self._pending.popleft()
+                    self._pending.popleft().queued = False
                     _settle(head.future, exc=e)
                     self.rejected += 1
                     continue
                 if fp_one > self.budget:
-                    self._pending.popleft()
+                    self._pending.popleft().queued = False
                     _settle(head.future, exc=MemoryError(
                         f"request needs {fp_one} bytes of device memory, budget {self.budget}"))
                     self.rejected += 1
@@ -225,8 +236,13 @@ class Server:
                     group.pop()
                 if not group:
                     break              # wait for memory to free up
-                ids = set(id(r) for r in group)
-                self._pending = collections.deque(r for r in self._pending if id(r) not in ids)
+                for r in group:
+                    r.queued = False
+                if self.mixed:         # the group was the queue's head
+                    while self._pending and not self._pending[0].queued:
+                        self._pending.popleft()
+                else:
+                    self._pending = collections.deque(r for r in self._pending if r.queued)
                 slot = self._free_slots.pop()
                 t0 = time.perf_counter()
                 try:
@@ -254,32 +270,67 @@ def _al(n: int) -> int:
 
 
 class _Slot:
-    """Pinned host staging of one in-flight slot (models, geometry rows, chi^2
-    and gradient outputs), grown on demand.  Host memory only: the device
-    buffers of a micro-batch are allocated per launch (see GpuExecutor)."""
+    """Pinned host staging of one in-flight slot, grown on demand: ``h_in``
+    holds the models and geometry rows laid out as in the device buffer,
+    ``h_out`` the chi^2 values and gradients, so that each direction is one
+    copy.  Host memory only: the device buffer of a micro-batch is allocated
+    per launch (see GpuExecutor)."""
 
-    def __init__(self, torch, dtype):
-        self.torch, self.dtype = torch, dtype
-        self.cap = (0, 0, 0)
+    def __init__(self, torch):
+        self.torch = torch
+        self.cap = (0, 0)
 
-    def grow(self, K, n_model, n_grad):
+    def grow(self, n_in, n_out):
         torch = self.torch
-        if K <= self.cap[0] and n_model <= self.cap[1] and n_grad <= self.cap[2]:
+        if n_in <= self.cap[0] and n_out <= self.cap[1]:
             return
-        K = max(K, self.cap[0])
-        n_model = max(n_model, self.cap[1], 1)
-        n_grad = max(n_grad, self.cap[2], 1)
-        pin = dict(pin_memory=True)
-        self.h_model = torch.empty(n_model, dtype=self.dtype, **pin)
-        self.h_geo = torch.empty((K, 6), dtype=torch.float64, **pin)
-        self.h_chi2 = torch.empty(K, dtype=torch.float64, **pin)
-        self.h_grad = torch.empty(n_grad, dtype=self.dtype, **pin)
-        self.cap = (K, n_model, n_grad)
+        n_in, n_out = max(n_in, self.cap[0], 256), max(n_out, self.cap[1], 256)
+        self.h_in = torch.empty(n_in, dtype=torch.uint8, pin_memory=True)
+        self.h_out = torch.empty(n_out, dtype=torch.uint8, pin_memory=True)
+        self.in_np, self.out_np = self.h_in.numpy(), self.h_out.numpy()
+        self.cap = (n_in, n_out)
+
+
+class _Layout:
+    """Byte layout of one micro-batch's device buffer for a request signature:
+    [batch_exec workspace | models | geometry rows | chi^2 | gradients], the
+    workspace size being the library planner's own figure for the call."""
+
+    def __init__(self, ex, sig):
+        from . import JOB_PROFILE
+
+        K = len(sig)
+        nr = np.array([s[3] for s in sig], dtype=np.int64)
+        grad = np.array([s[4] for s in sig], dtype=bool)
+        specs = [(ex.datasets[s[0]], JOB_PROFILE, s[1], s[2], s[3], s[4]) for s in sig]
+        self.K, self.el = K, ex.el
+        self.ws = _al(ex._ws_bytes(specs))
+        self.mo = np.concatenate([[0], np.cumsum(nr)]).astype(np.int64)   # model offsets
+        n_model = int(self.mo[-1])
+        gof = np.concatenate([[0], np.cumsum(np.where(grad, nr, 0))]).astype(np.int64)
+        self.n_grad = int(gof[-1])
+        self.goff = np.where(grad, gof[:-1], -1)                           # gradient offsets
+        self.nr, self.grad = nr, grad
+        self.o_model = self.ws
+        self.o_geo = self.o_model + _al(self.el * n_model)
+        self.o_chi2 = self.o_geo + _al(48 * K)
+        self.o_grad = self.o_chi2 + _al(8 * K)
+        self.total = self.o_grad + _al(self.el * max(self.n_grad, 1))
+        # the gal_job table: everything but the device addresses, filled per launch
+        self.jobs = np.zeros(K, dtype=ex._job_dtype)
+        self.jobs["ds"] = [ex.datasets[s[0]]._h.value for s in sig]
+        self.jobs["kind"] = JOB_PROFILE
+        self.jobs["Nxy"] = [s[1] for s in sig]
+        self.jobs["dxy"] = [s[2] for s in sig]
+        self.jobs["Nr"] = nr
+        self.rel_model = self.o_model + self.el * self.mo[:-1]
+        self.rel_geo = self.o_geo + 48 * np.arange(K, dtype=np.int64)
+        self.rel_grad = np.where(grad, self.o_grad + self.el * np.maximum(self.goff, 0), 0)
 
 
 class GpuExecutor:
     """HIP executor: datasets resident in HBM, one stream and pinned staging
-    per in-flight slot, one batch_exec call per micro-batch (any mix of
+    per in-flight slot, one gal_batch_exec call per micro-batch (any mix of
     requests, gradients included).
 
     Device memory: each micro-batch gets one buffer of exactly
@@ -287,26 +338,47 @@ class GpuExecutor:
     planner computes for its job list, then the models, geometry rows, chi^2
     and gradient outputs -- taken on the slot's stream when it is launched and
     released when its results are collected.  The scheduler's count of bytes
-    in flight is therefore the device memory the micro-batches hold."""
+    in flight is therefore the device memory the micro-batches hold.
+
+    Host cost per micro-batch: the layout of a request signature (datasets,
+    grids, profile lengths, gradient flags) is planned once and cached; a
+    launch fills one pinned staging buffer, makes one copy to the device, one
+    library call with a job table built from the cached layout, and one copy
+    back.  The workspace's status word is not read here (a request whose
+    geometry fails the device checks gets a NaN chi^2)."""
 
     mixed_batches = True
 
-    def __init__(self, device=None, dtype=None, max_batch: int = 16, max_inflight: int = 4):
+    def __init__(self, device=None, dtype=None, max_batch: int = 16, max_inflight: int = 4,
+                 layout_cache: int = 4096):
+        import ctypes
+
         import torch
 
-        from . import JOB_PROFILE, Dataset, Workspace, batch_exec, exec_workspace_bytes
+        from . import Dataset, _lib, _native, exec_workspace_bytes
 
         self.torch = torch
-        self._Dataset, self._batch_exec, self._JOB_PROFILE = Dataset, batch_exec, JOB_PROFILE
-        self._Workspace, self._ws_bytes = Workspace, exec_workspace_bytes
+        self._Dataset, self._ws_bytes = Dataset, exec_workspace_bytes
+        self._lib, self._check = _lib, _native.check
         self.device = torch.device("cuda", torch.cuda.current_device()) if device is None \
             else torch.device(device)
         self.dtype = torch.float64 if dtype is None else dtype
+        self.np_dtype = np.float64 if self.dtype == torch.float64 else np.float32
         self.el = 8 if self.dtype == torch.float64 else 4
         self.max_batch = max_batch
         self.streams = [torch.cuda.Stream(device=self.device) for _ in range(max_inflight)]
-        self.slots = [_Slot(torch, self.dtype) for _ in range(max_inflight)]
+        self.slots = [_Slot(torch) for _ in range(max_inflight)]
         self.datasets = {}
+        self._layouts = collections.OrderedDict()
+        self._layout_cap = int(layout_cache)
+        G = _native.GalJob
+        names = [f[0] for f in G._fields_]
+        fmt = {"ds": np.uint64, "model": np.uint64, "geo": np.uint64, "vis": np.uint64,
+               "dxy": np.float64}
+        self._job_dtype = np.dtype({"names": names,
+                                    "formats": [fmt.get(n, np.int32) for n in names],
+                                    "offsets": [getattr(G, n).offset for n in names],
+                                    "itemsize": ctypes.sizeof(G)})
 
     def default_budget(self) -> int:
         free, total = self.torch.cuda.mem_get_info(self.device)
@@ -319,84 +391,64 @@ class GpuExecutor:
         t = lambda a: self.torch.as_tensor(np.ascontiguousarray(a), dtype=self.dtype,
                                            device=self.device)
         self.datasets[name] = self._Dataset(t(u), t(v), t(re), t(im), t(w))
+        self._layouts.clear()
         return self.datasets[name]
 
-    def layout(self, reqs):
-        """Byte offsets of the parts of a micro-batch's device buffer:
-        (workspace bytes, model offset, geo offset, chi2 offset, grad offset,
-        total).  The workspace size is the planner's own figure for the
-        batch_exec call the launch makes."""
-        nr = [int(np.size(r.I)) for r in reqs]
-        specs = [(self.datasets[r.dataset], self._JOB_PROFILE, int(r.Nxy), float(r.dxy), n,
-                  bool(r.grad)) for r, n in zip(reqs, nr)]
-        ws = _al(self._ws_bytes(specs))
-        K, n_model = len(reqs), sum(nr)
-        n_grad = sum(n for n, r in zip(nr, reqs) if r.grad)
-        o_model = ws
-        o_geo = o_model + _al(self.el * n_model)
-        o_chi2 = o_geo + _al(48 * K)
-        o_grad = o_chi2 + _al(8 * K)
-        total = o_grad + _al(self.el * max(n_grad, 1))
-        return ws, o_model, o_geo, o_chi2, o_grad, total
+    def layout(self, reqs) -> _Layout:
+        """The micro-batch's buffer layout (cached per request signature)."""
+        sig = tuple(r.key() for r in reqs)
+        L = self._layouts.get(sig)
+        if L is None:
+            L = _Layout(self, sig)
+            self._layouts[sig] = L
+            if len(self._layouts) > self._layout_cap:
+                self._layouts.popitem(last=False)
+        return L
 
     def footprint(self, reqs) -> int:
         """Device bytes a micro-batch holds while in flight (exact)."""
-        return self.layout(reqs)[-1]
+        return self.layout(reqs).total
 
     def launch(self, reqs, slot):
         torch = self.torch
         st, S = self.streams[slot], self.slots[slot]
-        K = len(reqs)
-        nr = [int(np.size(r.I)) for r in reqs]
-        mo = np.concatenate([[0], np.cumsum(nr)]).astype(np.int64)
-        n_grad = sum(n for n, r in zip(nr, reqs) if r.grad)
-        S.grow(K, int(mo[-1]), n_grad)
-        hm, hg = S.h_model.numpy(), S.h_geo.numpy()
-        for k, r in enumerate(reqs):
-            I = r.I.detach().cpu().numpy() if torch.is_tensor(r.I) else np.asarray(r.I)
-            hm[mo[k]:mo[k + 1]] = I
-            hg[k] = (r.Rmin, r.dR, r.inc, r.PA, r.dRA, r.dDec)
-        ws_b, o_model, o_geo, o_chi2, o_grad, total = self.layout(reqs)
+        L = self.layout(reqs)
+        n_in, n_out = L.o_chi2 - L.o_model, L.total - L.o_chi2
+        S.grow(n_in, n_out)
+        hm = S.in_np[: L.el * int(L.mo[-1])].view(self.np_dtype)
+        hg = S.in_np[L.o_geo - L.o_model: L.o_geo - L.o_model + 48 * L.K].view(np.float64)
+        hg = hg.reshape(L.K, 6)
+        models = [r.I.detach().cpu().numpy() if torch.is_tensor(r.I) else r.I for r in reqs]
+        np.concatenate(models, out=hm, casting="same_kind")
+        hg[:] = [(r.Rmin, r.dR, r.inc, r.PA, r.dRA, r.dDec) for r in reqs]
         with torch.cuda.stream(st):
-            buf = torch.empty(total, dtype=torch.uint8, device=self.device)
-            view = lambda o, n, dt: buf[o:o + n * (8 if dt == torch.float64 else 4)].view(dt)
-            d_model = view(o_model, int(mo[-1]), self.dtype)
-            d_geo = view(o_geo, 6 * K, torch.float64).view(K, 6)
-            d_chi2 = view(o_chi2, K, torch.float64)
-            d_grad = view(o_grad, max(n_grad, 1), self.dtype)
-            ws = self._Workspace(self.device, torch.float64)
-            ws.buf = buf[:ws_b]
-            ws.buf[:256].zero_()   # the control block (status flag)
-            jobs, grads, goff = [], [], []
-            g0 = 0
-            for k, r in enumerate(reqs):
-                jobs.append({"ds": self.datasets[r.dataset], "kind": self._JOB_PROFILE,
-                             "Nxy": int(r.Nxy), "dxy": float(r.dxy),
-                             "model": d_model[mo[k]:mo[k + 1]], "geo": d_geo[k]})
-                if r.grad:
-                    grads.append(d_grad[g0:g0 + nr[k]])
-                    goff.append(g0)
-                    g0 += nr[k]
-                else:
-                    grads.append(None)
-                    goff.append(-1)
-            d_model.copy_(S.h_model[:mo[-1]], non_blocking=True)
-            d_geo.copy_(S.h_geo[:K], non_blocking=True)
-            self._batch_exec(jobs, grads if n_grad else None, out=d_chi2, ws=ws)
-            S.h_chi2[:K].copy_(d_chi2, non_blocking=True)
-            if n_grad:
-                S.h_grad[:n_grad].copy_(d_grad[:n_grad], non_blocking=True)
+            buf = torch.empty(L.total, dtype=torch.uint8, device=self.device)
+            buf[L.o_model:L.o_chi2].copy_(S.h_in[:n_in], non_blocking=True)
+            base = buf.data_ptr()
+            jobs = L.jobs.copy()
+            jobs["model"] = base + L.rel_model
+            jobs["geo"] = base + L.rel_geo
+            grads = None
+            if L.n_grad:
+                grads = np.where(L.grad, base + L.rel_grad, 0).astype(np.uint64)
+            self._check(self._lib().gal_batch_exec(
+                jobs.ctypes.data, L.K, base + L.o_chi2,
+                None if grads is None else grads.ctypes.data, base, L.ws,
+                st.cuda_stream), "serve launch")
+            S.h_out[:n_out].copy_(buf[L.o_chi2:L.total], non_blocking=True)
             ev = torch.cuda.Event()
             ev.record(st)
-        return [ev, S, nr, goff, buf]
+        return [ev, S, L, buf]
 
     def done(self, handle) -> bool:
         return handle[0].query()
 
     def collect(self, handle):
-        ev, S, nr, goff = handle[:4]
+        ev, S, L = handle[:3]
         ev.synchronize()
-        handle[4] = None   # the micro-batch's device buffer goes back to the allocator
-        c, g = S.h_chi2.numpy(), S.h_grad.numpy()
-        return [(float(c[k]), None if goff[k] < 0 else g[goff[k]:goff[k] + nr[k]].copy())
-                for k in range(len(nr))]
+        handle[3] = None   # the micro-batch's device buffer goes back to the allocator
+        c = S.out_np[: 8 * L.K].view(np.float64)
+        g0 = L.o_grad - L.o_chi2
+        g = S.out_np[g0: g0 + L.el * max(L.n_grad, 1)].view(self.np_dtype)
+        return [(float(c[k]), None if L.goff[k] < 0 else g[L.goff[k]:L.goff[k] + L.nr[k]].copy())
+                for k in range(L.K)]

@@ -173,6 +173,6 @@ def test_footprint_is_the_device_memory_a_micro_batch_holds():
         assert fp >= need_ws + staging, (fp, need_ws, staging)
         assert fp <= need_ws + staging + 5 * 256
         h = ex.launch(reqs, 0)
-        assert h[4].numel() == fp        # the launch holds exactly the footprint
+        assert h[3].numel() == fp        # the launch holds exactly the footprint
         out = ex.collect(h)
         assert len(out) == len(reqs) and all(np.isfinite(c) for c, _ in out)
