@@ -86,6 +86,7 @@ struct SGroup {          // scenes sharing one pass over a dataset
     const int32_t *perm;              // stored point -> registration index
     int64_t M;
     int blk0, nblk;      // flattened block range of the group
+    int nchunk, cpb;     // chunks of SAMPLE_NT * SAMPLE_PPT points; chunks per block
     int job_off, nj;     // lists[job_off + m]: job indices, scene members adjacent
     int sc_off, nsc;     // lists[sc_off + s]: first member of scene s; [sc_off + nsc] = nj
 };
@@ -301,12 +302,16 @@ __device__ __forceinline__ void job_scatter(const JobDesc &J, const BlockPoints<
 // visibility output).  Block -> group by binary search over the groups' first
 // blocks (after the XCD remap); each thread keeps SAMPLE_PPT points in
 // registers and evaluates every job of the group.  GRAD: jobs with a gradient
-// output also scatter their residuals.
-template <typename T, bool REAL, bool GRAD>
+// output also scatter their residuals.  MULTI: a block takes cpb consecutive
+// chunks of its group (groups of few jobs, where one chunk is too little
+// work to cover the block's set-up and memory latency), loading the next
+// chunk's observations while it evaluates the current one.
+template <typename T, bool REAL, bool GRAD, bool MULTI = false>
 __global__ __launch_bounds__(SAMPLE_NT) void kb_sample_chi2(const JobDesc *__restrict__ jobs,
                                                             const SGroup *__restrict__ groups,
                                                             const int *__restrict__ lists,
                                                             int ngroups, char *ws) {
+    static_assert(!(GRAD && MULTI), "one chunk per block with gradients");
     constexpr int PPT = SAMPLE_PPT;
     constexpr int NV = REAL ? 1 : 2;
     __shared__ double tile[GRAD ? SCAT_TILE : 1];
@@ -321,91 +326,112 @@ __global__ __launch_bounds__(SAMPLE_NT) void kb_sample_chi2(const JobDesc *__res
         else hi = mid - 1;
     }
     const SGroup &G = groups[lo];
-    const int chunk = bid - G.blk0;
+    const int c0 = MULTI ? (bid - G.blk0) * G.cpb : bid - G.blk0;
+    const int c1 = MULTI ? min(c0 + G.cpb, G.nchunk) : c0 + 1;
     // chi^2 only: points strided by the block size (each load instruction
     // reads one contiguous run); with gradients: SAMPLE_PPT consecutive
     // points per thread, neighbours in the locality order of datasets, whose
     // equal stencils block_scatter folds in registers before the LDS atomics
     constexpr int64_t PSTEP = GRAD ? 1 : SAMPLE_NT;
-    const int64_t base = (int64_t)chunk * (SAMPLE_NT * PPT) + threadIdx.x * (GRAD ? PPT : 1);
     const gptr<T> u = as_global<T>(G.u), v = as_global<T>(G.v);
     const gptr<T> re = as_global<T>(G.re), im = as_global<T>(G.im), w = as_global<T>(G.w);
-    double uu[PPT], vv[PPT], rr[PPT], ii[PPT], ww[PPT];
-#pragma unroll
-    for (int p = 0; p < PPT; ++p) {
-        const int64_t k = base + p * PSTEP;
-        const bool in = k < G.M;
-        uu[p] = in ? (double)u[k] : 0.0;
-        vv[p] = in ? (double)v[k] : 0.0;
-        rr[p] = in ? (double)re[k] : 0.0;
-        ii[p] = in ? (double)im[k] : 0.0;
-        ww[p] = in ? (double)w[k] : 0.0;  // points past M weigh nothing
-    }
-    Control *ctl = (Control *)ws;
-    bool bad = false;
-    for (int jj = 0; jj < G.nj; ++jj) {
-        const JobDesc &J = jobs[lists[G.job_off + jj]];
-        const SampleArgs a = sample_from_job(J, G.M);
-        const Geom g = geom_of(J);
-        double acc = 0.0;
-        PointAdd<NV> pa[PPT];
+    auto first = [&](int chunk) {
+        return (int64_t)chunk * (SAMPLE_NT * PPT) + threadIdx.x * (GRAD ? PPT : 1);
+    };
+    // the observations of a chunk as stored (points past M: 0, weight 0)
+    T su[PPT], sv[PPT], sr[PPT], si[PPT], sw[PPT];
+    auto fetch = [&](int chunk) {
+        const int64_t b = first(chunk);
 #pragma unroll
         for (int p = 0; p < PPT; ++p) {
-            const bool in = base + p * PSTEP < G.M;
-            pa[p].q = -1;
-            // exp(i theta), theta = 2 pi (u dRA + v dDec)
-            double sn, cs;
-            phase_of(a, uu[p], vv[p], sn, cs);
-            double Vre, Vim;
-            bool ok;
-            // an off-grid stencil points at valid nodes; its value is discarded
-            if constexpr (REAL) {
-                const T *S = (const T *)(ws + J.spec_off);
-                const StencilE<T> st = locate_e<T>(S, g, a, uu[p], vv[p]);
-                ok = st.ok;
-                double x0, x1, y0, y1;
-                nodes_e<T>(S, st, g.CS, x0, x1, y0, y1);
-                double b = bilerp(x0, y0, x1, y1, st.s, st.t);  // cos(inc) = 1 on real spectra
-                b = ok ? b : __builtin_nan("");
-                Vre = b * cs;
-                Vim = b * sn;
-                if (GRAD && J.grad && in && ok) {
-                    // Re(conj(R) e^{i theta}) on the real spectrum
-                    const double R0 = rr[p] - Vre, R1 = ii[p] - Vim;
-                    pa[p] = point_add_real<T>(st, ww[p] * (R0 * cs + R1 * sn));
-                }
-            } else {
-                const c2<T> *S = (const c2<T> *)(ws + J.spec_off);
-                const Stencil<T> st = locate<T>(S, g, a, uu[p], vv[p]);
-                ok = st.ok;
-                const c2<T> n00 = st.c0[0], n10 = st.c0[1], n01 = st.c0[g.CS], n11 = st.c0[g.CS + 1];
-                const double s = st.s, t = st.t;
-                const double w00 = (1.0 - t) * (1.0 - s), w01 = (1.0 - t) * s;
-                const double w10 = t * (1.0 - s), w11 = t * s;
-                double br = w00 * (double)n00.x + w01 * (double)n01.x + w10 * (double)n10.x +
-                            w11 * (double)n11.x;
-                double bi = w00 * (double)n00.y + w01 * (double)n01.y + w10 * (double)n10.y +
-                            w11 * (double)n11.y;
-                if (st.mirror) bi = -bi;
-                br *= a.cinc;
-                bi *= a.cinc;
-                Vre = ok ? br * cs - bi * sn : __builtin_nan("");
-                Vim = ok ? br * sn + bi * cs : __builtin_nan("");
-                if (GRAD && J.grad && in && ok)
-                    pa[p] = point_add_cplx<T>(st, ww[p] * a.cinc, rr[p] - Vre, ii[p] - Vim, sn, cs);
-            }
-            bad |= in && !ok;
-            // no branch on `in`: a point past M has w = 0 and a valid stencil
-            // at u = v = 0 (finite V), so it adds 0, and the four points'
-            // gathers can be in flight together
-            const double dr = Vre - rr[p], di = Vim - ii[p];
-            acc += ww[p] * (dr * dr + di * di);
+            const int64_t k = b + p * PSTEP;
+            const bool in = k < G.M;
+            su[p] = in ? u[k] : T(0);
+            sv[p] = in ? v[k] : T(0);
+            sr[p] = in ? re[k] : T(0);
+            si[p] = in ? im[k] : T(0);
+            sw[p] = in ? w[k] : T(0);  // points past M weigh nothing
         }
-        if (GRAD && J.grad) block_scatter<T, NV, PPT>((T *)(ws + J.a_off), g.CS, pa, tile, box);
-        // one partial per wave (no barrier between chi^2-only jobs); kb_reduce adds them
-        const double wsum = wave_sum_permute(acc);
-        if ((threadIdx.x & 63) == 0)
-            ((double *)(ws + J.part_off))[chunk * WAVES + (threadIdx.x >> 6)] = wsum;
+    };
+    fetch(c0);
+    Control *ctl = (Control *)ws;
+    bool bad = false;
+    for (int chunk = c0; chunk < c1; ++chunk) {
+        const int64_t base = first(chunk);
+        double uu[PPT], vv[PPT], rr[PPT], ii[PPT], ww[PPT];
+#pragma unroll
+        for (int p = 0; p < PPT; ++p) {
+            uu[p] = (double)su[p];
+            vv[p] = (double)sv[p];
+            rr[p] = (double)sr[p];
+            ii[p] = (double)si[p];
+            ww[p] = (double)sw[p];
+        }
+        if (MULTI && chunk + 1 < c1) fetch(chunk + 1);  // in flight during this chunk's jobs
+        for (int jj = 0; jj < G.nj; ++jj) {
+            const JobDesc &J = jobs[lists[G.job_off + jj]];
+            const SampleArgs a = sample_from_job(J, G.M);
+            const Geom g = geom_of(J);
+            double acc = 0.0;
+            PointAdd<NV> pa[PPT];
+#pragma unroll
+            for (int p = 0; p < PPT; ++p) {
+                const bool in = base + p * PSTEP < G.M;
+                pa[p].q = -1;
+                // exp(i theta), theta = 2 pi (u dRA + v dDec)
+                double sn, cs;
+                phase_of(a, uu[p], vv[p], sn, cs);
+                double Vre, Vim;
+                bool ok;
+                // an off-grid stencil points at valid nodes; its value is discarded
+                if constexpr (REAL) {
+                    const T *S = (const T *)(ws + J.spec_off);
+                    const StencilE<T> st = locate_e<T>(S, g, a, uu[p], vv[p]);
+                    ok = st.ok;
+                    double x0, x1, y0, y1;
+                    nodes_e<T>(S, st, g.CS, x0, x1, y0, y1);
+                    double b = bilerp(x0, y0, x1, y1, st.s, st.t);  // cos(inc) = 1 on real spectra
+                    b = ok ? b : __builtin_nan("");
+                    Vre = b * cs;
+                    Vim = b * sn;
+                    if (GRAD && J.grad && in && ok) {
+                        // Re(conj(R) e^{i theta}) on the real spectrum
+                        const double R0 = rr[p] - Vre, R1 = ii[p] - Vim;
+                        pa[p] = point_add_real<T>(st, ww[p] * (R0 * cs + R1 * sn));
+                    }
+                } else {
+                    const c2<T> *S = (const c2<T> *)(ws + J.spec_off);
+                    const Stencil<T> st = locate<T>(S, g, a, uu[p], vv[p]);
+                    ok = st.ok;
+                    const c2<T> n00 = st.c0[0], n10 = st.c0[1], n01 = st.c0[g.CS], n11 = st.c0[g.CS + 1];
+                    const double s = st.s, t = st.t;
+                    const double w00 = (1.0 - t) * (1.0 - s), w01 = (1.0 - t) * s;
+                    const double w10 = t * (1.0 - s), w11 = t * s;
+                    double br = w00 * (double)n00.x + w01 * (double)n01.x + w10 * (double)n10.x +
+                                w11 * (double)n11.x;
+                    double bi = w00 * (double)n00.y + w01 * (double)n01.y + w10 * (double)n10.y +
+                                w11 * (double)n11.y;
+                    if (st.mirror) bi = -bi;
+                    br *= a.cinc;
+                    bi *= a.cinc;
+                    Vre = ok ? br * cs - bi * sn : __builtin_nan("");
+                    Vim = ok ? br * sn + bi * cs : __builtin_nan("");
+                    if (GRAD && J.grad && in && ok)
+                        pa[p] = point_add_cplx<T>(st, ww[p] * a.cinc, rr[p] - Vre, ii[p] - Vim, sn, cs);
+                }
+                bad |= in && !ok;
+                // no branch on `in`: a point past M has w = 0 and a valid stencil
+                // at u = v = 0 (finite V), so it adds 0, and the four points'
+                // gathers can be in flight together
+                const double dr = Vre - rr[p], di = Vim - ii[p];
+                acc += ww[p] * (dr * dr + di * di);
+            }
+            if (GRAD && J.grad) block_scatter<T, NV, PPT>((T *)(ws + J.a_off), g.CS, pa, tile, box);
+            // one partial per wave (no barrier between chi^2-only jobs); kb_reduce adds them
+            const double wsum = wave_sum_permute(acc);
+            if ((threadIdx.x & 63) == 0)
+                ((double *)(ws + J.part_off))[chunk * WAVES + (threadIdx.x >> 6)] = wsum;
+        }
     }
     if (bad) atomicOr(&ctl->flag, STATUS_UV);
 }
@@ -543,7 +569,7 @@ __global__ __launch_bounds__(REDUCE_NT) void kb_reduce(const JobDesc *__restrict
     __syncthreads();
     for (int k = threadIdx.x; k < njobs; k += REDUCE_NT)
         if (jobs[k].bad && jobs[k].part_off == J.part_off) any_bad = 1;
-    const int n = groups[job_group[j]].nblk * WAVES;
+    const int n = groups[job_group[j]].nchunk * WAVES;
     const double tot = block_sum(strided_sum((const double *)(ws + J.part_off), n), red);
     if (threadIdx.x == 0) chi2[j] = any_bad ? __builtin_nan("") : tot;
 }

@@ -1060,6 +1060,7 @@ struct BatchPlan {
         int prec;
         int kc;                     // kinds: 0 images, 1 profiles, 2 both; + 3: scenes
         int group_off, count, blocks;
+        bool multi;                 // some group takes several chunks per block
     };
     std::vector<SClass> sclasses;
     size_t table_bytes = 0;         // jobs | groups | lists | job_group
@@ -1962,9 +1963,15 @@ static int plan_batch(const gal_job *jobs, int n, void *const *grads, size_t bas
         G.w = ds->w;
         G.perm = ds->perm;
         G.M = ds->M;
-        G.nblk = (int)sample_blocks(G.M);
+        G.nchunk = (int)sample_blocks(G.M);
         G.job_off = (int)P.lists.size();
         G.nj = D.nj;
+        // plain groups of few jobs take several chunks per block (one chunk
+        // of one job is too little work to cover a block's set-up and memory
+        // latency); scene groups and gradient runs one
+        const bool scene = cls(D) % 6 >= 3;
+        G.cpb = (P.grads || scene) ? 1 : (G.nj <= 2 ? 4 : (G.nj <= 4 ? 2 : 1));
+        G.nblk = (G.nchunk + G.cpb - 1) / G.cpb;
         for (int u : D.units)
             for (int i : units[u]) {
                 P.job_group[i] = (int)P.groups.size();
@@ -1982,11 +1989,12 @@ static int plan_batch(const gal_job *jobs, int n, void *const *grads, size_t bas
         const int prec = c < 6 ? 8 : 4;
         const int kc = c % 6;
         if (P.sclasses.empty() || P.sclasses.back().prec != prec || P.sclasses.back().kc != kc)
-            P.sclasses.push_back({prec, kc, (int)P.groups.size(), 0, 0});
+            P.sclasses.push_back({prec, kc, (int)P.groups.size(), 0, 0, false});
         BatchPlan::SClass &sc = P.sclasses.back();
         G.blk0 = sc.blocks;
         sc.blocks += G.nblk;
         sc.count += 1;
+        sc.multi = sc.multi || G.cpb > 1;
         P.groups.push_back(G);
     }
     auto make_groups = [&](bool grad_only, std::vector<BatchPlan::FGroup> &out) {
@@ -2018,7 +2026,7 @@ static int plan_batch(const gal_job *jobs, int n, void *const *grads, size_t bas
     size_t off = base;
     for (const auto &u : units) {
         P.jobs[u[0]].part_off = off;
-        off += align256((size_t)P.groups[P.job_group[u[0]]].nblk * WAVES * sizeof(double));
+        off += align256((size_t)P.groups[P.job_group[u[0]]].nchunk * WAVES * sizeof(double));
         for (int i : u) P.jobs[i].part_off = P.jobs[u[0]].part_off;
     }
     auto spec_bytes = [&](int i) {
@@ -2159,6 +2167,9 @@ static int batch_sample(const BatchPlan::SClass &c, bool grads, const BatchTable
     const char *name = REAL ? "kb_sample_sym_chi2" : "kb_sample_chi2";
     if (grads)
         return launch(name, kb_sample_chi2<T, REAL, true>, grid, blk, s, t.jobs, g, t.lists, c.count, ws);
+    if (c.multi)
+        return launch(name, kb_sample_chi2<T, REAL, false, true>, grid, blk, s, t.jobs, g, t.lists,
+                      c.count, ws);
     return launch(name, kb_sample_chi2<T, REAL, false>, grid, blk, s, t.jobs, g, t.lists, c.count, ws);
 }
 
