@@ -457,7 +457,8 @@ def main():
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=400, help="timed batched steps")
     ap.add_argument("--warmup", type=int, default=20)
-    ap.add_argument("--batch", type=int, default=16, help="models per batched step")
+    ap.add_argument("--batch", type=int, default=64,
+                    help="models (walkers) per batched step; 16 is also measured")
     ap.add_argument("--plain-steps", type=int, default=2000)
     ap.add_argument("--latency-samples", type=int, default=300)
     ap.add_argument("--grad-steps", type=int, default=300, help="timed plain gradient calls")
@@ -601,41 +602,60 @@ def main():
 
     progress("batched walkers (headline)")
     # ---- batched: K walkers (different profiles and geometry) per step ----
-    K = args.batch
-    rng = np.random.default_rng(1102)
-    Ib = f64(np.stack([case.I * (1.0 + 0.05 * rng.standard_normal(Nr)) for _ in range(K)]))
-    geob = f64(np.array([[case.Rmin, case.dR, case.inc + 0.05 * rng.standard_normal(),
-                          case.PA + 0.05 * rng.standard_normal(),
-                          0.1 * case.dxy * rng.standard_normal(),
-                          0.1 * case.dxy * rng.standard_normal()] for _ in range(K)]))
-    batch = gal.profile_batch(ds, Ib, geob, N, case.dxy)
-    batch_tune_ms = {}
     tuned_plain = list(tuned)
-    if args.fft_variants_batch:
-        tuned = [int(x) for x in args.fft_variants_batch.split(",")]
-        gal.tune_set(N, tuned, torch.float64)
-    elif not args.fft_variants:
-        tuned = gal.autotune_batch(batch, N, torch.float64, times=batch_tune_ms)
-    step = batch.chi2
-    graph = None
-    if not args.no_graph:
-        side = torch.cuda.Stream(device=dev)
-        side.wait_stream(torch.cuda.current_stream(dev))
-        with torch.cuda.stream(side):
-            batch.chi2()                      # warm-up outside the capture
-        torch.cuda.current_stream(dev).wait_stream(side)
+
+    def walkers(K):
+        """A step of K walkers replayed from a HIP graph: (batch, models, ms per
+        step, per-kernel times, replay matches eager, FFT variants, tuning times)."""
+        rng = np.random.default_rng(1102)
+        Ib = f64(np.stack([case.I * (1.0 + 0.05 * rng.standard_normal(Nr)) for _ in range(K)]))
+        geob = f64(np.array([[case.Rmin, case.dR, case.inc + 0.05 * rng.standard_normal(),
+                              case.PA + 0.05 * rng.standard_normal(),
+                              0.1 * case.dxy * rng.standard_normal(),
+                              0.1 * case.dxy * rng.standard_normal()] for _ in range(K)]))
+        batch = gal.profile_batch(ds, Ib, geob, N, case.dxy)
+        tune_ms = {}
+        if args.fft_variants_batch:
+            tv = [int(x) for x in args.fft_variants_batch.split(",")]
+            gal.tune_set(N, tv, torch.float64)
+        elif not args.fft_variants:
+            tv = gal.autotune_batch(batch, N, torch.float64, times=tune_ms)
+        else:
+            tv = list(tuned)
+        step = batch.chi2
+        if not args.no_graph:
+            side = torch.cuda.Stream(device=dev)
+            side.wait_stream(torch.cuda.current_stream(dev))
+            with torch.cuda.stream(side):
+                batch.chi2()                      # warm-up outside the capture
+            torch.cuda.current_stream(dev).wait_stream(side)
+            torch.cuda.synchronize()
+            graph = torch.cuda.CUDAGraph()
+            with torch.cuda.graph(graph):
+                batch.chi2()
+            step = graph.replay
+        ms = _timed(step, args.steps, args.warmup, torch)
+        # every replay matches an eager execution
+        replayed = batch.out.clone()
+        eager = batch.chi2().clone()
         torch.cuda.synchronize()
-        graph = torch.cuda.CUDAGraph()
-        with torch.cuda.graph(graph):
-            batch.chi2()
-        step = graph.replay
-    ms_batch = _timed(step, args.steps, args.warmup, torch)
+        ok = bool(torch.equal(eager, replayed))
+        kt = _kernel_times(gal, batch.chi2, max(args.steps // 4, 20), torch)
+        return batch, Ib, ms, kt, ok, tv, tune_ms
+
+    # 16 walkers (the form of earlier measurements), then the headline's K
+    b16 = None
+    if args.batch != 16:
+        bt, _, ms16, kt16, ok16, tv16, _ = walkers(16)
+        b16 = {"value": round(16 * 1e3 / ms16, 1), "unit": "chi2 evals/s",
+               "ms_per_step": round(ms16, 5), "batch": 16, "fft_variants": tv16,
+               "graph_replay_matches_eager": ok16,
+               "kernels": {k: {kk: (round(vv, 3) if isinstance(vv, float) else vv)
+                               for kk, vv in x.items()} for k, x in kt16.items()}}
+        bt.close()
+    K = args.batch
+    batch, Ib, ms_batch, kern, replay_ok, tuned, batch_tune_ms = walkers(K)
     chi2_batch = batch.out.cpu().numpy()
-    # every replay matches an eager execution
-    eager = batch.chi2().clone()
-    torch.cuda.synchronize()
-    replay_ok = bool(torch.equal(eager, batch.out))
-    kern = _kernel_times(gal, batch.chi2, max(args.steps // 4, 20), torch)
     evals_per_s = K * 1e3 / ms_batch
 
     progress("batched gradients")
@@ -804,6 +824,7 @@ def main():
                                  "p99": round(float(np.percentile(lat, 99)), 4)},
                   "kernels": rnd(kern_plain)},
         "batched_vs_plain": round(evals_per_s / (1e3 / ms_plain), 3),
+        "batch_16": b16,
         "grad": {"plain": {"value": round(1e3 / ms_grad, 1), "unit": "chi2+grad evals/s",
                            "ms_per_eval": round(ms_grad, 5), "kernels": rnd(kern_grad)},
                  "batched": {"value": round(K * 1e3 / ms_bgrad, 1), "unit": "chi2+grad evals/s",
