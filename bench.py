@@ -35,7 +35,7 @@ if ROOT not in sys.path:
 
 HBM_PEAK_GBS = 8000.0
 FP64_PEAK_TFLOPS = 78.6   # 256 CUs x 4 SIMDs x 16 lanes x 2 (FMA) x 2.4 GHz
-TRAFFIC_FILE = os.path.join(ROOT, "profiles", "hbm_traffic__chi2Profile_2048_M1e6_K16.md")
+TRAFFIC_FILE = os.path.join(ROOT, "profiles", "hbm_traffic__chi2Profile_2048_M1e6_K64.md")
 METRIC = "χ² evals/s at 2048², 1M uv (FP64), batched/served vs plain; p50/p99 latency"
 
 
