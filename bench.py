@@ -342,7 +342,7 @@ def cube_bench(gal, torch, np, dev, steps, warmup):
 def _serve_rate(Server, Request, ex, params, rate, n_req, warm, grad_frac, rng):
     """Poisson arrivals at `rate` of warm + n_req requests; statistics of the
     last n_req (the warm-up requests complete before the counters start)."""
-    srv = Server(ex, max_batch=16, max_inflight=4).start()
+    srv = Server(ex, max_batch=ex.max_batch, max_inflight=4).start()
     gaps = rng.exponential(1.0 / rate, n_req + warm)
     t_next = time.perf_counter()
     futs = []
@@ -370,7 +370,8 @@ def _serve_rate(Server, Request, ex, params, rate, n_req, warm, grad_frac, rng):
             "peak_hbm_MB": round(st["peak_hbm_bytes"] / 1e6, 1)}
 
 
-def serve_bench(gal, torch, np, dev, rates, sat_rates, n_req, warm, grad_frac, n_datasets, max_M):
+def serve_bench(gal, torch, np, dev, rates, sat_rates, n_req, warm, grad_frac, n_datasets, max_M,
+                max_batch=64):
     """Poisson stream of chi2Profile (+ gradient) requests against resident
     datasets, served by the continuous-batching loop; latency and throughput
     per arrival rate, then offered rates raised until the served rate falls
@@ -378,7 +379,7 @@ def serve_bench(gal, torch, np, dev, rates, sat_rates, n_req, warm, grad_frac, n
     import workloads as wl
     from paper_1709_06999_amd.serve import GpuExecutor, Request, Server
 
-    ex = GpuExecutor(dev, torch.float64, max_batch=16, max_inflight=4)
+    ex = GpuExecutor(dev, torch.float64, max_batch=max_batch, max_inflight=4)
     f64 = lambda a: torch.as_tensor(np.ascontiguousarray(a, dtype=np.float64), device=dev)
     # each dataset observes a fixed "true" profile at 2048^2 (model from the library) plus noise
     truth = wl.serve_requests(1, seed=1549)[0]
@@ -484,6 +485,8 @@ def main():
     ap.add_argument("--serve-rates", default="100,200,500,1000,2000,5000",
                     help="Poisson arrival rates (requests/s) of the served-load section")
     ap.add_argument("--serve-requests", type=int, default=2000, help="timed requests per rate")
+    ap.add_argument("--serve-max-batch", type=int, default=64,
+                    help="largest micro-batch of the served-load section")
     ap.add_argument("--saturation-rates", default="10000,20000,50000,100000",
                     help="offered rates above the sweep, raised until the served rate falls "
                          "behind the offered one")
@@ -512,7 +515,7 @@ def main():
     sat_rates = [int(r) for r in args.saturation_rates.split(",")] if args.saturation_rates else []
     if args.serve_only:
         served = serve_bench(gal, torch, np, dev, rates, sat_rates, args.serve_requests, 200, 0.5,
-                             8, 2_000_000)
+                             8, 2_000_000, args.serve_max_batch)
         print(json.dumps({"served": served}), flush=True)
         return
     case = wl.profile_2048()
@@ -730,7 +733,7 @@ def main():
     served = None
     if not args.no_serve:
         served = serve_bench(gal, torch, np, dev, rates, sat_rates, args.serve_requests, 200, 0.5,
-                             8, 2_000_000)
+                             8, 2_000_000, args.serve_max_batch)
         for key, mb in (("headline", 64), ("headline_mb16", 16)):
             served[key] = served_headline(gal, torch, np, dev, case, 8000, 500, mb)
             served[key]["served_vs_plain"] = round(served[key]["value"] / (1e3 / ms_plain), 3)
