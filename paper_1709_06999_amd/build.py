@@ -9,10 +9,7 @@ import subprocess
 import sys
 
 HERE = os.path.dirname(os.path.abspath(__file__))
-ROOT = os.path.dirname(HERE)
 SRC = os.path.join(HERE, "csrc", "galario_hip.hip")
-DEPS = [os.path.join(HERE, "csrc", f) for f in ("fft_block.h", "kernels.h")] + [
-    os.path.join(ROOT, "include", "galario_hip.h")]
 LIB = os.path.join(HERE, "libgalario_hip.so")
 
 HIPCC_FLAGS = [
