@@ -413,7 +413,7 @@ __device__ __forceinline__ void adj_rows_body(const Geom &g, const c2<T> *__rest
 template <typename T, typename Cfg>
 __global__ __launch_bounds__(Cfg::NT) void k_adj_rows(Geom g, const c2<T> *__restrict__ H,
                                                       T *__restrict__ grad) {
-    adj_rows_body<T, Cfg>(g, H, grad, blockIdx.x);
+    adj_rows_body<T, Cfg>(g, H, grad, xcd_remap(blockIdx.x, gridDim.x));
 }
 
 // ---- swept profile: columns -------------------------------------------------
@@ -469,72 +469,63 @@ __global__ __launch_bounds__(Cfg::NT) void k_adj_cols_sym(Geom g, int Qe, T *__r
 }
 
 // ---- swept profile: rows and the transposed sweep ----------------------------
-// Quadrant rows 2m, 2m+1 (<= N/2): even extension over q of (-1)^q H[r][q]
-// (halved off q = 0, N/2), packed; g[r][c] = -2 x transform, c in [0, N/2].
-// Each pixel then adds m(r) m(c) g dxy^2 (1 - f) to bin j and ... f to bin j+1
-// (centre pixel: (1 + Rmin/dR) to bin 0 and -Rmin/dR to bin 1) in an LDS
-// histogram, flushed with one atomic per touched bin into copy blk mod
-// GI_COPIES of the bin accumulator: the outer bins are reached by almost
-// every row pair, and same-address atomics serialise, so the copies split
-// those chains; k_sum_bins adds the copies afterwards.
+// Quadrant rows r = 2m, 2m+1 (<= N/2): g_r[c] = -2 sum_q (-1)^q H[r][q]
+// cos(2 pi q c / N) over the even extension in q, c in [0, N/2] -- the
+// transform of an even sequence, taken at half length by even_transform with
+// x[0] = H[r][0], x[q] = (-1)^q H[r][q] / 2 for 0 < q < N/2 (the extension
+// counts those twice) and x[N/2] = (-1)^(N/2) H[r][N/2].  Each pixel then
+// adds m(r) m(c) g dxy^2 (1 - f) to bin j and ... f to bin j+1 (centre pixel:
+// (1 + Rmin/dR) to bin 0 and -Rmin/dR to bin 1) in an LDS histogram, flushed
+// with one atomic per touched bin into copy blk mod GI_COPIES of the bin
+// accumulator: the outer bins are reached by almost every row pair, and
+// same-address atomics serialise, so the copies split those chains;
+// k_sum_bins adds the copies afterwards.  A block takes ppb consecutive
+// groups of B row pairs and flushes its histogram once: a row pair touches
+// thousands of bins, so the flush's global atomics, not the transform, bound
+// a pass with one group per block.  Cfg is the half-length shape (L = N/2),
+// as for rows_even_body.
 constexpr int GI_COPIES = 16;
 template <typename T, typename Cfg>
 __device__ __forceinline__ void adj_rows_sym_body(const Geom &g, const T *__restrict__ H,
                                                   const SweepArgs &sw, double *__restrict__ gI,
-                                                  double *hist, int blk) {
+                                                  double *hist, int blk, int ppb) {
     constexpr int L = Cfg::L, B = Cfg::B, NT = Cfg::NT, E = Cfg::E;
-    constexpr int N = L;
+    constexpr int h = L, N = 2 * L;
     constexpr int R0 = pass_radix(L, 1, Cfg::RMAX);
     constexpr int LR = L / R0;
     __shared__ c2<T> lds[B * Cfg::LS];
+    __shared__ c2<T> xh[B];
+    __shared__ c2<double> part[B * LR];
     __shared__ int jlo_s, jhi_s;
     const int tid = threadIdx.x;
-    const int m0 = blk * B;
+    const int Qr = g.Q;  // kept columns (<= N/2 + 1)
     const T half = T(0.5);
-    const int Qr = g.Q;  // kept columns
-    c2<T> v[E];
-#pragma unroll
-    for (int i = 0; i < E / R0; ++i) {
-        const int gi = tid + i * NT;
-        const int b = gi / LR, j = gi % LR;
-        const int r = 2 * (m0 + b);
-#pragma unroll
-        for (int t = 0; t < R0; ++t) {
-            const int n = j + t * LR;
-            const int qq = n <= N / 2 ? n : N - n;
-            c2<T> x{T(0), T(0)};
-            if (r <= N / 2 && qq < Qr) {
-                const T h1 = H[(size_t)qq * g.CS + r];
-                const T h2 = (r + 1 <= N / 2) ? H[(size_t)qq * g.CS + r + 1] : T(0);
-                x = {h1, h2};
-                if (qq & 1) x = {-x.x, -x.y};
-                if (qq != 0 && qq != N / 2) x = {half * x.x, half * x.y};
-            }
-            v[i * R0 + t] = x;
+    // x[q] of rows r (in .x) and r + 1 (in .y); row N/2 + 1 is not kept
+    auto load = [&](int r, int q) {
+        c2<T> x{T(0), T(0)};
+        if (r <= N / 2 && q < Qr) {
+            const T *src = H + (size_t)q * g.CS + r;
+            x = (r + 1 <= N / 2) ? *reinterpret_cast<const c2<T> *>(src) : c2<T>{src[0], T(0)};
+            if (q & 1) x = {-x.x, -x.y};
         }
-    }
+        return x;
+    };
     for (int k = tid; k < sw.Nr; k += NT) hist[k] = 0.0;
     if (tid == 0) {
         jlo_s = sw.Nr;
         jhi_s = -1;
     }
-    fft_passes<Cfg, 1>(v, lds, twiddles<T>(), tid);  // ends with a barrier
-    constexpr int NH = N / 2 + 1;
     int jlo = sw.Nr, jhi = -1;
-    for (int idx = tid; idx < 2 * B * NH; idx += NT) {
-        const int rb = idx / NH, c = idx % NH;
-        const int r = 2 * m0 + rb;
-        if (r > N / 2) continue;
-        const c2<T> z = lds[Cfg::at(rb >> 1, c)];
-        const double gpix = -2.0 * (double)((rb & 1) ? z.y : z.x);
+    // pixel (r, c) with the value X of the transform
+    auto pixel = [&](int r, int c, double X) {
         const double mult = ((r == 0 || r == N / 2) ? 1.0 : 2.0) * ((c == 0 || c == N / 2) ? 1.0 : 2.0);
-        const double gw = gpix * mult * sw.pix_area;
+        const double gw = -2.0 * X * mult * sw.pix_area;
         if (r == N / 2 && c == N / 2) {
             atomicAdd(&hist[0], gw * (1.0 - sw.t0));
             atomicAdd(&hist[1], gw * sw.t0);
             jlo = 0;
             jhi = jhi > 1 ? jhi : 1;
-            continue;
+            return;
         }
         const double xs = (double)(N / 2 - c) * sw.dxs;  // as sweep_pixel
         const double y = (double)(N / 2 - r) * sw.dxy;
@@ -549,6 +540,35 @@ __device__ __forceinline__ void adj_rows_sym_body(const Geom &g, const T *__rest
             jlo = j < jlo ? j : jlo;
             jhi = j + 1 > jhi ? j + 1 : jhi;
         }
+    };
+    static_assert(B * h == E * NT, "staging: E values per thread");
+    for (int i = 0; i < ppb; ++i) {
+        const int m0 = (blk * ppb + i) * B;
+        if (2 * m0 > N / 2) break;  // the same for the whole block
+#pragma unroll
+        for (int k = 0; k < E; ++k) {
+            const int idx = tid + k * NT;
+            const int b = idx / h, q = idx % h;
+            c2<T> x = load(2 * (m0 + b), q);
+            if (q != 0) x = {half * x.x, half * x.y};
+            lds[Cfg::at(b, q)] = x;
+        }
+        if (tid < B) xh[tid] = load(2 * (m0 + tid), h);
+        __syncthreads();
+        // m in [0, h/2]: columns 2m and 2m + 1 (<= h)
+        even_transform<T, Cfg, B == 1>(
+            lds, xh, part, tid, h / 2 + 1, [&](int b) { return 2 * (m0 + b) <= N / 2; },
+            [&](int b, int m, c2<T> ev, c2<T> od) {
+                const int r = 2 * (m0 + b);
+                const bool two = r + 1 <= N / 2;
+                pixel(r, 2 * m, (double)ev.x);
+                if (two) pixel(r + 1, 2 * m, (double)ev.y);
+                if (2 * m + 1 <= h) {
+                    pixel(r, 2 * m + 1, -(double)od.x);
+                    if (two) pixel(r + 1, 2 * m + 1, -(double)od.y);
+                }
+            });
+        __syncthreads();  // before the next group is staged over this one
     }
     jlo = wave_min(jlo);  // one LDS atomic per wave instead of one per thread
     jhi = wave_max(jhi);
@@ -558,17 +578,18 @@ __device__ __forceinline__ void adj_rows_sym_body(const Geom &g, const T *__rest
     }
     __syncthreads();
     for (int k = jlo_s + tid; k <= jhi_s; k += NT) {
-        const double h = hist[k];
-        if (h != 0.0) atomicAdd(&gI[k], h);
+        const double hv = hist[k];
+        if (hv != 0.0) atomicAdd(&gI[k], hv);
     }
 }
 
 template <typename T, typename Cfg>
 __global__ __launch_bounds__(Cfg::NT) void k_adj_rows_sym(Geom g, const T *__restrict__ H,
-                                                          SweepArgs sw, double *__restrict__ gI) {
+                                                          SweepArgs sw, double *__restrict__ gI,
+                                                          int ppb) {
     extern __shared__ double hist[];
     adj_rows_sym_body<T, Cfg>(g, H, sw, gI + (size_t)(blockIdx.x % GI_COPIES) * sw.Nr, hist,
-                              blockIdx.x);
+                              xcd_remap(blockIdx.x, gridDim.x), ppb);
 }
 
 // profile gradient: the sum of the accumulator copies, in the array type

@@ -586,8 +586,8 @@ template <typename T, typename Cfg>
 __global__ __launch_bounds__(Cfg::NT) void kb_adj_rows(const JobDesc *__restrict__ jobs,
                                                        const int *__restrict__ list, char *ws) {
     const JobDesc &j = jobs[list[blockIdx.y]];
-    adj_rows_body<T, Cfg>(geom_of(j), (const c2<T> *)(ws + j.a_off), (T *)j.grad, blockIdx.x,
-                          j.bad != 0);
+    adj_rows_body<T, Cfg>(geom_of(j), (const c2<T> *)(ws + j.a_off), (T *)j.grad,
+                          xcd_remap(blockIdx.x, gridDim.x), j.bad != 0);
 }
 
 template <typename T, typename Cfg>
@@ -601,12 +601,12 @@ __global__ __launch_bounds__(Cfg::NT) void kb_adj_cols_sym(const JobDesc *__rest
 template <typename T, typename Cfg>
 __global__ __launch_bounds__(Cfg::NT) void kb_adj_rows_sym(const JobDesc *__restrict__ jobs,
                                                            const int *__restrict__ list,
-                                                           char *ws) {
+                                                           char *ws, int ppb) {
     extern __shared__ double hist[];
     const JobDesc &j = jobs[list[blockIdx.y]];
     adj_rows_sym_body<T, Cfg>(geom_of(j), (const T *)(ws + j.a_off), sweep_of(j),
                               (double *)(ws + j.gi_off) + (size_t)(blockIdx.x % GI_COPIES) * j.Nr,
-                              hist, blockIdx.x);
+                              hist, xcd_remap(blockIdx.x, gridDim.x), ppb);
 }
 
 // profile gradients: the sum of the accumulator copies into the caller's array

@@ -770,6 +770,15 @@ static size_t grad_ws_bytes(int N, int64_t M, int Nr) {
 // single job's few hundred row pairs leave the CUs short of waves)
 constexpr int ADJ_E = 4;
 
+// Row-pair groups per block of the transposed sweep, which flushes its
+// histogram once per block: as many as leave about two rounds of blocks
+// on the chip (3 resident per CU), at most ADJ_PPB_MAX.
+constexpr int ADJ_PPB_MAX = 4;
+static int adj_ppb(int groups, int jobs) {
+    const int per = (int)(((int64_t)groups * jobs) / (2 * 3 * 256));
+    return per < 1 ? 1 : (per > ADJ_PPB_MAX ? ADJ_PPB_MAX : per);
+}
+
 template <typename T, int N>
 static int launch_adjoint(bool profile, const Geom &gs, int Qe, const SweepArgs &sw, void *A,
                           T *grad, double *gI, hipStream_t s) {
@@ -779,9 +788,11 @@ static int launch_adjoint(bool profile, const Geom &gs, int Qe, const SweepArgs 
         int rc = launch("k_adj_cols_sym", k_adj_cols_sym<T, C>, dim3((Qe / 2 + B - 1) / B),
                         dim3(C::NT), s, gs, Qe, A);
         if (rc) return rc;
-        const int pairs = N / 4 + 1;
-        return launch_sm("k_adj_rows_sym", k_adj_rows_sym<T, C>, dim3((pairs + B - 1) / B),
-                         dim3(C::NT), (unsigned)(sw.Nr * sizeof(double)), s, gs, A, sw, gI);
+        const int groups = (N / 4 + 1 + B - 1) / B;
+        const int ppb = adj_ppb(groups, 1);
+        using CH = CfgE<T, N / 2, B, ADJ_E>;  // rows: half-length transforms of even rows
+        return launch_sm("k_adj_rows_sym", k_adj_rows_sym<T, CH>, dim3((groups + ppb - 1) / ppb),
+                         dim3(CH::NT), (unsigned)(sw.Nr * sizeof(double)), s, gs, A, sw, gI, ppb);
     }
     int rc = launch("k_adj_cols", k_adj_cols<T, C>, dim3((gs.Q + B - 1) / B), dim3(C::NT), s, gs,
                     A);
@@ -2119,9 +2130,12 @@ static int batch_adj_n(const BatchPlan::FGroup &f, const BatchTables &t, char *w
         rc = launch("kb_adj_cols_sym", kb_adj_cols_sym<T, C>, dim3((f.maxQe / 2 + B - 1) / B, f.count),
                     dim3(C::NT), s, t.jobs, list, ws);
         if (rc) return rc;
-        rc = launch_sm("kb_adj_rows_sym", kb_adj_rows_sym<T, C>,
-                       dim3((N / 4 + 1 + B - 1) / B, f.count), dim3(C::NT),
-                       (unsigned)(f.maxNr * sizeof(double)), s, t.jobs, list, ws);
+        using CH = CfgE<T, N / 2, B, ADJ_E>;  // rows: half-length transforms of even rows
+        const int groups = (N / 4 + 1 + B - 1) / B;
+        const int ppb = adj_ppb(groups, f.count);
+        rc = launch_sm("kb_adj_rows_sym", kb_adj_rows_sym<T, CH>,
+                       dim3((groups + ppb - 1) / ppb, f.count), dim3(CH::NT),
+                       (unsigned)(f.maxNr * sizeof(double)), s, t.jobs, list, ws, ppb);
         if (rc) return rc;
         return launch("kb_grad_out", kb_grad_out<T>, dim3((f.maxNr + 255) / 256, f.count), dim3(256),
                       s, t.jobs, list, ws);

@@ -366,7 +366,11 @@ __device__ __forceinline__ void rows_sym_body(PI I, const SweepArgs &sw, const G
 // at xh[b] (one sequence in .x, the other in .y), staged by the caller and
 // followed by a barrier.  For every pair b with active(b) and m in [0, Mk),
 // out(b, m, ev, od) receives ev = X[2m] and od = -X[2m+1] of both sequences.
-template <typename T, typename Cfg, typename Active, typename Out>
+// The outputs of a pair are taken by one wave, or with SPREAD (B = 1 only)
+// by every thread of the block: contiguous runs of m per thread, the odd
+// outputs' prefix sum then crossing the waves through LDS (one more barrier;
+// active(0) must then hold for the whole block or for none of it).
+template <typename T, typename Cfg, bool SPREAD = false, typename Active, typename Out>
 __device__ __forceinline__ void even_transform(c2<T> *lds, const c2<T> *xh, c2<double> *part,
                                                int tid, int Mk, Active active, Out out) {
     constexpr int L = Cfg::L, B = Cfg::B, NT = Cfg::NT, E = Cfg::E;
@@ -401,6 +405,45 @@ __device__ __forceinline__ void even_transform(c2<T> *lds, const c2<T> *xh, c2<d
     // one wave per pair: X[1] in a fixed order, then the outputs with the
     // prefix sum of the odd ones over contiguous runs of m per lane
     const int wave = tid >> 6, lane = tid & 63;
+    if constexpr (SPREAD) {
+        static_assert(B == 1, "SPREAD: one pair per block");
+        __shared__ c2<double> wtot[NW];  // run sums of each wave
+        if (!active(0)) return;
+        double x1 = 0.0, x2 = 0.0;  // X[1], the same in every wave
+        for (int k = lane; k < LR; k += 64) {
+            x1 += part[k].x;
+            x2 += part[k].y;
+        }
+        x1 = wave_sum(x1);
+        x2 = wave_sum(x2);
+        const int ch = (Mk + NT - 1) / NT;
+        const int mb = min(tid * ch, Mk), me = min(mb + ch, Mk);
+        double t1 = 0.0, t2 = 0.0;
+        for (int m = mb; m < me; ++m) {
+            const c2<T> z = lds[Cfg::at(0, m)], zc = lds[Cfg::at(0, (H - m) & (H - 1))];
+            t1 += (double)z.y - (double)zc.y;
+            t2 += (double)zc.x - (double)z.x;
+        }
+        const double e1 = wave_excl_scan(t1), e2 = wave_excl_scan(t2);
+        if (lane == 63) wtot[wave] = c2<double>{e1 + t1, e2 + t2};
+        __syncthreads();
+        double b1 = 0.0, b2 = 0.0;
+        for (int w = 0; w < wave; ++w) {
+            b1 += wtot[w].x;
+            b2 += wtot[w].y;
+        }
+        double a1 = x1 + (b1 + e1), a2 = x2 + (b2 + e2);
+        for (int m = mb; m < me; ++m) {
+            const c2<T> z = lds[Cfg::at(0, m)], zc = lds[Cfg::at(0, (H - m) & (H - 1))];
+            a1 += (double)z.y - (double)zc.y;
+            a2 += (double)zc.x - (double)z.x;
+            const c2<T> ev{(T)(0.5 * ((double)z.x + (double)zc.x)),
+                           (T)(0.5 * ((double)z.y + (double)zc.y))};
+            const c2<T> od{(T)(-a1), (T)(-a2)};
+            out(0, m, ev, od);
+        }
+        return;
+    }
     const int ch = (Mk + 63) / 64;
     const int mb = lane * ch, me = min(mb + ch, Mk);
     for (int b = wave; b < B; b += NW) {
