@@ -165,6 +165,13 @@ __global__ __launch_bounds__(Cfg::NT) void kb_cols_sym(const JobDesc *__restrict
     cols_sym_body<T, Cfg>(geom_of(j), j.Qe, (T *)(ws + j.spec_off), blockIdx.x);
 }
 
+template <typename T, typename Cfg>
+__global__ __launch_bounds__(Cfg::NT) void kb_cols_even(const JobDesc *__restrict__ jobs,
+                                                        const int *__restrict__ list, char *ws) {
+    const JobDesc &j = jobs[list[blockIdx.y]];
+    cols_even_body<T, Cfg>(geom_of(j), j.Qe, (T *)(ws + j.spec_off), blockIdx.x);
+}
+
 // ---- sampling stage ------------------------------------------------------
 // One job at one point: the bilinear value of its spectrum (cos(inc) for
 // images) times the phase of its offset, plus the stencil for a scatter.

@@ -252,13 +252,22 @@ static int run_rows_sym(const FftJob<T> &j) {
                       j.s, j.src, j.sw, j.g, j.Qe, j.buf);
     }
 }
+// columns of a swept profile: variant 0 takes the half-length transform of
+// the even columns (cols_even_body, E = 8), variants 1 and 2 the full-length
+// one (cols_sym_body, E = 8 and 4)
 template <typename T, int N, int VAR>
 static int run_cols_sym(const FftJob<T> &j) {
     constexpr int B = cols_B(N);
-    using C = CfgE<T, N, B, var_E(VAR)>;
     const int pairs = j.Qe / 2;
-    return launch("k_cols_sym", k_cols_sym<T, C>, dim3((pairs + B - 1) / B), dim3(C::NT), j.s, j.g,
-                  j.Qe, j.buf);
+    if constexpr (VAR == 0) {
+        using C = CfgE<T, N / 2, B, 8>;
+        return launch("k_cols_even", k_cols_even<T, C>, dim3((pairs + B - 1) / B), dim3(C::NT),
+                      j.s, j.g, j.Qe, j.buf);
+    } else {
+        using C = CfgE<T, N, B, var_E(VAR)>;
+        return launch("k_cols_sym", k_cols_sym<T, C>, dim3((pairs + B - 1) / B), dim3(C::NT),
+                      j.s, j.g, j.Qe, j.buf);
+    }
 }
 
 // 16384^2: one schedule per pass.  Rows of images at half length (E = 8);
@@ -423,9 +432,15 @@ static int runb_rows_sym(const FftJobB &j) {
 template <typename T, int N, int VAR>
 static int runb_cols_sym(const FftJobB &j) {
     constexpr int B = cols_B(N);
-    using C = CfgE<T, N, B, var_E(VAR)>;
-    return launch("kb_cols_sym", kb_cols_sym<T, C>, dim3((j.maxQe / 2 + B - 1) / B, j.count),
-                  dim3(C::NT), j.s, j.jobs, j.list, j.ws);
+    if constexpr (VAR == 0) {
+        using C = CfgE<T, N / 2, B, 8>;
+        return launch("kb_cols_even", kb_cols_even<T, C>, dim3((j.maxQe / 2 + B - 1) / B, j.count),
+                      dim3(C::NT), j.s, j.jobs, j.list, j.ws);
+    } else {
+        using C = CfgE<T, N, B, var_E(VAR)>;
+        return launch("kb_cols_sym", kb_cols_sym<T, C>, dim3((j.maxQe / 2 + B - 1) / B, j.count),
+                      dim3(C::NT), j.s, j.jobs, j.list, j.ws);
+    }
 }
 
 template <typename T, int N>
