@@ -229,6 +229,25 @@ def _kernel_times(gal, fn, steps, torch):
     return {k: {"avg_us": 1e3 * ms / n, "launches": n} for k, (ms, n) in times.items()}
 
 
+def stage_probe(gal, torch, dev, blocks=977, reps=50):
+    """What a persistent kernel would pay per stage handoff: the same kernel
+    (every block writes 8 KB, then one agent-scope atomic per block) without
+    an atomic, with a relaxed, a release and an acquire-release one; average
+    duration per launch (HIP events).  The release is the handoff a block
+    needs to publish its stage output to the others."""
+    ws = torch.zeros(gal.probe_stage_bytes(blocks), dtype=torch.uint8, device=dev)
+    avg = {}
+    for mode, name in enumerate(("none", "relaxed", "release", "acq_rel")):
+        for _ in range(5):
+            gal.probe_stage(mode, blocks, ws)
+        t = _kernel_times(gal, lambda: gal.probe_stage(mode, blocks, ws), reps, torch)
+        avg[name] = round(t[f"k_stage_probe<{mode}>"]["avg_us"], 3)
+    return {"blocks": blocks, "threads_per_block": 256, "bytes_per_block": 8192, "avg_us": avg,
+            "release_minus_relaxed_us": round(avg["release"] - avg["relaxed"], 3),
+            "form": "k_stage_probe: every block writes its 8 KB slice, then one agent-scope "
+                    "atomic add per block on a counter nothing waits on"}
+
+
 def image_bench(gal, torch, np, dev, case, dtype, steps, warmup, grad=False, raw=False):
     """Plain chi2Image calls (one evaluation per call) on a case: evals/s,
     p50/p99 latency, per-kernel times and the dominant kernel's roofline; on
@@ -480,6 +499,9 @@ def main():
                     help="fixed FFT variants for the batched sections (default: as "
                          "--fft-variants, else autotuned on the batch)")
     ap.add_argument("--no-serve", action="store_true", help="skip the served-load section")
+    ap.add_argument("--stage-probe", action="store_true",
+                    help="run only the stage-handoff probe (what a persistent kernel pays per "
+                         "stage) and print its JSON")
     ap.add_argument("--serve-only", action="store_true",
                     help="run only the served-load section and print its JSON (profiling aid)")
     ap.add_argument("--serve-rates", default="100,200,500,1000,2000,5000",
@@ -513,6 +535,9 @@ def main():
     gal.init(0)
     rates = [int(r) for r in args.serve_rates.split(",")]
     sat_rates = [int(r) for r in args.saturation_rates.split(",")] if args.saturation_rates else []
+    if args.stage_probe:
+        print(json.dumps({"stage_probe": stage_probe(gal, torch, dev)}), flush=True)
+        return
     if args.serve_only:
         served = serve_bench(gal, torch, np, dev, rates, sat_rates, args.serve_requests, 200, 0.5,
                              8, 2_000_000, args.serve_max_batch)
@@ -851,6 +876,7 @@ def main():
                   "form": f"{S} copies of the 2048^2 profile (one scene) on the M=1e6 dataset; "
                           "persistent plan, one gal_batch_chi2 per evaluation"},
         "evals_vs_unpruned_bytes": unpruned,
+        "stage_probe": stage_probe(gal, torch, dev),
         "served": served,
         "images": images,
         "kernels": rnd(kern),

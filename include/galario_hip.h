@@ -444,6 +444,18 @@ int gal_timing_enable(int on);
 int gal_timing_reset(void);
 int gal_timing_read(int cap, const char **names, double *total_ms, int64_t *launches);
 
+/* Measurement aid: the cost of the device-scope handoff a persistent kernel
+ * needs between two stages, which is why the batches run one kernel per stage
+ * instead.  Launches k_stage_probe over `blocks` blocks of 256 threads on
+ * `stream`: every block writes its 8 KB slice of a stage output, then one
+ * thread adds 1 to a counter at agent scope with no atomic (mode 0), a relaxed
+ * (1), a release (2) or an acquire-release (3) atomic.  Nothing waits on the
+ * counter.  ws: device memory of at least gal_probe_stage_bytes(blocks) bytes,
+ * the counter in its first 256 bytes.  GAL_ERR_SIZE for a mode outside [0, 3]
+ * or blocks outside [1, 65536], GAL_ERR_WORKSPACE for a smaller ws. */
+size_t gal_probe_stage_bytes(int blocks);
+int gal_probe_stage(int mode, int blocks, void *ws, size_t ws_bytes, void *stream);
+
 #ifdef __cplusplus
 }
 #endif

@@ -891,6 +891,19 @@ class timing:
         return {names[i].decode(): (ms[i], int(cnt[i])) for i in range(n)}
 
 
+def probe_stage_bytes(blocks: int) -> int:
+    """Workspace bytes of the stage-handoff probe (gal_probe_stage_bytes)."""
+    return int(_lib().gal_probe_stage_bytes(blocks))
+
+
+def probe_stage(mode: int, blocks: int, ws: torch.Tensor):
+    """One launch of the stage-handoff probe (gal_probe_stage) on the current
+    stream: every block writes 8 KB, then one agent-scope atomic per block --
+    none (0), relaxed (1), release (2) or acquire-release (3)."""
+    check(_lib().gal_probe_stage(mode, blocks, _ptr(ws), ws.numel() * ws.element_size(),
+                                 _stream(ws.device)), "gal_probe_stage")
+
+
 # ----------------------------------------------------------------------------
 # autograd: chi^2 of a profile / image on a dataset, differentiable in the model
 class _Chi2Profile(torch.autograd.Function):

@@ -87,6 +87,8 @@ _SIG = {
     "gal_timing_reset": (I, []),
     "gal_timing_read": (I, [I, ctypes.POINTER(ctypes.c_char_p), ctypes.POINTER(D),
                             ctypes.POINTER(I64)]),
+    "gal_probe_stage_bytes": (SZ, [I]),
+    "gal_probe_stage": (I, [I, I, P, SZ, P]),
 }
 _PRECISION_SUFFIXED = {
     "gal_sweep", "gal_sampleImage", "gal_sampleProfile", "gal_chi2Image", "gal_chi2Profile",

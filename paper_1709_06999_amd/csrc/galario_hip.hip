@@ -2388,6 +2388,54 @@ int gal_timing_reset(void) {
     return GAL_OK;
 }
 
+// ---- stage-handoff probe ----------------------------------------------------
+// Every block writes its slice of a stage output, then publishes it with one
+// agent-scope atomic on a counter (MODE 0: none, 1: relaxed, 2: release,
+// 3: acquire-release).  Nothing waits on the counter, so every block exits.
+constexpr int PROBE_NT = 256, PROBE_PER_THREAD = 4;
+template <int MODE>
+__global__ __launch_bounds__(PROBE_NT) void k_stage_probe(double *__restrict__ out,
+                                                          unsigned int *ctr) {
+    double *o = out + (size_t)blockIdx.x * (PROBE_NT * PROBE_PER_THREAD);
+#pragma unroll
+    for (int k = 0; k < PROBE_PER_THREAD; ++k)
+        o[threadIdx.x + PROBE_NT * k] = (double)(blockIdx.x + k);
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        if constexpr (MODE == 1)
+            __hip_atomic_fetch_add(ctr, 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+        else if constexpr (MODE == 2)
+            __hip_atomic_fetch_add(ctr, 1u, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_AGENT);
+        else if constexpr (MODE == 3)
+            __hip_atomic_fetch_add(ctr, 1u, __ATOMIC_ACQ_REL, __HIP_MEMORY_SCOPE_AGENT);
+    }
+}
+
+size_t gal_probe_stage_bytes(int blocks) {
+    if (blocks < 1 || blocks > 65536) return 0;
+    return 256 + (size_t)blocks * PROBE_NT * PROBE_PER_THREAD * sizeof(double);
+}
+
+int gal_probe_stage(int mode, int blocks, void *ws, size_t ws_bytes_, void *stream) {
+    if (!ws) return fail(GAL_ERR_NULL, "workspace is NULL");
+    if (mode < 0 || mode > 3) return fail(GAL_ERR_SIZE, "probe mode %d", mode);
+    const size_t need = gal_probe_stage_bytes(blocks);
+    if (need == 0) return fail(GAL_ERR_SIZE, "probe blocks %d", blocks);
+    if (ws_bytes_ < need) return fail(GAL_ERR_WORKSPACE, "workspace of %zu bytes, need %zu", ws_bytes_, need);
+    int rc = ensure_init();
+    if (rc) return rc;
+    hipStream_t s = (hipStream_t)stream;
+    unsigned int *ctr = (unsigned int *)ws;
+    double *out = (double *)((char *)ws + 256);
+    const dim3 grid(blocks), blk(PROBE_NT);
+    switch (mode) {
+        case 0: return launch("k_stage_probe<0>", k_stage_probe<0>, grid, blk, s, out, ctr);
+        case 1: return launch("k_stage_probe<1>", k_stage_probe<1>, grid, blk, s, out, ctr);
+        case 2: return launch("k_stage_probe<2>", k_stage_probe<2>, grid, blk, s, out, ctr);
+        default: return launch("k_stage_probe<3>", k_stage_probe<3>, grid, blk, s, out, ctr);
+    }
+}
+
 int gal_timing_read(int cap, const char **names, double *total_ms, int64_t *launches) {
     std::lock_guard<std::mutex> lk(g_tm_mu);
     std::vector<const char *> nm;
