@@ -109,6 +109,11 @@ __device__ __forceinline__ void block_scatter(T *__restrict__ A, int CS, const P
         ilo = min(ilo, box[4 * k + 2]);
         ihi = max(ihi, box[4 * k + 3]);
     }
+    // the same in every lane of the block: scalar from here on
+    qlo = __builtin_amdgcn_readfirstlane(qlo);
+    qhi = __builtin_amdgcn_readfirstlane(qhi);
+    ilo = __builtin_amdgcn_readfirstlane(ilo);
+    ihi = __builtin_amdgcn_readfirstlane(ihi);
     if (qlo > qhi) return;  // no point of the block adds anything (uniform)
     const int TQ = qhi - qlo + 2, TI = ihi - ilo + 2;
     const int SQ = SCAT_TILE / (TI * NV);  // q-rows per window
