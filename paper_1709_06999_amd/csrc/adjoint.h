@@ -277,7 +277,7 @@ __global__ __launch_bounds__(SAMPLE_NT) void k_sample_scatter(
         phase_of(a, uu, vv, sn, cs);
         if constexpr (REAL) {
             // an off-grid stencil points at valid nodes; its value is discarded
-            const StencilE<T> st = locate_e<T>(S, g, a, uu, vv);
+            const StencilE<T> st = locate_e<T>(g, a, uu, vv);
             double x0, x1, y0, y1;
             nodes_e<T>(S, st, g.CS, x0, x1, y0, y1);
             const double b = bilerp(x0, y0, x1, y1, st.s, st.t);

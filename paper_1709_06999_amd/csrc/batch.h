@@ -190,7 +190,7 @@ __device__ __forceinline__ JobPoint<T, REAL> job_point(const JobDesc &J, const S
     phase_of(a, u, v, r.sn, r.cs);
     // an off-grid stencil points at valid nodes; its value is discarded
     if constexpr (REAL) {
-        r.st = locate_e<T>((const T *)(ws + J.spec_off), g, a, u, v);
+        r.st = locate_e<T>(g, a, u, v);
         const StencilE<T> &st = r.st;
         double x0, x1, y0, y1;
         nodes_e<T>((const T *)(ws + J.spec_off), st, g.CS, x0, x1, y0, y1);
@@ -393,7 +393,7 @@ __global__ __launch_bounds__(SAMPLE_NT) void kb_sample_chi2(const JobDesc *__res
                 // an off-grid stencil points at valid nodes; its value is discarded
                 if constexpr (REAL) {
                     const T *S = (const T *)(ws + J.spec_off);
-                    const StencilE<T> st = locate_e<T>(S, g, a, uu[p], vv[p]);
+                    const StencilE<T> st = locate_e<T>(g, a, uu[p], vv[p]);
                     ok = st.ok;
                     double x0, x1, y0, y1;
                     nodes_e<T>(S, st, g.CS, x0, x1, y0, y1);

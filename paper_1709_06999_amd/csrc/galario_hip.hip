@@ -185,10 +185,6 @@ static int launch(const char *name, void (*kernel)(KArgs...), dim3 grid, dim3 bl
 // autotuner (gal_autotune_*) times them per image size and precision; the
 // defaults below are used until it has run.
 enum FftKind { K_ROWS_IMG = 0, K_COLS = 1, K_ROWS_SYM = 2, K_COLS_SYM = 3, NKIND = 4 };
-static const char *kind_name(int k) {
-    static const char *n[NKIND] = {"rows_image", "cols", "rows_sym", "cols_sym"};
-    return n[k];
-}
 constexpr int NVAR = 3;
 constexpr int var_E(int var) { return var == 0 ? 16 : (var == 1 ? 8 : 4); }
 constexpr int min_c(int a, int b) { return a < b ? a : b; }

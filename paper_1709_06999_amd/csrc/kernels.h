@@ -940,8 +940,8 @@ __device__ __forceinline__ void nodes_e(const T *__restrict__ S, const StencilE<
 }
 
 template <typename T>
-__device__ __forceinline__ StencilE<T> locate_e(const T *__restrict__ S, const Geom &g,
-                                                const SampleArgs &a, double u, double v) {
+__device__ __forceinline__ StencilE<T> locate_e(const Geom &g, const SampleArgs &a, double u,
+                                                double v) {
     StencilE<T> st;
     const double fu = u * a.cpa_du - v * a.spa_du;
     const double fv = u * a.spa_du + v * a.cpa_du;
@@ -998,7 +998,7 @@ __global__ __launch_bounds__(SAMPLE_NT) void k_sample_sym(
     double x0[PPT], x1[PPT], y0[PPT], y1[PPT];
 #pragma unroll
     for (int p = 0; p < PPT; ++p) {
-        st[p] = locate_e<T>(S, g, a, uu[p], vv[p]);
+        st[p] = locate_e<T>(g, a, uu[p], vv[p]);
         nodes_e<T>(S, st[p], g.CS, x0[p], x1[p], y0[p], y1[p]);
     }
     double acc = 0.0;
