@@ -44,12 +44,15 @@ __device__ __forceinline__ gptr<T> as_global(const void *p) {
 // is exact); (cos, -sin)(pi n / 128) is entry n mod 256 of the length-256
 // twiddle row (exp(-2 pi i m / 256), stored at [256, 512)); sin and cos of
 // z = pi r by their Taylor series through z^5 and z^6 (|z| <= pi/256:
-// truncation below 1e-17); then the angle-addition formulas.  About 18 FP64
-// operations and one cached 16-byte load; abs. error a few 1e-16.
+// truncation below 1e-17); then the angle-addition formulas.  About 15 FP64
+// operations and one cached 16-byte load; abs. error a few 1e-16.  The table
+// index is exact for |y| < 2^51, i.e. phases |u dRA + v dDec| below 2^43
+// turns; a NaN y reads some entry in range and gives a NaN phase.
 __device__ __forceinline__ void sincospi_tab(double y, double &sn, double &cs) {
     const double n = rint(y);
-    const double m = fma(-256.0, floor(n * (1.0 / 256.0)), n);  // n mod 256
-    const uint32_t idx = (uint32_t)(int)fmin(fmax(m, 0.0), 255.0);  // NaN -> 0
+    // n mod 256: n + 1.5 2^52 holds n in the low bits of its significand
+    // (two's complement), whatever the sign of n
+    const uint32_t idx = (uint32_t)__double_as_longlong(n + 6755399441055744.0) & 255u;
     const c2<double> t = *(const c2<double> *)((const char *)(g_tw_d + 256) + idx * 16u);
     const double z = (y - n) * (3.141592653589793 / 128.0);
     const double z2 = z * z;
