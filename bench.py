@@ -171,16 +171,21 @@ def kernel_roofline(kern, alg_bytes, alg_flops):
 
 
 def source_digest():
-    """SHA-256 over the HIP sources (file names and contents, sorted): ties
-    stored counter readings to the kernels they were taken from."""
+    """SHA-256 over the HIP sources (file names and code, sorted), comments and
+    blank lines left out: ties stored counter readings to the kernels they
+    were taken from, whatever their comments say."""
     import hashlib
+    import re
 
     h = hashlib.sha256()
     d = os.path.join(ROOT, "paper_1709_06999_amd", "csrc")
     for name in sorted(os.listdir(d)):
         h.update(name.encode())
-        with open(os.path.join(d, name), "rb") as f:
-            h.update(f.read())
+        with open(os.path.join(d, name), encoding="utf-8") as f:
+            code = re.sub(r"/\*.*?\*/", "", f.read(), flags=re.S)
+        code = "\n".join(ln.rstrip() for ln in (re.sub(r"//.*", "", x) for x in code.splitlines())
+                          if ln.strip())
+        h.update(code.encode())
     return h.hexdigest()
 
 

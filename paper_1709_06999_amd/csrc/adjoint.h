@@ -481,10 +481,11 @@ __global__ __launch_bounds__(Cfg::NT) void k_adj_cols_sym(Geom g, int Qe, T *__r
 // counts those twice) and x[N/2] = (-1)^(N/2) H[r][N/2].  Each pixel then
 // adds m(r) m(c) g dxy^2 (1 - f) to bin j and ... f to bin j+1 (centre pixel:
 // (1 + Rmin/dR) to bin 0 and -Rmin/dR to bin 1) in an LDS histogram, flushed
-// with one atomic per touched bin into copy blk mod GI_COPIES of the bin
-// accumulator: the outer bins are reached by almost every row pair, and
-// same-address atomics serialise, so the copies split those chains;
-// k_sum_bins adds the copies afterwards.  A block takes ppb consecutive
+// with one atomic per touched bin into gI, one of GI_COPIES copies of the bin
+// accumulator (the kernels pick it by block index): the outer bins are
+// reached by almost every row pair, and same-address atomics serialise, so
+// the copies split those chains; k_sum_bins adds the copies afterwards.
+// A block takes ppb consecutive
 // groups of B row pairs and flushes its histogram once: a row pair touches
 // thousands of bins, so the flush's global atomics, not the transform, bound
 // a pass with one group per block.  Cfg is the half-length shape (L = N/2),
