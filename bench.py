@@ -69,7 +69,7 @@ def algorithmic_bytes(N, Nr, M, Q, P, kind="profile", p=8):
         inter = (N // 2 + 1) * Qe * p
         spec = (P + 1) * Qe * p
         return {"k_rows_sym": Nr * p + inter, "k_rows_even": Nr * p + inter, "k_cols_sym": inter + spec,
-                "k_sample_sym_chi2": 5 * p * M + spec, "k_reduce": red}
+                "k_cols_even": inter + spec, "k_sample_sym_chi2": 5 * p * M + spec, "k_reduce": red}
     inter = N * Q * 2 * p
     spec = Q * (2 * P + 1) * 2 * p
     return {"k_rows_image": N * N * p + inter, "k_cols": inter + spec,
@@ -100,12 +100,14 @@ def fft_flops(N, Q, K=1):
     of (even) rows, a complex FFT of length N/2 at 5 L log2 L plus 12 flops per
     point of pre- and post-processing -- the half-length transform, whichever
     variant runs (the full-length one does redundant work).  Column pass:
-    columns [0, Qe) two at a time, complex FFT of length N."""
+    columns [0, Qe) two at a time, complex FFT of length N, whichever variant
+    runs (the half-length one, kb_cols_even, does less)."""
     Qe = Q + (Q & 1)
     h = N // 2
     rows = (N // 4 + 1) * (5.0 * h * math.log2(h) + 12.0 * h) + (h + 1) ** 2 * SWEEP_FLOPS_PER_PIXEL
     cols = (Qe // 2) * 5.0 * N * math.log2(N)
-    return {"kb_rows_sym": K * rows, "kb_rows_even": K * rows, "kb_cols_sym": K * cols}
+    return {"kb_rows_sym": K * rows, "kb_rows_even": K * rows, "kb_cols_sym": K * cols,
+            "kb_cols_even": K * cols}
 
 
 def sample_flops(M, K=1):
@@ -704,7 +706,7 @@ def main():
     Qe = Q + (Q & 1)
     spec = (P + 1) * Qe * 8
     ab_batch = {"kb_rows_sym": K * ab["k_rows_sym"], "kb_rows_even": K * ab["k_rows_sym"],
-                "kb_cols_sym": K * ab["k_cols_sym"],
+                "kb_cols_sym": K * ab["k_cols_sym"], "kb_cols_even": K * ab["k_cols_sym"],
                 "kb_sample_sym_chi2": 5 * 8 * M + K * spec, "kb_reduce": K * ab["k_reduce"]}
     for k in kern:
         if k in ab_batch:
